@@ -1,0 +1,332 @@
+"""Pins of the CPU FP64 oracle against facts the paper and the mathematics fix.
+
+The paper prints no solution values, so the oracle is pinned by closed forms
+(linear amplification matrix of the scheme; CFL bound), invariants (lake at
+rest, mass and momentum conservation, mirror symmetry, reflective wall as a
+symmetry plane, uniform directions), physics (linear gravity-wave speed
+sqrt(g H)) and the observed order of accuracy.  Each pin is chosen so that a
+plausible slip in the oracle (a flipped sign, a shifted face index, a dropped
+flux term, x and y swapped) fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import PERIODIC, REFLECT, SCHEME_PAPER, SCHEME_TRANSVERSE
+from paper_1107_2157_amd import ics
+
+G = 9.8
+SCHEMES = [SCHEME_PAPER, SCHEME_TRANSVERSE]
+
+
+def interior(a):
+    return a[1:-1, 1:-1]
+
+
+# --------------------------------------------------------------------------
+# Closed form: linearised scheme (Lax-Wendroff steps, SWE Jacobians)
+# --------------------------------------------------------------------------
+def jacobians(h0, u0, v0, g=G):
+    """Flux Jacobians dF/dU, dG/dU of the SWE at (h0, h0 u0, h0 v0)."""
+    c2 = g * h0
+    a = np.array([[0, 1, 0], [c2 - u0 * u0, 2 * u0, 0], [-u0 * v0, v0, u0]], dtype=float)
+    b = np.array([[0, 0, 1], [-u0 * v0, v0, u0], [c2 - v0 * v0, 0, 2 * v0]], dtype=float)
+    return a, b
+
+
+def amplification(alpha, beta, mux, muy, a, b, transverse):
+    """Symbol of one step for a Fourier mode exp(i(alpha i + beta j)):
+    I - i mux A sin(alpha) - mux^2 A^2 (1 - cos alpha) - (same in y)
+    [- mux muy (AB + BA)/2 sin(alpha) sin(beta) with the transverse term]."""
+    m = (np.eye(3) - 1j * mux * a * math.sin(alpha) - mux ** 2 * (a @ a) * (1 - math.cos(alpha))
+         - 1j * muy * b * math.sin(beta) - muy ** 2 * (b @ b) * (1 - math.cos(beta)))
+    if transverse:
+        m = m - 0.5 * mux * muy * (a @ b + b @ a) * math.sin(alpha) * math.sin(beta)
+    return m
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("u0,v0", [(0.0, 0.0), (0.4, -0.25)])
+@pytest.mark.parametrize("kx,ky", [(1, 0), (0, 2), (3, 2), (5, 7)])
+def test_linear_modes_match_amplification_matrix(scheme, u0, v0, kx, ky):
+    nx, ny, nsteps = 16, 12, 5
+    h0, dx, dy = 1.0, 1.0, 0.8
+    dt = 0.5 * min(dx, dy) / (max(abs(u0), abs(v0)) + math.sqrt(G * h0))
+    eps = 1e-7
+    rng = np.random.default_rng(kx * 10 + ky)
+    uhat = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+    alpha, beta = 2 * math.pi * kx / nx, 2 * math.pi * ky / ny
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    phase = np.exp(1j * (alpha * ii + beta * jj))
+    base = np.array([h0, h0 * u0, h0 * v0])
+    state0 = [base[c] + eps * np.real(uhat[c] * phase) for c in range(3)]
+    H, U, V, _ = oracle.run(*state0, nsteps, g=G, dx=dx, dy=dy, dt_fixed=dt, scheme=scheme,
+                            bcx=PERIODIC, bcy=PERIODIC)
+    a, b = jacobians(h0, u0, v0)
+    m = np.linalg.matrix_power(amplification(alpha, beta, dt / dx, dt / dy, a, b,
+                                             scheme == SCHEME_TRANSVERSE), nsteps)
+    uhat_n = m @ uhat
+    for c, arr in enumerate((H, U, V)):
+        got = (interior(arr) - base[c]) / eps
+        want = np.real(uhat_n[c] * phase)
+        assert np.max(np.abs(got - want)) <= 1e-5 * np.max(np.abs(uhat)), (c, scheme)
+
+
+@pytest.mark.parametrize("u0", [0.0, 0.3, -0.7])
+def test_one_d_modes_are_textbook_lax_wendroff(u0):
+    """For y-independent modes each characteristic field evolves by the
+    textbook Lax-Wendroff factor 1 - i nu sin(t) - nu^2 (1 - cos t), nu the
+    Courant number of that characteristic (speeds u - c, u, u + c)."""
+    h0, dx = 1.0, 1.0
+    c = math.sqrt(G * h0)
+    dt = 0.5 * dx / (abs(u0) + c)
+    a, b = jacobians(h0, u0, 0.0)
+    for theta in np.linspace(0.1, math.pi, 7):
+        m = amplification(theta, 0.0, dt / dx, dt / dx, a, b, False)
+        got = list(np.linalg.eigvals(m))
+        for nu in ((u0 - c) * dt / dx, u0 * dt / dx, (u0 + c) * dt / dx):
+            want = 1 - 1j * nu * math.sin(theta) - nu * nu * (1 - math.cos(theta))
+            k = int(np.argmin([abs(z - want) for z in got]))
+            assert abs(got.pop(k) - want) < 1e-12
+        # and the oracle follows that symbol for the same 1-D mode
+    nx, ny = 32, 3
+    alpha = 2 * math.pi * 3 / nx
+    ii = np.arange(nx)[None, :].repeat(ny, 0)
+    uhat = np.array([1.0 + 0.5j, -0.3 + 0.2j, 0.7 - 0.1j])
+    eps = 1e-7
+    base = np.array([h0, h0 * u0, 0.0])
+    state0 = [base[k] + eps * np.real(uhat[k] * np.exp(1j * alpha * ii)) for k in range(3)]
+    H, U, V, _ = oracle.run(*state0, 4, g=G, dt_fixed=dt, bcx=PERIODIC, bcy=PERIODIC)
+    want = np.linalg.matrix_power(amplification(alpha, 0.0, dt, dt, a, b, False), 4) @ uhat
+    for k, arr in enumerate((H, U, V)):
+        np.testing.assert_allclose((interior(arr) - base[k]) / eps,
+                                   np.real(want[k] * np.exp(1j * alpha * ii)), atol=1e-5)
+
+
+def test_literal_scheme_growth_rate_and_transverse_stability():
+    """The literal scheme (no transverse term) is weakly unstable for oblique
+    modes: growth 1.0206 per step at rest and CFL 0.5; the transverse variant
+    has spectral radius 1 there."""
+    a, b = jacobians(1.0, 0.0, 0.0)
+    dt = 0.5 / math.sqrt(G)
+    grid = np.linspace(0, math.pi, 61)
+    rho = lambda tr: max(max(abs(np.linalg.eigvals(amplification(x, y, dt, dt, a, b, tr))))
+                         for x in grid for y in grid)
+    assert abs(rho(False) - 1.0206) < 5e-4
+    assert rho(True) <= 1.0 + 1e-12
+
+
+# --------------------------------------------------------------------------
+# CFL bound
+# --------------------------------------------------------------------------
+def test_cfl_dt_closed_form():
+    """Constant moving state: max speed = max(|u|, |v|) + sqrt(g h) and
+    dt = cfl * min(dx, dy) / that speed (the CFL remark, per step)."""
+    h, u, v = 1.7, -0.9, 0.4
+    st = [np.full((5, 7), x) for x in (h, h * u, h * v)]
+    H, U, V = (oracle.with_halo(a) for a in st)
+    s = oracle.max_speed(H, U, V, G)
+    assert s == pytest.approx(0.9 + math.sqrt(G * h), rel=1e-15)
+    _, _, _, t, dts = oracle.run(*st, 3, cfl=0.5, dx=1.0, dy=0.5, bcx=PERIODIC, bcy=PERIODIC,
+                                 return_dts=True)
+    np.testing.assert_allclose(dts, 0.5 * 0.5 / (0.9 + math.sqrt(G * h)), rtol=1e-14)
+    assert t == pytest.approx(dts.sum(), rel=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Invariants
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("bc", [REFLECT, PERIODIC])
+def test_lake_at_rest_is_exact(scheme, bc):
+    st = [np.full((9, 13), 1.37), np.zeros((9, 13)), np.zeros((9, 13))]
+    H, U, V, _ = oracle.run(*st, 50, g=G, scheme=scheme, bcx=bc, bcy=bc)
+    assert np.all(interior(H) == 1.37) and np.all(interior(U) == 0) and np.all(interior(V) == 0)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_mass_conserved_dam_break_reflective(scheme):
+    h, hu, hv = (a.numpy() for a in ics.dam_break_state(64))
+    m0 = math.fsum(h.ravel())
+    H, U, V, _ = oracle.run(h, hu, hv, 100, scheme=scheme)
+    assert abs(math.fsum(interior(H).ravel()) - m0) / m0 <= 1e-12
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_mass_and_momentum_conserved_periodic(scheme):
+    h, hu, hv = (a.numpy() for a in ics.random_state(40, 30, seed=11, amp_h=0.2, amp_m=0.05))
+    sums0 = [math.fsum(a.ravel()) for a in (h, hu, hv)]
+    H, U, V, _ = oracle.run(h, hu, hv, 100, scheme=scheme, bcx=PERIODIC, bcy=PERIODIC)
+    sums1 = [math.fsum(interior(a).ravel()) for a in (H, U, V)]
+    assert abs(sums1[0] - sums0[0]) / sums0[0] <= 1e-12
+    # momentum: no wall forces with periodic boundaries; scale by total mass * sqrt(g)
+    for k in (1, 2):
+        assert abs(sums1[k] - sums0[k]) / (sums0[0] * math.sqrt(G)) <= 1e-12
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_dam_break_mirror_symmetry_bitwise(scheme):
+    h, hu, hv = (a.numpy() for a in ics.dam_break_state(128))
+    H, U, V, _ = oracle.run(h, hu, hv, 100, scheme=scheme)
+    H, U, V = interior(H), interior(U), interior(V)
+    assert np.array_equal(H, H[:, ::-1]) and np.array_equal(U, -U[:, ::-1]) and np.array_equal(V, V[:, ::-1])
+    assert np.array_equal(H, H[::-1, :]) and np.array_equal(U, U[::-1, :]) and np.array_equal(V, -V[::-1, :])
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_transpose_equivariance(scheme):
+    """Swapping x and y (and hu with hv) commutes with the step up to the
+    rounding of the x-before-y subtraction order."""
+    h, hu, hv = (a.numpy() for a in ics.random_state(24, 17, seed=5))
+    A = oracle.run(h, hu, hv, 30, scheme=scheme)
+    B = oracle.run(h.T.copy(), hv.T.copy(), hu.T.copy(), 30, scheme=scheme)
+    np.testing.assert_allclose(interior(B[0]).T, interior(A[0]), rtol=0, atol=1e-13)
+    np.testing.assert_allclose(interior(B[2]).T, interior(A[1]), rtol=0, atol=1e-13)
+    np.testing.assert_allclose(interior(B[1]).T, interior(A[2]), rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_reflective_wall_is_a_symmetry_plane(scheme):
+    """A reflective box equals one quadrant of the doubled, mirror-extended
+    periodic domain (normal momentum negated in the mirror images).  Pins the
+    wall ghost values, their signs and (transverse scheme) the corners."""
+    ny, nx = 10, 14
+    h, hu, hv = (a.numpy() for a in ics.random_state(nx, ny, seed=3))
+    big_h = np.block([[h, h[:, ::-1]], [h[::-1, :], h[::-1, ::-1]]])
+    big_u = np.block([[hu, -hu[:, ::-1]], [hu[::-1, :], -hu[::-1, ::-1]]])
+    big_v = np.block([[hv, hv[:, ::-1]], [-hv[::-1, :], -hv[::-1, ::-1]]])
+    A = oracle.run(h, hu, hv, 25, scheme=scheme, bcx=REFLECT, bcy=REFLECT, dt_fixed=0.05)
+    B = oracle.run(big_h, big_u, big_v, 25, scheme=scheme, bcx=PERIODIC, bcy=PERIODIC, dt_fixed=0.05)
+    for a, b in zip(A[:3], B[:3]):
+        assert np.array_equal(interior(a), interior(b)[:ny, :nx])
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_uniform_directions_stay_uniform(scheme):
+    rng = np.random.default_rng(2)
+    row = 1.0 + 0.3 * rng.random(20)
+    mom = 0.1 * rng.standard_normal(20)
+    # y-uniform: h(x), hu(x), hv = 0 -> stays y-uniform and hv stays 0
+    h = np.tile(row, (6, 1)); hu = np.tile(mom, (6, 1)); hv = np.zeros_like(h)
+    H, U, V, _ = oracle.run(h, hu, hv, 40, scheme=scheme, bcx=PERIODIC, bcy=REFLECT)
+    assert np.all(interior(H) == interior(H)[:1]) and np.all(interior(V) == 0)
+    # x-uniform
+    H, U, V, _ = oracle.run(h.T.copy(), hv.T.copy(), hu.T.copy(), 40, scheme=scheme, bcx=REFLECT, bcy=PERIODIC)
+    assert np.all(interior(H) == interior(H)[:, :1]) and np.all(interior(U) == 0)
+
+
+# --------------------------------------------------------------------------
+# Physics: linear gravity-wave speed sqrt(g H)
+# --------------------------------------------------------------------------
+def _peak(profile, lo, hi):
+    k = lo + int(np.argmax(profile[lo:hi]))
+    ym, y0, yp = profile[k - 1], profile[k], profile[k + 1]
+    return k + 0.5 * (ym - yp) / (ym - 2 * y0 + yp)
+
+
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_linear_gravity_wave_speed(axis):
+    n, w, sigma, eps, x0 = 2048, 4, 24.0, 1e-3, 512.0
+    x = np.arange(n) + 0.5
+    pulse = 1.0 + eps * np.exp(-((x - x0) ** 2) / (2 * sigma ** 2))
+    h = np.tile(pulse, (w, 1))
+    z = np.zeros_like(h)
+    dt = 0.5 / math.sqrt(G)
+    c = math.sqrt(G)
+    s1, s2 = 400, 1200
+    pos = []
+    state = (h, z, z.copy()) if axis == "x" else (h.T.copy(), z.T.copy(), z.T.copy())
+    for nsteps in (s1, s2):
+        H, _, _, _ = oracle.run(*state, nsteps, g=G, dt_fixed=dt, bcx=PERIODIC, bcy=PERIODIC)
+        prof = interior(H)[0] if axis == "x" else interior(H)[:, 0]
+        pos.append(_peak(prof, int(x0) + 50, n - 10))
+    speed = (pos[1] - pos[0]) / ((s2 - s1) * dt)
+    assert abs(speed - c) / c < 0.01, speed
+
+
+# --------------------------------------------------------------------------
+# Accuracy order on a smooth solution
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("two_d", [False, True])
+def test_convergence_order(scheme, two_d):
+    """Smooth periodic flow on [0,1)^2, same Courant number on each grid,
+    errors against a 4x finer run (restricted by averaging fine cells).
+    Lax-Wendroff is second order where its dt^2 term is complete: in 1-D, and
+    in 2-D with the transverse term.  The literal 2-D scheme drops the
+    (AB + BA) u_xy part of that term, so in 2-D it is only first order."""
+    def init(n):
+        x = (np.arange(n) + 0.5) / n
+        X, Y = np.meshgrid(x, x, indexing="xy")
+        if not two_d:
+            h = 1.0 + 0.1 * np.sin(2 * np.pi * X)
+            return h, 0.05 * h, 0.0 * h
+        h = 1.0 + 0.1 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)
+        return h, 0.05 * np.cos(2 * np.pi * Y) * h, 0.02 * np.sin(2 * np.pi * X) * h
+
+    T = 0.05
+
+    def solve(n):
+        dx = 1.0 / n
+        dt = 0.4 * dx / (0.2 + math.sqrt(G * 1.1))
+        steps = int(round(T / dt))
+        dt = T / steps
+        H, _, _, _ = oracle.run(*init(n), steps, g=G, dx=dx, dy=dx, dt_fixed=dt, scheme=scheme,
+                                bcx=PERIODIC, bcy=PERIODIC)
+        return interior(H)
+
+    def restrict(a, f):
+        n = a.shape[0] // f
+        return a.reshape(n, f, n, f).mean(axis=(1, 3))
+
+    ref = solve(256)
+    errs = [np.sqrt(np.mean((solve(n) - restrict(ref, 256 // n)) ** 2)) for n in (32, 64)]
+    order = math.log2(errs[0] / errs[1])
+    if two_d and scheme == SCHEME_PAPER:
+        assert order < 1.5, (errs, order)
+    else:
+        assert order >= 1.8, (errs, order)
+
+
+# --------------------------------------------------------------------------
+# The paper's printed Fortran statements for h (reading of the signs)
+# --------------------------------------------------------------------------
+def region_cpy(a, halo):
+    """Interior of ``a`` (Fortran (x, y) indexing stored here as [y, x]) with
+    ``halo = [left, right, down, up]`` cells removed, as a copy."""
+    lt, rt, dn, up = halo
+    ny, nx = a.shape
+    return a[dn:ny - up, lt:nx - rt].copy()
+
+
+def test_fortran_h_statements_give_the_oracle_h():
+    """Cross-check of the sign reading: the paper's h face statement and h
+    update statement, evaluated with region copies, give the oracle's h."""
+    h, hu, hv = (a.numpy() for a in ics.random_state(11, 9, seed=8))
+    H, U, V = (oracle.with_halo(a) for a in (h, hu, hv))
+    oracle.fill_halo(H, U, V, REFLECT, REFLECT)
+    dt, dx, dy = 0.07, 1.0, 1.3
+    face_lt, face_rt, face_dn, face_up = [0, 1, 1, 1], [1, 0, 1, 1], [1, 1, 0, 1], [1, 1, 1, 0]
+    Hx = 0.5 * (region_cpy(H, face_lt) + region_cpy(H, face_rt)) + (0.5 * dt / dx) * (region_cpy(U, face_lt) - region_cpy(U, face_rt))
+    # the h update needs the face momenta Ux (x faces) and Vy (y faces)
+    FU = lambda Hh, Uu, Vv: Uu * Uu / Hh + 0.5 * G * Hh * Hh
+    GV = lambda Hh, Uu, Vv: Vv * Vv / Hh + 0.5 * G * Hh * Hh
+    Ux = 0.5 * (region_cpy(U, face_lt) + region_cpy(U, face_rt)) + (0.5 * dt / dx) * (
+        FU(region_cpy(H, face_lt), region_cpy(U, face_lt), None) - FU(region_cpy(H, face_rt), region_cpy(U, face_rt), None))
+    Vy = 0.5 * (region_cpy(V, face_dn) + region_cpy(V, face_up)) + (0.5 * dt / dy) * (
+        GV(region_cpy(H, face_dn), None, region_cpy(V, face_dn)) - GV(region_cpy(H, face_up), None, region_cpy(V, face_up)))
+    assert Hx.shape == (9, 12) and Vy.shape == (10, 11)
+    f_lt, f_rt, f_dn, f_up = [0, 1, 0, 0], [1, 0, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]
+    pH = region_cpy(H, [1, 1, 1, 1]) + (dt / dx) * (region_cpy(Ux, f_lt) - region_cpy(Ux, f_rt)) \
+        + (dt / dy) * (region_cpy(Vy, f_dn) - region_cpy(Vy, f_up))
+    oH, _, _ = oracle.step(H, U, V, G, dx, dy, dt, SCHEME_PAPER)
+    assert np.array_equal(interior(oH), pH)
+
+
+def test_unstable_state_is_reported():
+    h = np.full((6, 6), 1.0)
+    h[2, 3] = -0.5
+    with pytest.raises(oracle.Unstable):
+        oracle.run(h, np.zeros_like(h), np.zeros_like(h), 3, dt_fixed=0.01)
