@@ -1,0 +1,151 @@
+/*
+ * sw.h - C ABI of libsw, an MI355X (gfx950) library for the explicit
+ * two-step Lax-Wendroff time step of the 2-D shallow-water equations.
+ *
+ * The operation is the one of the paper's "Shallow Water Model" section:
+ * conserved state U = (h, hu, hv) at cell centres of a structured grid with a
+ * one-cell halo; per time step
+ *   (a) boundary values in the halo, applied outside the stencil kernel;
+ *   (b) dt from the CFL bound dt <= dx / (sqrt(g h) + |u|), here recomputed
+ *       every step as dt = cfl * min(dx, dy) / max_cells(max(|u|, |v|) + sqrt(g h)),
+ *       or a fixed dt (the paper's mode);
+ *   (c) step 1: half-step states on every cell face,
+ *         U_{i+1/2,j} = (U_i + U_{i+1})/2 - dt/(2 dx) (F(U_{i+1}) - F(U_i))
+ *         U_{i,j+1/2} = (U_j + U_{j+1})/2 - dt/(2 dy) (G(U_{j+1}) - G(U_j));
+ *   (d) step 2: dimensionally unsplit conservative update
+ *         U^{n+1} = U^n - dt/dx (F_{i+1/2} - F_{i-1/2}) - dt/dy (G_{j+1/2} - G_{j-1/2})
+ *       with F, G the SWE fluxes evaluated at the face states;
+ *   (e) double buffering: inputs are read-only, every output cell is written
+ *       by exactly one thread into the other buffer.
+ * The half-step sign follows the paper's Fortran face statement (its printed
+ * equation has the opposite sign and F in place of G in y).
+ *
+ * Conventions
+ *  - Every call returns sw_status (0 = ok, < 0 = error).  Nothing aborts or
+ *    throws across the ABI.  On error, sw_last_error_detail() holds a
+ *    thread-local message.
+ *  - "device pointer" = memory from hipMalloc (or a torch CUDA tensor) on the
+ *    current HIP device; "host pointer" = ordinary process memory.
+ *  - Streams are passed as void* (a hipStream_t; NULL = the null stream).
+ *    Calls marked async only enqueue work on that stream.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef SW_H
+#define SW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SW_OK = 0,
+    SW_EINVAL = -1,     /* bad argument: shape, pointer, alignment, option combination */
+    SW_ENOTSUP = -2,    /* valid but unsupported (halo width != 1, ...) */
+    SW_ENOMEM = -3,     /* host or device allocation failed */
+    SW_EHIP = -4,       /* a HIP runtime call failed (detail in sw_last_error_detail) */
+    SW_EUNSTABLE = -5   /* sticky: a step produced h <= 0 or a non-finite value */
+} sw_status;
+
+typedef enum { SW_F32 = 0, SW_F64 = 1 } sw_dtype;
+
+/* Global boundary conditions (the paper leaves them to the programmer, outside
+ * the kernel).  REFLECT: solid wall, ghost = mirror of the edge cell with the
+ * wall-normal momentum negated.  PERIODIC: ghost = opposite edge cell.
+ * Corner ghosts are the x-then-y composition of the two rules. */
+typedef enum { SW_BC_REFLECT = 0, SW_BC_PERIODIC = 1 } sw_bc;
+
+/* SW_SCHEME_PAPER: the paper's step 1 (1-D differences only).
+ * SW_SCHEME_TRANSVERSE: step 1 also carries the transverse flux term
+ *   - dt/(2 dy) * 1/4 [(G_{i,j+1} + G_{i+1,j+1}) - (G_{i,j-1} + G_{i+1,j-1})]
+ * on x faces (and the mirrored F term on y faces): the standard 2-D
+ * Lax-Wendroff, linearly stable up to CFL ~0.6 (not in the paper). */
+typedef enum { SW_SCHEME_PAPER = 0, SW_SCHEME_TRANSVERSE = 1 } sw_scheme;
+
+typedef struct { int32_t nx, ny; } sw_grid;                    /* interior cells */
+typedef struct { int32_t left, right, down, up; } sw_halo;     /* the paper's halo = [left, right, down, up] */
+
+typedef struct {
+    sw_dtype dtype;     /* arithmetic and storage type of the state */
+    sw_bc bc_x, bc_y;   /* boundary condition on the x walls and on the y walls */
+    sw_scheme scheme;
+    double dy;          /* <= 0 means dy = dx */
+    double cfl;         /* > 0: per-step CFL dt with this Courant number */
+    double dt_fixed;    /* > 0: fixed dt.  Exactly one of cfl, dt_fixed is > 0 */
+} sw_opts;
+
+/* Device layout of one state plane, chosen by the library.
+ * Cell (i, j), i in [-1, nx], j in [-1, ny] (ghosts at -1 and nx / ny) lives at
+ * element  origin + j * pitch + i  of the plane.  Rows are 256-byte aligned
+ * at the first interior column, so the interior is vector-load aligned. */
+typedef struct {
+    int64_t pitch;        /* elements per row */
+    int64_t origin;       /* element offset of interior cell (0, 0) */
+    int64_t plane_elems;  /* elements to allocate per plane */
+    int32_t elem_bytes;   /* 4 (SW_F32) or 8 (SW_F64) */
+    int32_t reserved;
+} sw_layout;
+
+/* Caller-owned device memory: two buffers (ping-pong) of three planes
+ * (h, hu, hv), each a device pointer, 256-byte aligned, holding
+ * layout.plane_elems elements.  buf[cur] holds U^n. */
+typedef struct {
+    void *plane[2][3];
+    int32_t cur;
+    int32_t reserved;
+} sw_state;
+
+typedef struct sw_ctx sw_ctx;   /* opaque; owns device scalars (dt ring, time, flags) */
+
+/* Layout of a plane for a grid and dtype.  Pure host computation.
+ * Errors: SW_EINVAL for nx, ny < 1, nx > 2^30, an unknown dtype or a NULL out. */
+sw_status sw_layout_query(sw_grid grid, sw_dtype dtype, sw_layout *out);
+
+/* Create a solver context for one grid (problem statement: grid, halo, g, dx).
+ * opts may be NULL: SW_F32, reflective walls, paper scheme, dy = dx, cfl 0.5.
+ * halo must be {1, 1, 1, 1} (the width the scheme needs), else SW_ENOTSUP.
+ * Allocates a few hundred bytes of device memory on the current device.
+ * Errors: SW_EINVAL (shape, g <= 0, dx <= 0, cfl/dt_fixed not exactly one
+ * positive, unknown enum), SW_ENOTSUP, SW_ENOMEM, SW_EHIP. */
+sw_status sw_create(sw_grid grid, sw_halo halo, double g, double dx, const sw_opts *opts, sw_ctx **out);
+sw_status sw_destroy(sw_ctx *ctx);
+sw_status sw_get_layout(const sw_ctx *ctx, sw_layout *out);
+
+/* Async.  Materialise the halo of buf[cur] from its interior by the boundary
+ * conditions (paper: BCs applied outside the kernel).  Interior untouched.
+ * Errors: SW_EINVAL (NULL / misaligned planes, cur not 0 or 1), SW_EHIP. */
+sw_status sw_fill_halo(sw_ctx *ctx, const sw_state *state, void *stream);
+
+/* Async.  Advance buf[cur] by nsteps time steps (nsteps >= 0) on the stream
+ * without any host synchronisation; then state->cur ^= (nsteps & 1).  dt is
+ * recomputed on the device every step (or fixed).  On return of the work,
+ * buf[cur] holds U^{n+nsteps} with its halo filled.  The halo of buf[cur] on
+ * entry is ignored (it is refilled first).  A step that produces h <= 0 or a
+ * non-finite value sets the context's sticky unstable flag (reported by
+ * sw_sync_status); the run continues on garbage.
+ * Errors (synchronous): SW_EINVAL, SW_EHIP. */
+sw_status sw_step(sw_ctx *ctx, sw_state *state, int32_t nsteps, void *stream);
+
+/* Synchronise the stream, then report the simulated time, the last dt and the
+ * number of steps taken since sw_create / sw_reset_time.  Any output pointer
+ * may be NULL.  Returns SW_EUNSTABLE if the sticky flag is set. */
+sw_status sw_sync_status(sw_ctx *ctx, void *stream, double *t, double *last_dt, int64_t *steps);
+
+/* Async.  Zero the simulated time and step counter and clear the sticky flag. */
+sw_status sw_reset_time(sw_ctx *ctx, void *stream);
+
+/* Kernel variant used by sw_step: 0 = auto (fastest known), 1 = one thread
+ * per cell reading neighbours from global memory (baseline), 2 = fused
+ * row-marching kernel.  Results are identical up to rounding order.
+ * Errors: SW_EINVAL for an unknown variant. */
+sw_status sw_set_variant(sw_ctx *ctx, int32_t variant);
+
+const char *sw_strerror(sw_status status);
+const char *sw_last_error_detail(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SW_H */

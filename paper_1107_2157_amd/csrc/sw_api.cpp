@@ -1,0 +1,271 @@
+// libsw C-ABI host side: argument validation, layout, context lifetime and
+// the launch sequence of a time-step call.  All arguments are validated
+// before any HIP call, so invalid input never reaches a kernel.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <new>
+#include <string>
+
+#include "../../include/sw.h"
+#include "sw_internal.h"
+
+struct sw_ctx {
+    sw_grid grid;
+    sw_opts opts;
+    double g, dx, dy;
+    sw_layout layout;
+    int device;
+    int variant;
+    SwScalars *sc;   // device
+};
+
+namespace {
+
+thread_local std::string g_detail;
+
+sw_status fail(sw_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_detail = buf;
+    return s;
+}
+
+#define SW_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) return fail(SW_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int64_t kAlignBytes = 256;
+
+sw_status layout_for(sw_grid grid, sw_dtype dtype, sw_layout *out) {
+    if (!out) return fail(SW_EINVAL, "layout: NULL output");
+    if (dtype != SW_F32 && dtype != SW_F64) return fail(SW_EINVAL, "layout: unknown dtype %d", (int)dtype);
+    if (grid.nx < 1 || grid.ny < 1) return fail(SW_EINVAL, "layout: grid %d x %d is empty", grid.nx, grid.ny);
+    if (grid.nx > (1 << 30) || grid.ny > (1 << 30)) return fail(SW_EINVAL, "layout: grid side above 2^30");
+    const int64_t eb = dtype == SW_F64 ? 8 : 4;
+    const int64_t a = kAlignBytes / eb;                       // elements per 256 bytes
+    const int64_t lead = a;                                   // interior starts 256 B into each row
+    int64_t pitch = (lead + (int64_t)grid.nx + 1 + a - 1) / a * a;
+    // Avoid row pitches that are a large power of two (all rows would start on
+    // the same HBM channel): add one 256-byte block if pitch*eb is a multiple of 64 KiB.
+    if ((pitch * eb) % (64 * 1024) == 0) pitch += a;
+    out->pitch = pitch;
+    out->origin = pitch + lead;
+    out->plane_elems = pitch * ((int64_t)grid.ny + 2);
+    out->elem_bytes = (int32_t)eb;
+    out->reserved = 0;
+    return SW_OK;
+}
+
+sw_status check_state(const sw_ctx *ctx, const sw_state *st, bool both_buffers) {
+    if (!st) return fail(SW_EINVAL, "state: NULL");
+    if (st->cur != 0 && st->cur != 1) return fail(SW_EINVAL, "state: cur = %d (must be 0 or 1)", st->cur);
+    for (int b = 0; b < 2; ++b) {
+        if (!both_buffers && b != st->cur) continue;
+        for (int k = 0; k < 3; ++k) {
+            const void *p = st->plane[b][k];
+            if (!p) return fail(SW_EINVAL, "state: plane[%d][%d] is NULL", b, k);
+            if ((uintptr_t)p % kAlignBytes) return fail(SW_EINVAL, "state: plane[%d][%d] not 256-byte aligned", b, k);
+        }
+    }
+    if (both_buffers)
+        for (int k = 0; k < 3; ++k)
+            for (int m = 0; m < 3; ++m)
+                if (st->plane[0][k] == st->plane[1][m])
+                    return fail(SW_EINVAL, "state: buffers 0 and 1 share plane memory (double buffering needs distinct planes)");
+    return SW_OK;
+}
+
+SwLaunch launch_of(const sw_ctx *ctx, const sw_state *st, int from) {
+    SwLaunch a{};
+    const int64_t eb = ctx->layout.elem_bytes;
+    for (int k = 0; k < 3; ++k) {
+        a.in[k] = (const char *)st->plane[from][k] + ctx->layout.origin * eb;
+        a.out[k] = (char *)st->plane[from ^ 1][k] + ctx->layout.origin * eb;
+    }
+    a.pitch = ctx->layout.pitch;
+    a.nx = ctx->grid.nx;
+    a.ny = ctx->grid.ny;
+    a.g = ctx->g;
+    a.dx = ctx->dx;
+    a.dy = ctx->dy;
+    a.cfl = ctx->opts.cfl;
+    a.dt_fixed = ctx->opts.dt_fixed;
+    a.bc_x = (int32_t)ctx->opts.bc_x;
+    a.bc_y = (int32_t)ctx->opts.bc_y;
+    a.scheme = (int32_t)ctx->opts.scheme;
+    a.dtype = (int32_t)ctx->opts.dtype;
+    a.sc = ctx->sc;
+    a.step = 0;
+    return a;
+}
+
+sw_status use_device(const sw_ctx *ctx) {
+    int cur = -1;
+    SW_HIP(hipGetDevice(&cur));
+    if (cur != ctx->device) SW_HIP(hipSetDevice(ctx->device));
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sw_strerror(sw_status s) {
+    switch (s) {
+        case SW_OK: return "ok";
+        case SW_EINVAL: return "invalid argument";
+        case SW_ENOTSUP: return "not supported";
+        case SW_ENOMEM: return "out of memory";
+        case SW_EHIP: return "HIP runtime error";
+        case SW_EUNSTABLE: return "unstable: h <= 0 or non-finite value";
+    }
+    return "unknown status";
+}
+
+const char *sw_last_error_detail(void) { return g_detail.c_str(); }
+
+sw_status sw_layout_query(sw_grid grid, sw_dtype dtype, sw_layout *out) { return layout_for(grid, dtype, out); }
+
+sw_status sw_create(sw_grid grid, sw_halo halo, double g, double dx, const sw_opts *opts, sw_ctx **out) {
+    if (!out) return fail(SW_EINVAL, "create: NULL output");
+    *out = nullptr;
+    sw_opts o;
+    if (opts) {
+        o = *opts;
+    } else {
+        o.dtype = SW_F32;
+        o.bc_x = o.bc_y = SW_BC_REFLECT;
+        o.scheme = SW_SCHEME_PAPER;
+        o.dy = 0.0;
+        o.cfl = 0.5;
+        o.dt_fixed = 0.0;
+    }
+    sw_layout lay;
+    sw_status st = layout_for(grid, o.dtype, &lay);
+    if (st != SW_OK) return st;
+    if (!(g > 0) || !(dx > 0)) return fail(SW_EINVAL, "create: g = %g and dx = %g must be > 0", g, dx);
+    double dy = o.dy > 0 ? o.dy : dx;
+    if ((o.bc_x != SW_BC_REFLECT && o.bc_x != SW_BC_PERIODIC) || (o.bc_y != SW_BC_REFLECT && o.bc_y != SW_BC_PERIODIC))
+        return fail(SW_EINVAL, "create: unknown boundary condition");
+    if (o.scheme != SW_SCHEME_PAPER && o.scheme != SW_SCHEME_TRANSVERSE)
+        return fail(SW_EINVAL, "create: unknown scheme %d", (int)o.scheme);
+    if ((o.cfl > 0) == (o.dt_fixed > 0))
+        return fail(SW_EINVAL, "create: exactly one of cfl (%g) and dt_fixed (%g) must be > 0", o.cfl, o.dt_fixed);
+    if (!(o.cfl >= 0) || !(o.dt_fixed >= 0)) return fail(SW_EINVAL, "create: cfl / dt_fixed not a number");
+    if (halo.left < 0 || halo.right < 0 || halo.down < 0 || halo.up < 0)
+        return fail(SW_EINVAL, "create: negative halo width");
+    if (halo.left != 1 || halo.right != 1 || halo.down != 1 || halo.up != 1)
+        return fail(SW_ENOTSUP, "create: halo [%d,%d,%d,%d]; the scheme uses [1,1,1,1]", halo.left, halo.right,
+                    halo.down, halo.up);
+    sw_ctx *c = new (std::nothrow) sw_ctx{};
+    if (!c) return fail(SW_ENOMEM, "create: host allocation");
+    c->grid = grid;
+    c->opts = o;
+    c->opts.dy = dy;
+    c->g = g;
+    c->dx = dx;
+    c->dy = dy;
+    c->layout = lay;
+    c->variant = 0;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->sc, sizeof(SwScalars));
+    if (e == hipSuccess) e = hipMemset(c->sc, 0, sizeof(SwScalars));
+    if (e != hipSuccess) {
+        if (c->sc) (void)hipFree(c->sc);
+        delete c;
+        return fail(e == hipErrorOutOfMemory ? SW_ENOMEM : SW_EHIP, "create: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return SW_OK;
+}
+
+sw_status sw_destroy(sw_ctx *ctx) {
+    if (!ctx) return SW_OK;
+    if (ctx->sc) {
+        (void)use_device(ctx);
+        (void)hipFree(ctx->sc);
+    }
+    delete ctx;
+    return SW_OK;
+}
+
+sw_status sw_get_layout(const sw_ctx *ctx, sw_layout *out) {
+    if (!ctx || !out) return fail(SW_EINVAL, "get_layout: NULL argument");
+    *out = ctx->layout;
+    return SW_OK;
+}
+
+sw_status sw_set_variant(sw_ctx *ctx, int32_t variant) {
+    if (!ctx) return fail(SW_EINVAL, "set_variant: NULL context");
+    if (variant < 0 || variant > 2) return fail(SW_EINVAL, "set_variant: unknown variant %d", variant);
+    ctx->variant = variant;
+    return SW_OK;
+}
+
+sw_status sw_fill_halo(sw_ctx *ctx, const sw_state *state, void *stream) {
+    if (!ctx) return fail(SW_EINVAL, "fill_halo: NULL context");
+    sw_status st = check_state(ctx, state, false);
+    if (st != SW_OK) return st;
+    if ((st = use_device(ctx)) != SW_OK) return st;
+    SwLaunch a = launch_of(ctx, state, state->cur);
+    SW_HIP(sw_launch_fill_halo(a, (hipStream_t)stream));
+    return SW_OK;
+}
+
+sw_status sw_step(sw_ctx *ctx, sw_state *state, int32_t nsteps, void *stream) {
+    if (!ctx) return fail(SW_EINVAL, "step: NULL context");
+    if (nsteps < 0) return fail(SW_EINVAL, "step: nsteps = %d < 0", nsteps);
+    sw_status st = check_state(ctx, state, true);
+    if (st != SW_OK) return st;
+    if (nsteps == 0) return SW_OK;
+    if ((st = use_device(ctx)) != SW_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    int variant = ctx->variant;
+    if (variant == 0) variant = ctx->opts.scheme == SW_SCHEME_PAPER ? 2 : 1;
+    if (variant == 2 && ctx->opts.scheme != SW_SCHEME_PAPER)
+        return fail(SW_ENOTSUP, "step: the fused kernel implements the paper scheme only");
+    SW_HIP(sw_launch_reset(ctx->sc, 0, s));
+    SwLaunch a = launch_of(ctx, state, state->cur);
+    SW_HIP(sw_launch_prologue(a, s));
+    int cur = state->cur;
+    for (int n = 0; n < nsteps; ++n) {
+        SwLaunch b = launch_of(ctx, state, cur);
+        b.step = n;
+        SW_HIP(sw_launch_step(b, variant, s));
+        cur ^= 1;
+    }
+    state->cur = cur;
+    return SW_OK;
+}
+
+sw_status sw_sync_status(sw_ctx *ctx, void *stream, double *t, double *last_dt, int64_t *steps) {
+    if (!ctx) return fail(SW_EINVAL, "sync_status: NULL context");
+    sw_status st = use_device(ctx);
+    if (st != SW_OK) return st;
+    SW_HIP(hipStreamSynchronize((hipStream_t)stream));
+    SwScalars h;
+    SW_HIP(hipMemcpy(&h, ctx->sc, sizeof h, hipMemcpyDeviceToHost));
+    if (t) *t = h.t;
+    if (last_dt) *last_dt = h.last_dt;
+    if (steps) *steps = h.steps;
+    if (h.unstable) return fail(SW_EUNSTABLE, "a step produced h <= 0 or a non-finite value");
+    return SW_OK;
+}
+
+sw_status sw_reset_time(sw_ctx *ctx, void *stream) {
+    if (!ctx) return fail(SW_EINVAL, "reset_time: NULL context");
+    sw_status st = use_device(ctx);
+    if (st != SW_OK) return st;
+    SW_HIP(sw_launch_reset(ctx->sc, 1, (hipStream_t)stream));
+    return SW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,42 @@
+// Internal interface between the C-ABI host code and the HIP kernels of libsw.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+// Device-resident scalars of one solver context.
+//  smax[3]  ring of max-signal-speed slots, as the bit pattern of a
+//           non-negative double (so unsigned max == double max).  Step n
+//           reads slot n%3, max-reduces U^{n+1} into slot (n+1)%3 and clears
+//           slot (n+2)%3 for step n+1.
+struct SwScalars {
+    unsigned long long smax[3];
+    double t;                 // simulated time
+    double last_dt;           // dt of the last step
+    long long steps;          // steps taken
+    unsigned int unstable;    // sticky: some step produced h <= 0 or non-finite
+    unsigned int pad;
+};
+
+// One launch's view of the state and the parameters of the scheme.  Plane
+// pointers point at interior cell (0, 0); cell (i, j) is p[j * pitch + i]
+// for i in [-1, nx], j in [-1, ny].
+struct SwLaunch {
+    const void *in[3];
+    void *out[3];
+    int64_t pitch;
+    int32_t nx, ny;
+    double g, dx, dy, cfl, dt_fixed;
+    int32_t bc_x, bc_y;       // 0 reflect, 1 periodic
+    int32_t scheme;           // 0 paper, 1 transverse
+    int32_t dtype;            // 0 f32, 1 f64
+    SwScalars *sc;
+    int32_t step;             // index of this step inside the call (ring position)
+};
+
+hipError_t sw_launch_reset(SwScalars *sc, int clear_time, hipStream_t s);
+// Fill the halo of `in` (written through in[]) and max-reduce its interior
+// signal speed into slot 0.
+hipError_t sw_launch_prologue(const SwLaunch &a, hipStream_t s);
+hipError_t sw_launch_fill_halo(const SwLaunch &a, hipStream_t s);
+// variant: 1 = per-cell baseline, 2 = fused row-marching kernel.
+hipError_t sw_launch_step(const SwLaunch &a, int variant, hipStream_t s);

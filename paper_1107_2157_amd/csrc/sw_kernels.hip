@@ -1,0 +1,158 @@
+// libsw HIP kernels (gfx950): context reset, CFL prologue with halo fill,
+// stand-alone halo fill, and the per-cell baseline step.
+#include "sw_common.h"
+
+using namespace sw;
+
+namespace {
+
+__global__ void k_reset(SwScalars *sc, int clear_time) {
+    if (threadIdx.x == 0) {
+        sc->smax[0] = 0ull;
+        sc->smax[1] = 0ull;
+        sc->smax[2] = 0ull;
+        if (clear_time) {
+            sc->t = 0.0;
+            sc->last_dt = 0.0;
+            sc->steps = 0;
+            sc->unstable = 0u;
+        }
+    }
+}
+
+// Fill the halo of the buffer from its interior and max-reduce the interior
+// signal speed into ring slot 0 (the dt of the first step of a call).
+template <typename T>
+__global__ __launch_bounds__(256) void k_prologue(SwLaunch a) {
+    T *P[3] = {(T *)a.in[0], (T *)a.in[1], (T *)a.in[2]};
+    const int nx = a.nx, ny = a.ny;
+    const int64_t n = (int64_t)nx * ny;
+    const T g = (T)a.g;
+    double smax = 0.0;
+    bool bad = false;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int j = (int)(idx / nx), i = (int)(idx - (int64_t)j * nx);
+        int64_t off = (int64_t)j * a.pitch + i;
+        U3<T> c = {P[0][off], P[1][off], P[2][off]};
+        T s = signal_speed(c, g);
+        bad |= !(s <= finite_max<T>());
+        smax = fmax(smax, (double)s);
+        if (i == 0 || i == nx - 1 || j == 0 || j == ny - 1)
+            write_ghosts(P, a.pitch, nx, ny, a.bc_x, a.bc_y, i, j, c);
+    }
+    smax = wave_max(smax);
+    unsigned long long anybad = __ballot(bad);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&a.sc->smax[0], (unsigned long long)__double_as_longlong(smax));
+        if (anybad) atomicOr(&a.sc->unstable, 1u);
+    }
+}
+
+// Halo only: one thread per perimeter cell (corner cells appear twice and
+// write identical values).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill_halo(SwLaunch a) {
+    T *P[3] = {(T *)a.in[0], (T *)a.in[1], (T *)a.in[2]};
+    const int nx = a.nx, ny = a.ny;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (t < nx) { i = t; j = 0; }
+    else if (t < 2 * nx) { i = t - nx; j = ny - 1; }
+    else if (t < 2 * nx + ny) { i = 0; j = t - 2 * nx; }
+    else if (t < 2 * nx + 2 * ny) { i = nx - 1; j = t - 2 * nx - ny; }
+    else return;
+    int64_t off = (int64_t)j * a.pitch + i;
+    U3<T> c = {P[0][off], P[1][off], P[2][off]};
+    write_ghosts(P, a.pitch, nx, ny, a.bc_x, a.bc_y, i, j, c);
+}
+
+// Baseline step: one thread per interior cell, neighbours read straight from
+// global memory, each face computed by both cells that share it.  64 x 4
+// threads per block.
+template <typename T, int TRANS>
+__global__ __launch_bounds__(256) void k_step_cell(SwLaunch a) {
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const double dt = step_dt(a);
+    const T k = (T)(0.5 * a.g), g = (T)a.g;
+    const T lx = (T)(0.5 * dt / a.dx), ly = (T)(0.5 * dt / a.dy);
+    const T mx = (T)(dt / a.dx), my = (T)(dt / a.dy);
+    const T lx4 = (T)(0.125 * dt / a.dx), ly4 = (T)(0.125 * dt / a.dy);
+    const T *I[3] = {(const T *)a.in[0], (const T *)a.in[1], (const T *)a.in[2]};
+    T *O[3] = {(T *)a.out[0], (T *)a.out[1], (T *)a.out[2]};
+    const int64_t pitch = a.pitch;
+    double smax = 0.0;
+    bool bad = false;
+    if (i < a.nx && j < a.ny) {
+        auto ld = [&](int di, int dj) {
+            int64_t off = (int64_t)(j + dj) * pitch + (i + di);
+            return U3<T>{I[0][off], I[1][off], I[2][off]};
+        };
+        U3<T> c = ld(0, 0), w = ld(-1, 0), e = ld(1, 0), s = ld(0, -1), n = ld(0, 1);
+        U3<T> Fc = flux_f(c, k), Fw = flux_f(w, k), Fe = flux_f(e, k);
+        U3<T> Gc = flux_g(c, k), Gs = flux_g(s, k), Gn = flux_g(n, k);
+        U3<T> xl = half_step(w, c, Fw, Fc, lx), xr = half_step(c, e, Fc, Fe, lx);
+        U3<T> yd = half_step(s, c, Gs, Gc, ly), yu = half_step(c, n, Gc, Gn, ly);
+        if (TRANS) {
+            U3<T> sw_ = ld(-1, -1), se = ld(1, -1), nw = ld(-1, 1), ne = ld(1, 1);
+            U3<T> Gsw = flux_g(sw_, k), Gse = flux_g(se, k), Gnw = flux_g(nw, k), Gne = flux_g(ne, k);
+            U3<T> Gw = flux_g(w, k), Ge = flux_g(e, k);
+            U3<T> Fsw = flux_f(sw_, k), Fse = flux_f(se, k), Fnw = flux_f(nw, k), Fne = flux_f(ne, k);
+            U3<T> Fs = flux_f(s, k), Fn = flux_f(n, k);
+            xl = add_transverse(xl, Gsw, Gs, Gnw, Gn, ly4);
+            xr = add_transverse(xr, Gs, Gse, Gn, Gne, ly4);
+            yd = add_transverse(yd, Fsw, Fw, Fse, Fe, lx4);
+            yu = add_transverse(yu, Fw, Fnw, Fe, Fne, lx4);
+        }
+        U3<T> FL = flux_f(xl, k), FR = flux_f(xr, k), GD = flux_g(yd, k), GU = flux_g(yu, k);
+        U3<T> r = {fma(-my, GU.h - GD.h, fma(-mx, FR.h - FL.h, c.h)),
+                   fma(-my, GU.p - GD.p, fma(-mx, FR.p - FL.p, c.p)),
+                   fma(-my, GU.q - GD.q, fma(-mx, FR.q - FL.q, c.q))};
+        int64_t off = (int64_t)j * pitch + i;
+        O[0][off] = r.h; O[1][off] = r.p; O[2][off] = r.q;
+        write_ghosts(O, pitch, a.nx, a.ny, a.bc_x, a.bc_y, i, j, r);
+        T sp = signal_speed(r, g);
+        bad = !(sp <= finite_max<T>());
+        smax = (double)sp;
+    }
+    step_epilogue(a, smax, bad, dt, blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0);
+}
+
+template <typename T> hipError_t launch_step_cell(const SwLaunch &a, hipStream_t s) {
+    dim3 grid((a.nx + 63) / 64, (a.ny + 3) / 4);
+    if (a.scheme) k_step_cell<T, 1><<<grid, 256, 0, s>>>(a);
+    else k_step_cell<T, 0><<<grid, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t sw_launch_fused(const SwLaunch &a, hipStream_t s);
+
+hipError_t sw_launch_reset(SwScalars *sc, int clear_time, hipStream_t s) {
+    k_reset<<<1, 64, 0, s>>>(sc, clear_time);
+    return hipGetLastError();
+}
+
+hipError_t sw_launch_prologue(const SwLaunch &a, hipStream_t s) {
+    int64_t n = (int64_t)a.nx * a.ny;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (a.dtype) k_prologue<double><<<(unsigned)blocks, 256, 0, s>>>(a);
+    else k_prologue<float><<<(unsigned)blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t sw_launch_fill_halo(const SwLaunch &a, hipStream_t s) {
+    int64_t n = 2 * ((int64_t)a.nx + a.ny);
+    unsigned blocks = (unsigned)((n + 255) / 256);
+    if (a.dtype) k_fill_halo<double><<<blocks, 256, 0, s>>>(a);
+    else k_fill_halo<float><<<blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t sw_launch_step(const SwLaunch &a, int variant, hipStream_t s) {
+    if (variant == 2) return sw_launch_fused(a, s);
+    return a.dtype ? launch_step_cell<double>(a, s) : launch_step_cell<float>(a, s);
+}

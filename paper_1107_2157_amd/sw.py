@@ -1,0 +1,192 @@
+"""Thin ctypes binding of libsw (``include/sw.h``).
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  PyTorch provides the device memory (plane tensors) and the stream.
+If ``libsw.so`` is not built, loading fails loudly; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(PKG, "libsw.so")
+
+OK, EINVAL, ENOTSUP, ENOMEM, EHIP, EUNSTABLE = 0, -1, -2, -3, -4, -5
+F32, F64 = 0, 1
+REFLECT, PERIODIC = 0, 1
+SCHEME_PAPER, SCHEME_TRANSVERSE = 0, 1
+VARIANT_AUTO, VARIANT_CELL, VARIANT_FUSED = 0, 1, 2
+
+_DT = {"f32": F32, "f64": F64, torch.float32: F32, torch.float64: F64}
+_TORCH_DT = {F32: torch.float32, F64: torch.float64}
+
+
+class SwError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+class Unstable(SwError):
+    """The sticky flag is set: some step produced h <= 0 or a non-finite value."""
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32)]
+
+
+class Halo(ctypes.Structure):
+    _fields_ = [("left", ctypes.c_int32), ("right", ctypes.c_int32),
+                ("down", ctypes.c_int32), ("up", ctypes.c_int32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int),
+                ("scheme", ctypes.c_int), ("dy", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("dt_fixed", ctypes.c_double)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("pitch", ctypes.c_int64), ("origin", ctypes.c_int64),
+                ("plane_elems", ctypes.c_int64), ("elem_bytes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class State(ctypes.Structure):
+    _fields_ = [("plane", (ctypes.c_void_p * 3) * 2), ("cur", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+# name -> (restype, argtypes); every symbol of include/sw.h
+SIGNATURES = {
+    "sw_layout_query": (ctypes.c_int, [Grid, ctypes.c_int, ctypes.POINTER(Layout)]),
+    "sw_create": (ctypes.c_int, [Grid, Halo, ctypes.c_double, ctypes.c_double, ctypes.POINTER(Opts),
+                                 ctypes.POINTER(ctypes.c_void_p)]),
+    "sw_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sw_get_layout": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Layout)]),
+    "sw_fill_halo": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(State), ctypes.c_void_p]),
+    "sw_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(State), ctypes.c_int32, ctypes.c_void_p]),
+    "sw_sync_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "sw_reset_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sw_set_variant": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "sw_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "sw_last_error_detail": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Load libsw.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is not built; run `python -m paper_1107_2157_amd.build`")
+        L = ctypes.CDLL(LIBPATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int, where: str):
+    if status != OK:
+        detail = lib().sw_last_error_detail().decode(errors="replace")
+        cls = Unstable if status == EUNSTABLE else SwError
+        raise cls(status, where, detail)
+
+
+def layout_query(nx: int, ny: int, dtype="f32") -> Layout:
+    out = Layout()
+    check(lib().sw_layout_query(Grid(nx, ny), _DT[dtype], ctypes.byref(out)), "sw_layout_query")
+    return out
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Solver:
+    """One grid: a context plus its ping-pong state planes in device memory."""
+
+    def __init__(self, nx: int, ny: int, g: float = 9.8, dx: float = 1.0, dtype="f32",
+                 bc_x: int = REFLECT, bc_y: int = REFLECT, scheme: int = SCHEME_PAPER,
+                 dy: float = 0.0, cfl: float = 0.5, dt_fixed: float = 0.0, device="cuda",
+                 variant: int = VARIANT_AUTO):
+        self.nx, self.ny = nx, ny
+        self.dtype = _DT[dtype]
+        self.torch_dtype = _TORCH_DT[self.dtype]
+        opts = Opts(self.dtype, bc_x, bc_y, scheme, dy, cfl, dt_fixed)
+        ctx = ctypes.c_void_p()
+        check(lib().sw_create(Grid(nx, ny), Halo(1, 1, 1, 1), g, dx, ctypes.byref(opts), ctypes.byref(ctx)),
+              "sw_create")
+        self.ctx = ctx
+        self.layout = Layout()
+        check(lib().sw_get_layout(ctx, ctypes.byref(self.layout)), "sw_get_layout")
+        n = self.layout.plane_elems
+        self.planes = [[torch.zeros(n, dtype=self.torch_dtype, device=device) for _ in range(3)]
+                       for _ in range(2)]
+        self.state = State()
+        for b in range(2):
+            for k in range(3):
+                self.state.plane[b][k] = self.planes[b][k].data_ptr()
+        self.state.cur = 0
+        if variant != VARIANT_AUTO:
+            self.set_variant(variant)
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None) and _lib is not None:
+                _lib.sw_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    # ---- views -----------------------------------------------------------
+    def halo_view(self, k: int, buf: int | None = None) -> torch.Tensor:
+        """(ny + 2, nx + 2) strided view of plane k (0 h, 1 hu, 2 hv) with its halo."""
+        b = self.state.cur if buf is None else buf
+        L = self.layout
+        return torch.as_strided(self.planes[b][k], (self.ny + 2, self.nx + 2), (L.pitch, 1),
+                                L.origin - L.pitch - 1)
+
+    def interior(self, k: int, buf: int | None = None) -> torch.Tensor:
+        return self.halo_view(k, buf)[1:-1, 1:-1]
+
+    def set_state(self, h, hu, hv):
+        """Write an interior state (any float dtype/device) into buf[cur]."""
+        for k, a in enumerate((h, hu, hv)):
+            self.interior(k).copy_(torch.as_tensor(a).to(self.torch_dtype))
+
+    def get_state(self, halo: bool = False):
+        """Copy of (h, hu, hv) of buf[cur] on the host as float64 tensors."""
+        torch.cuda.synchronize()
+        f = self.halo_view if halo else self.interior
+        return tuple(f(k).to("cpu", torch.float64) for k in range(3))
+
+    # ---- calls -----------------------------------------------------------
+    def set_variant(self, variant: int):
+        check(lib().sw_set_variant(self.ctx, variant), "sw_set_variant")
+
+    def fill_halo(self, stream=None):
+        check(lib().sw_fill_halo(self.ctx, ctypes.byref(self.state), _stream_handle(stream)), "sw_fill_halo")
+
+    def step(self, nsteps: int, stream=None):
+        check(lib().sw_step(self.ctx, ctypes.byref(self.state), nsteps, _stream_handle(stream)), "sw_step")
+
+    def sync_status(self, stream=None):
+        """(t, last_dt, steps); raises Unstable if the sticky flag is set."""
+        t, dt, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        check(lib().sw_sync_status(self.ctx, _stream_handle(stream), ctypes.byref(t), ctypes.byref(dt),
+                                   ctypes.byref(n)), "sw_sync_status")
+        return t.value, dt.value, n.value
+
+    def reset_time(self, stream=None):
+        check(lib().sw_reset_time(self.ctx, _stream_handle(stream)), "sw_reset_time")

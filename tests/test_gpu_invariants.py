@@ -1,0 +1,99 @@
+"""Invariants of the scheme checked on the GPU path (through the C ABI):
+lake at rest (bitwise), mass conservation, mirror symmetry of a centred dam
+break (bitwise), determinism, and the sticky instability flag."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1107_2157_amd import ics, sw
+from swtest import G, announce
+
+pytestmark = pytest.mark.gpu
+VARIANTS = [sw.VARIANT_CELL, sw.VARIANT_FUSED]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("scheme", [sw.SCHEME_PAPER, sw.SCHEME_TRANSVERSE])
+def test_lake_at_rest_bitwise(variant, dtype, scheme):
+    if variant == sw.VARIANT_FUSED and scheme == sw.SCHEME_TRANSVERSE:
+        pytest.skip("fused kernel covers the paper scheme only")
+    for bc in (sw.REFLECT, sw.PERIODIC):
+        announce(f"lake at rest {dtype} v{variant} s{scheme} bc{bc}")
+        s = sw.Solver(129, 65, dtype=dtype, bc_x=bc, bc_y=bc, scheme=scheme, variant=variant)
+        h = torch.full((65, 129), 1.37, dtype=torch.float64)
+        s.set_state(h, torch.zeros_like(h), torch.zeros_like(h))
+        s.step(50)
+        H, U, V = s.get_state()
+        want = torch.tensor(1.37, dtype=s.torch_dtype).item()
+        assert bool((H == want).all()) and bool((U == 0).all()) and bool((V == 0).all())
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_mirror_symmetry_bitwise(variant, dtype):
+    announce(f"mirror {dtype} v{variant}")
+    s = sw.Solver(128, 128, dtype=dtype, variant=variant)
+    s.set_state(*ics.dam_break_state(128))
+    s.step(100)
+    H, U, V = (a.numpy() for a in s.get_state())
+    assert np.array_equal(H, H[:, ::-1]) and np.array_equal(U, -U[:, ::-1]) and np.array_equal(V, V[:, ::-1])
+    assert np.array_equal(H, H[::-1, :]) and np.array_equal(U, U[::-1, :]) and np.array_equal(V, -V[::-1, :])
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-6)])
+@pytest.mark.parametrize("bc", [sw.REFLECT, sw.PERIODIC])
+def test_mass_conservation(variant, dtype, tol, bc):
+    announce(f"mass {dtype} v{variant} bc{bc}")
+    n = 512
+    st = ics.bumps_state(n, n, seed=21, periodic=bc == sw.PERIODIC, count=8)
+    s = sw.Solver(n, n, dtype=dtype, bc_x=bc, bc_y=bc, variant=variant)
+    s.set_state(*st)
+    m0 = math.fsum(s.get_state()[0].numpy().ravel())
+    s.step(100)
+    m1 = math.fsum(s.get_state()[0].numpy().ravel())
+    assert abs(m1 - m0) / m0 <= tol
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_deterministic_bitwise(variant):
+    st = ics.bumps_state(700, 300, seed=5, periodic=True, count=8)
+    outs = []
+    for _ in range(2):
+        s = sw.Solver(700, 300, dtype="f32", bc_x=sw.PERIODIC, bc_y=sw.PERIODIC, variant=variant)
+        s.set_state(*st)
+        s.step(60)
+        outs.append([a.numpy() for a in s.get_state(halo=True)] + [s.sync_status()])
+    for a, b in zip(outs[0][:3], outs[1][:3]):
+        assert np.array_equal(a, b)
+    assert outs[0][3] == outs[1][3]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_negative_depth_sets_sticky_flag(variant):
+    s = sw.Solver(40, 30, dtype="f32", variant=variant, dt_fixed=0.01, cfl=0.0)
+    h = torch.ones((30, 40), dtype=torch.float64)
+    h[10, 20] = -1.0
+    s.set_state(h, torch.zeros_like(h), torch.zeros_like(h))
+    s.step(2)
+    with pytest.raises(sw.Unstable):
+        s.sync_status()
+    s.reset_time()
+    s.set_state(torch.ones_like(h), torch.zeros_like(h), torch.zeros_like(h))
+    s.step(2)
+    t, dt, n = s.sync_status()
+    assert n == 2 and t == pytest.approx(0.02)
+
+
+def test_step_zero_and_cur_flip():
+    s = sw.Solver(16, 16, dtype="f64")
+    s.set_state(*ics.dam_break_state(16))
+    s.step(0)
+    assert s.state.cur == 0
+    s.step(3)
+    assert s.state.cur == 1
+    s.step(1)
+    assert s.state.cur == 0
