@@ -138,9 +138,37 @@ sw_status sw_reset_time(sw_ctx *ctx, void *stream);
 
 /* Kernel variant used by sw_step: 0 = auto (fastest known), 1 = one thread
  * per cell reading neighbours from global memory (baseline), 2 = fused
- * row-marching kernel.  Results are identical up to rounding order.
- * Errors: SW_EINVAL for an unknown variant. */
+ * row-marching kernel (paper scheme only).  Results agree up to rounding
+ * order.  Errors: SW_EINVAL for an unknown variant. */
 sw_status sw_set_variant(sw_ctx *ctx, int32_t variant);
+
+/* Launch shape of the step kernel (what the autotuner searches).  Zero
+ * fields mean "library default".  All fused shapes compute every cell with
+ * the same arithmetic, so their results are bitwise identical; the per-cell
+ * baseline agrees with them to rounding. */
+typedef struct {
+    int32_t variant;    /* 0 auto, 1 per-cell baseline, 2 fused */
+    int32_t rows;       /* fused: rows per tile (>= 1) */
+    int32_t vec;        /* fused: cells per lane; SW_F32: 2 or 4, SW_F64: 1 or 2 */
+    int32_t occupancy;  /* fused: register budget in waves per SIMD: 0 (compiler's choice), 3 or 4 */
+} sw_tuning;
+
+/* Errors: SW_EINVAL for a NULL argument or an unsupported combination. */
+sw_status sw_set_tuning(sw_ctx *ctx, const sw_tuning *tuning);
+/* The tuning sw_step will use, with defaults resolved. */
+sw_status sw_get_tuning(const sw_ctx *ctx, sw_tuning *out);
+
+/* Pick the fastest launch shape for this context by timing candidates on the
+ * stream with the caller's state (steps_per_trial >= 1 steps each), then set
+ * it.  buf[cur], its halo and the context's time/flags are saved first and
+ * restored afterwards, so the simulation is left where it was.  Allocates
+ * (and frees) a temporary copy of one buffer of device memory.  If
+ * cache_path is non-NULL, a cached choice for the same (GPU, dtype, scheme,
+ * grid) is used without timing, and new choices are appended there.
+ * best may be NULL.  Synchronises the stream.
+ * Errors: SW_EINVAL, SW_ENOMEM, SW_EHIP, SW_ENOTSUP (no candidate ran). */
+sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per_trial, const char *cache_path, void *stream,
+                      sw_tuning *best);
 
 const char *sw_strerror(sw_status status);
 const char *sw_last_error_detail(void);

@@ -18,8 +18,8 @@ struct sw_ctx {
     double g, dx, dy;
     sw_layout layout;
     int device;
-    int variant;
-    SwScalars *sc;   // device
+    sw_tuning tuning;   // as set by the caller (zero = default)
+    SwScalars *sc;      // device
 };
 
 namespace {
@@ -116,6 +116,17 @@ sw_status use_device(const sw_ctx *ctx) {
 
 }  // namespace
 
+sw_status sw_ctx_describe(const sw_ctx *ctx, sw_grid *grid, sw_opts *opts, sw_layout *layout, void **scalars,
+                          size_t *scalars_bytes) {
+    if (!ctx) return fail(SW_EINVAL, "NULL context");
+    *grid = ctx->grid;
+    *opts = ctx->opts;
+    *layout = ctx->layout;
+    *scalars = ctx->sc;
+    *scalars_bytes = sizeof(SwScalars);
+    return use_device(ctx);
+}
+
 extern "C" {
 
 const char *sw_strerror(sw_status s) {
@@ -174,7 +185,7 @@ sw_status sw_create(sw_grid grid, sw_halo halo, double g, double dx, const sw_op
     c->dx = dx;
     c->dy = dy;
     c->layout = lay;
-    c->variant = 0;
+    c->tuning = sw_tuning{0, 0, 0, 0};
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipMalloc((void **)&c->sc, sizeof(SwScalars));
     if (e == hipSuccess) e = hipMemset(c->sc, 0, sizeof(SwScalars));
@@ -203,10 +214,52 @@ sw_status sw_get_layout(const sw_ctx *ctx, sw_layout *out) {
     return SW_OK;
 }
 
+namespace {
+// Resolve defaults; returns SW_OK or an error for unsupported settings.
+sw_status resolve_tuning(const sw_ctx *ctx, const sw_tuning &in, SwTuning *out) {
+    int variant = in.variant;
+    if (variant < 0 || variant > 2) return fail(SW_EINVAL, "tuning: unknown variant %d", variant);
+    if (variant == 0) variant = ctx->opts.scheme == SW_SCHEME_PAPER ? 2 : 1;
+    if (variant == 2 && ctx->opts.scheme != SW_SCHEME_PAPER)
+        return fail(SW_ENOTSUP, "tuning: the fused kernel implements the paper scheme only");
+    out->variant = variant;
+    out->vec = in.vec ? in.vec : sw_fused_default_vec((int)ctx->opts.dtype);
+    out->rows = in.rows ? in.rows : sw_fused_default_rows(ctx->grid.nx, ctx->grid.ny, out->vec);
+    out->minw = in.occupancy;
+    if (in.rows < 0) return fail(SW_EINVAL, "tuning: rows = %d", in.rows);
+    if (variant == 2 && !sw_fused_supported((int)ctx->opts.dtype, out->vec, out->minw))
+        return fail(SW_EINVAL, "tuning: vec %d / occupancy %d not available for this dtype", out->vec, out->minw);
+    return SW_OK;
+}
+}  // namespace
+
 sw_status sw_set_variant(sw_ctx *ctx, int32_t variant) {
     if (!ctx) return fail(SW_EINVAL, "set_variant: NULL context");
     if (variant < 0 || variant > 2) return fail(SW_EINVAL, "set_variant: unknown variant %d", variant);
-    ctx->variant = variant;
+    sw_tuning t = ctx->tuning;
+    t.variant = variant;
+    SwTuning r;
+    sw_status st = resolve_tuning(ctx, t, &r);
+    if (st != SW_OK && st != SW_ENOTSUP) return st;
+    ctx->tuning = t;
+    return SW_OK;
+}
+
+sw_status sw_set_tuning(sw_ctx *ctx, const sw_tuning *tuning) {
+    if (!ctx || !tuning) return fail(SW_EINVAL, "set_tuning: NULL argument");
+    SwTuning r;
+    sw_status st = resolve_tuning(ctx, *tuning, &r);
+    if (st != SW_OK) return st;
+    ctx->tuning = *tuning;
+    return SW_OK;
+}
+
+sw_status sw_get_tuning(const sw_ctx *ctx, sw_tuning *out) {
+    if (!ctx || !out) return fail(SW_EINVAL, "get_tuning: NULL argument");
+    SwTuning r;
+    sw_status st = resolve_tuning(ctx, ctx->tuning, &r);
+    if (st != SW_OK) return st;
+    *out = sw_tuning{r.variant, r.rows, r.vec, r.minw};
     return SW_OK;
 }
 
@@ -228,10 +281,8 @@ sw_status sw_step(sw_ctx *ctx, sw_state *state, int32_t nsteps, void *stream) {
     if (nsteps == 0) return SW_OK;
     if ((st = use_device(ctx)) != SW_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    int variant = ctx->variant;
-    if (variant == 0) variant = ctx->opts.scheme == SW_SCHEME_PAPER ? 2 : 1;
-    if (variant == 2 && ctx->opts.scheme != SW_SCHEME_PAPER)
-        return fail(SW_ENOTSUP, "step: the fused kernel implements the paper scheme only");
+    SwTuning tun;
+    if ((st = resolve_tuning(ctx, ctx->tuning, &tun)) != SW_OK) return st;
     SW_HIP(sw_launch_reset(ctx->sc, 0, s));
     SwLaunch a = launch_of(ctx, state, state->cur);
     SW_HIP(sw_launch_prologue(a, s));
@@ -239,7 +290,7 @@ sw_status sw_step(sw_ctx *ctx, sw_state *state, int32_t nsteps, void *stream) {
     for (int n = 0; n < nsteps; ++n) {
         SwLaunch b = launch_of(ctx, state, cur);
         b.step = n;
-        SW_HIP(sw_launch_step(b, variant, s));
+        SW_HIP(sw_launch_step(b, tun, s));
         cur ^= 1;
     }
     state->cur = cur;

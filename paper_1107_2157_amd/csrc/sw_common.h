@@ -84,28 +84,43 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// dt of step a.step: fixed, or cfl * min(dx, dy) / (max speed of U^n).
-__device__ __forceinline__ double step_dt(const SwLaunch &a) {
-    if (a.dt_fixed > 0) return a.dt_fixed;
-    double s = __longlong_as_double((long long)a.sc->smax[a.step % 3]);
-    return a.cfl * fmin(a.dx, a.dy) / s;
+// Max over the 64 stripes of ring slot `slot`.  Called by all 64 lanes of a
+// wave in uniform control flow; every lane gets the result.
+__device__ __forceinline__ double read_smax(const SwScalars *sc, int slot) {
+    return wave_max(__longlong_as_double((long long)sc->smax[slot][threadIdx.x & 63]));
 }
 
-// End of a step kernel: every wave max-reduces its cells' signal speeds into
-// the next ring slot and raises the sticky flag if any of its cells broke;
-// the first thread of the grid clears the slot after next and advances time.
-__device__ __forceinline__ void step_epilogue(const SwLaunch &a, double smax, bool bad, double dt, bool first_thread) {
+// dt of step a.step: fixed, or cfl * min(dx, dy) / (max speed of U^n).
+// Wave-wide (all 64 lanes, uniform control flow).
+__device__ __forceinline__ double step_dt(const SwLaunch &a) {
+    if (a.dt_fixed > 0) return a.dt_fixed;
+    return a.cfl * fmin(a.dx, a.dy) / read_smax(a.sc, a.step % 3);
+}
+
+// Wave-wide: max-reduce the lanes' signal speeds into stripe `stripe` of
+// ring slot `slot` and raise the sticky flag if any lane saw a broken cell.
+__device__ __forceinline__ void reduce_speed(SwScalars *sc, int slot, int stripe, double smax, bool bad) {
     smax = wave_max(smax);
     unsigned long long anybad = __ballot(bad);
     if ((threadIdx.x & 63) == 0) {
-        atomicMax(&a.sc->smax[(a.step + 1) % 3], (unsigned long long)__double_as_longlong(smax));
-        if (anybad) atomicOr(&a.sc->unstable, 1u);
+        atomicMax(&sc->smax[slot][stripe & (kStripes - 1)], (unsigned long long)__double_as_longlong(smax));
+        if (anybad) atomicOr(&sc->unstable, 1u);
     }
-    if (first_thread) {
-        atomicExch(&a.sc->smax[(a.step + 2) % 3], 0ull);
-        a.sc->t += dt;
-        a.sc->last_dt = dt;
-        a.sc->steps += 1;
+}
+
+// End of a step kernel (wave-wide): reduce this wave's speeds into the next
+// ring slot; the grid's first wave clears the slot after next and advances
+// the simulated time.
+__device__ __forceinline__ void step_epilogue(const SwLaunch &a, double smax, bool bad, double dt, bool first_wave,
+                                              int stripe) {
+    reduce_speed(a.sc, (a.step + 1) % 3, stripe, smax, bad);
+    if (first_wave) {
+        atomicExch(&a.sc->smax[(a.step + 2) % 3][threadIdx.x & 63], 0ull);
+        if ((threadIdx.x & 63) == 0) {
+            a.sc->t += dt;
+            a.sc->last_dt = dt;
+            a.sc->steps += 1;
+        }
     }
 }
 

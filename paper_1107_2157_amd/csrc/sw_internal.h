@@ -4,12 +4,15 @@
 #include <cstdint>
 
 // Device-resident scalars of one solver context.
-//  smax[3]  ring of max-signal-speed slots, as the bit pattern of a
-//           non-negative double (so unsigned max == double max).  Step n
-//           reads slot n%3, max-reduces U^{n+1} into slot (n+1)%3 and clears
-//           slot (n+2)%3 for step n+1.
+//  smax[3][64]  ring of max-signal-speed slots, each striped over 64 words
+//           (waves spread their atomics over the stripes; a reader takes the
+//           max of all 64), as the bit pattern of a non-negative double (so
+//           unsigned max == double max).  Step n reads ring slot n%3,
+//           max-reduces U^{n+1} into slot (n+1)%3 and clears slot (n+2)%3
+//           for step n+1.
+constexpr int kStripes = 64;
 struct SwScalars {
-    unsigned long long smax[3];
+    unsigned long long smax[3][kStripes];
     double t;                 // simulated time
     double last_dt;           // dt of the last step
     long long steps;          // steps taken
@@ -38,5 +41,15 @@ hipError_t sw_launch_reset(SwScalars *sc, int clear_time, hipStream_t s);
 // signal speed into slot 0.
 hipError_t sw_launch_prologue(const SwLaunch &a, hipStream_t s);
 hipError_t sw_launch_fill_halo(const SwLaunch &a, hipStream_t s);
-// variant: 1 = per-cell baseline, 2 = fused row-marching kernel.
-hipError_t sw_launch_step(const SwLaunch &a, int variant, hipStream_t s);
+// Tuning of a step launch.
+struct SwTuning {
+    int variant;     // 1 per-cell baseline, 2 fused
+    int rows;        // fused: rows per tile
+    int vec;         // fused: cells per lane
+    int minw;        // fused: register budget as waves per SIMD (0 = compiler's choice)
+};
+hipError_t sw_launch_step(const SwLaunch &a, const SwTuning &t, hipStream_t s);
+hipError_t sw_launch_fused_cfg(const SwLaunch &a, int rows, int vec, int minw, hipStream_t s);
+int sw_fused_default_rows(int nx, int ny, int vec);
+int sw_fused_default_vec(int dtype);
+bool sw_fused_supported(int dtype, int vec, int minw);

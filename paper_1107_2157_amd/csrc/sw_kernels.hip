@@ -7,10 +7,8 @@ using namespace sw;
 namespace {
 
 __global__ void k_reset(SwScalars *sc, int clear_time) {
+    if (threadIdx.x < 3 * kStripes) sc->smax[threadIdx.x / kStripes][threadIdx.x % kStripes] = 0ull;
     if (threadIdx.x == 0) {
-        sc->smax[0] = 0ull;
-        sc->smax[1] = 0ull;
-        sc->smax[2] = 0ull;
         if (clear_time) {
             sc->t = 0.0;
             sc->last_dt = 0.0;
@@ -41,12 +39,7 @@ __global__ __launch_bounds__(256) void k_prologue(SwLaunch a) {
         if (i == 0 || i == nx - 1 || j == 0 || j == ny - 1)
             write_ghosts(P, a.pitch, nx, ny, a.bc_x, a.bc_y, i, j, c);
     }
-    smax = wave_max(smax);
-    unsigned long long anybad = __ballot(bad);
-    if ((threadIdx.x & 63) == 0) {
-        atomicMax(&a.sc->smax[0], (unsigned long long)__double_as_longlong(smax));
-        if (anybad) atomicOr(&a.sc->unstable, 1u);
-    }
+    reduce_speed(a.sc, 0, (int)(blockIdx.x * 4 + (threadIdx.x >> 6)), smax, bad);
 }
 
 // Halo only: one thread per perimeter cell (corner cells appear twice and
@@ -69,11 +62,11 @@ __global__ __launch_bounds__(256) void k_fill_halo(SwLaunch a) {
 
 // Baseline step: one thread per interior cell, neighbours read straight from
 // global memory, each face computed by both cells that share it.  64 x 4
-// threads per block.
+// threads per block, each thread doing CELL_ROWS cells 4 rows apart.
+constexpr int CELL_ROWS = 4;
 template <typename T, int TRANS>
 __global__ __launch_bounds__(256) void k_step_cell(SwLaunch a) {
     const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
     const double dt = step_dt(a);
     const T k = (T)(0.5 * a.g), g = (T)a.g;
     const T lx = (T)(0.5 * dt / a.dx), ly = (T)(0.5 * dt / a.dy);
@@ -84,7 +77,9 @@ __global__ __launch_bounds__(256) void k_step_cell(SwLaunch a) {
     const int64_t pitch = a.pitch;
     double smax = 0.0;
     bool bad = false;
-    if (i < a.nx && j < a.ny) {
+    for (int rr = 0; rr < CELL_ROWS; ++rr) {
+        const int j = (blockIdx.y * CELL_ROWS + rr) * 4 + (threadIdx.x >> 6);
+        if (!(i < a.nx && j < a.ny)) continue;
         auto ld = [&](int di, int dj) {
             int64_t off = (int64_t)(j + dj) * pitch + (i + di);
             return U3<T>{I[0][off], I[1][off], I[2][off]};
@@ -113,14 +108,15 @@ __global__ __launch_bounds__(256) void k_step_cell(SwLaunch a) {
         O[0][off] = r.h; O[1][off] = r.p; O[2][off] = r.q;
         write_ghosts(O, pitch, a.nx, a.ny, a.bc_x, a.bc_y, i, j, r);
         T sp = signal_speed(r, g);
-        bad = !(sp <= finite_max<T>());
-        smax = (double)sp;
+        bad |= !(sp <= finite_max<T>());
+        smax = fmax(smax, (double)sp);
     }
-    step_epilogue(a, smax, bad, dt, blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0);
+    step_epilogue(a, smax, bad, dt, blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 64,
+                  (int)((blockIdx.y * gridDim.x + blockIdx.x) * 4 + (threadIdx.x >> 6)));
 }
 
 template <typename T> hipError_t launch_step_cell(const SwLaunch &a, hipStream_t s) {
-    dim3 grid((a.nx + 63) / 64, (a.ny + 3) / 4);
+    dim3 grid((a.nx + 63) / 64, (a.ny + 4 * CELL_ROWS - 1) / (4 * CELL_ROWS));
     if (a.scheme) k_step_cell<T, 1><<<grid, 256, 0, s>>>(a);
     else k_step_cell<T, 0><<<grid, 256, 0, s>>>(a);
     return hipGetLastError();
@@ -128,10 +124,8 @@ template <typename T> hipError_t launch_step_cell(const SwLaunch &a, hipStream_t
 
 }  // namespace
 
-hipError_t sw_launch_fused(const SwLaunch &a, hipStream_t s);
-
 hipError_t sw_launch_reset(SwScalars *sc, int clear_time, hipStream_t s) {
-    k_reset<<<1, 64, 0, s>>>(sc, clear_time);
+    k_reset<<<1, 256, 0, s>>>(sc, clear_time);
     return hipGetLastError();
 }
 
@@ -152,7 +146,7 @@ hipError_t sw_launch_fill_halo(const SwLaunch &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t sw_launch_step(const SwLaunch &a, int variant, hipStream_t s) {
-    if (variant == 2) return sw_launch_fused(a, s);
+hipError_t sw_launch_step(const SwLaunch &a, const SwTuning &t, hipStream_t s) {
+    if (t.variant == 2) return sw_launch_fused_cfg(a, t.rows, t.vec, t.minw, s);
     return a.dtype ? launch_step_cell<double>(a, s) : launch_step_cell<float>(a, s);
 }

@@ -1,0 +1,173 @@
+// Autotuner of the step kernel's launch shape.
+//
+// Candidates (fused kernel): cells per lane x register budget x rows per
+// tile.  Each candidate is timed with HIP events on the caller's stream over
+// a few steps of the caller's own state; the state (buf[cur] with its halo)
+// and the context's time scalars are saved first and restored before every
+// trial and at the end, so tuning leaves the simulation where it was.  Every
+// fused shape produces bitwise identical cells, so the choice affects speed
+// only.  Results are cached in a text file, one line per key
+//   <arch>:<CUs>:<dtype>:<scheme>:<nx>x<ny> variant rows vec occupancy us_per_step
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/sw.h"
+#include "sw_internal.h"
+
+namespace {
+
+std::string tune_key(sw_dtype dtype, sw_scheme scheme, int nx, int ny, int device) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    int cus = 0;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        auto colon = arch.find(':');
+        if (colon != std::string::npos) arch = arch.substr(0, colon);
+        cus = prop.multiProcessorCount;
+    }
+    std::ostringstream k;
+    k << arch << ":" << cus << ":" << (dtype == SW_F64 ? "f64" : "f32") << ":" << (int)scheme << ":" << nx << "x"
+      << ny;
+    return k.str();
+}
+
+bool cache_lookup(const char *path, const std::string &key, sw_tuning *t) {
+    if (!path || !*path) return false;
+    std::ifstream f(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string k;
+        sw_tuning c{};
+        double us;
+        if (is >> k >> c.variant >> c.rows >> c.vec >> c.occupancy >> us && k == key) {
+            *t = c;       // the last entry for a key wins
+            found = true;
+        }
+    }
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, const sw_tuning &t, double us) {
+    if (!path || !*path) return;
+    std::ofstream f(path, std::ios::app);
+    f << key << " " << t.variant << " " << t.rows << " " << t.vec << " " << t.occupancy << " " << us << "\n";
+}
+
+}  // namespace
+
+// Context accessor (sw_api.cpp).
+sw_status sw_ctx_describe(const sw_ctx *ctx, sw_grid *grid, sw_opts *opts, sw_layout *layout, void **scalars,
+                          size_t *scalars_bytes);
+
+extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per_trial, const char *cache_path,
+                                 void *stream, sw_tuning *best_out) {
+    sw_grid grid;
+    sw_opts opts;
+    sw_layout lay;
+    void *scal = nullptr;
+    size_t scal_bytes = 0;
+    sw_status st = sw_ctx_describe(ctx, &grid, &opts, &lay, &scal, &scal_bytes);
+    if (st != SW_OK) return st;
+    if (!state || steps_per_trial < 1) return SW_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return SW_EHIP;
+    const std::string key = tune_key(opts.dtype, opts.scheme, grid.nx, grid.ny, device);
+
+    sw_tuning best{};
+    if (cache_lookup(cache_path, key, &best) && sw_set_tuning(ctx, &best) == SW_OK) {
+        if (best_out) sw_get_tuning(ctx, best_out);
+        return SW_OK;
+    }
+
+    std::vector<sw_tuning> cands;
+    if (opts.scheme != SW_SCHEME_PAPER) {
+        cands.push_back(sw_tuning{1, 0, 0, 0});
+    } else {
+        const int vecs_f32[] = {2, 4}, vecs_f64[] = {1, 2};
+        const int *vecs = opts.dtype == SW_F64 ? vecs_f64 : vecs_f32;
+        const int rows_list[] = {8, 16, 32, 64, 128};
+        const int occs[] = {0, 3, 4};
+        for (int vi = 0; vi < 2; ++vi)
+            for (int occ : occs)
+                for (int rows : rows_list) cands.push_back(sw_tuning{2, rows, vecs[vi], occ});
+    }
+
+    // save buf[cur] (whole planes, halo included) and the time scalars
+    const size_t plane_bytes = (size_t)lay.plane_elems * (size_t)lay.elem_bytes;
+    void *backup = nullptr, *scal_backup = nullptr;
+    if (hipMalloc(&backup, 3 * plane_bytes) != hipSuccess) return SW_ENOMEM;
+    if (hipMalloc(&scal_backup, scal_bytes) != hipSuccess) {
+        (void)hipFree(backup);
+        return SW_ENOMEM;
+    }
+    const int cur0 = state->cur;
+    auto save = [&]() -> hipError_t {
+        for (int k = 0; k < 3; ++k) {
+            hipError_t e = hipMemcpyAsync((char *)backup + k * plane_bytes, state->plane[cur0][k], plane_bytes,
+                                          hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipMemcpyAsync(scal_backup, scal, scal_bytes, hipMemcpyDeviceToDevice, s);
+    };
+    auto restore = [&]() -> hipError_t {
+        state->cur = cur0;
+        for (int k = 0; k < 3; ++k) {
+            hipError_t e = hipMemcpyAsync(state->plane[cur0][k], (char *)backup + k * plane_bytes, plane_bytes,
+                                          hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipMemcpyAsync(scal, scal_backup, scal_bytes, hipMemcpyDeviceToDevice, s);
+    };
+
+    sw_tuning prev{};
+    sw_get_tuning(ctx, &prev);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double best_us = 1e300;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    if (he == hipSuccess) he = save();
+    for (size_t i = 0; i < cands.size() && he == hipSuccess; ++i) {
+        if (sw_set_tuning(ctx, &cands[i]) != SW_OK) continue;
+        if ((he = restore()) != hipSuccess) break;
+        if (sw_step(ctx, state, 1, stream) != SW_OK) continue;   // warm (code load, caches)
+        if ((he = hipEventRecord(e0, s)) != hipSuccess) break;
+        if (sw_step(ctx, state, steps_per_trial, stream) != SW_OK) continue;
+        if ((he = hipEventRecord(e1, s)) != hipSuccess) break;
+        if ((he = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.f;
+        if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        double us = 1000.0 * ms / steps_per_trial;
+        if (us < best_us) {
+            best_us = us;
+            best = cands[i];
+        }
+    }
+    if (he == hipSuccess) he = restore();
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(backup);
+    (void)hipFree(scal_backup);
+    if (he != hipSuccess) {
+        sw_set_tuning(ctx, &prev);
+        return SW_EHIP;
+    }
+    if (best_us >= 1e300) {
+        sw_set_tuning(ctx, &prev);
+        return SW_ENOTSUP;
+    }
+    sw_set_tuning(ctx, &best);
+    cache_store(cache_path, key, best, best_us);
+    if (best_out) sw_get_tuning(ctx, best_out);
+    return SW_OK;
+}

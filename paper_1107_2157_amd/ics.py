@@ -102,6 +102,20 @@ def bumps_height(nx: int, ny: int, bumps: list[Bump], periodic: bool,
     return h
 
 
+def bumps_band(nx: int, ny: int, row0: int, nrows: int, seed: int, periodic: bool,
+               count: int | None = None, dx: float = 1.0, dy: float = 1.0, device="cpu"):
+    """Rows ``[row0, row0 + nrows)`` of the ``(ny, nx)`` bump state (same
+    bumps as the full grid), for runs on a horizontal band of it."""
+    bumps = draw_bumps(seed, nx, ny, dx, dy, count)
+    h = torch.ones((nrows, nx), dtype=torch.float64, device=device)
+    for b in bumps:
+        gx = _axis_gauss(nx, dx, b.cx, b.sigma, periodic, device)
+        gy = _axis_gauss(ny, dy, b.cy, b.sigma, periodic, device)[row0:row0 + nrows]
+        h.addr_(gy, gx, alpha=b.amp)
+    z = torch.zeros_like(h)
+    return h, z, z.clone()
+
+
 def bumps_state(nx: int, ny: int, seed: int, periodic: bool, count: int | None = None,
                 dx: float = 1.0, dy: float = 1.0, device="cpu"):
     """Gaussian-bump still-water state ``(h, hu, hv)``."""

@@ -55,6 +55,14 @@ class Layout(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("rows", ctypes.c_int32), ("vec", ctypes.c_int32),
+                ("occupancy", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class State(ctypes.Structure):
     _fields_ = [("plane", (ctypes.c_void_p * 3) * 2), ("cur", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
@@ -75,6 +83,10 @@ SIGNATURES = {
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "sw_reset_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "sw_set_variant": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "sw_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
+    "sw_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
+    "sw_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(State), ctypes.c_int32, ctypes.c_char_p,
+                                   ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "sw_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sw_last_error_detail": (ctypes.c_char_p, []),
 }
@@ -174,6 +186,21 @@ class Solver:
     # ---- calls -----------------------------------------------------------
     def set_variant(self, variant: int):
         check(lib().sw_set_variant(self.ctx, variant), "sw_set_variant")
+
+    def set_tuning(self, variant=0, rows=0, vec=0, occupancy=0):
+        check(lib().sw_set_tuning(self.ctx, ctypes.byref(Tuning(variant, rows, vec, occupancy))), "sw_set_tuning")
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        check(lib().sw_get_tuning(self.ctx, ctypes.byref(t)), "sw_get_tuning")
+        return t.as_dict()
+
+    def autotune(self, steps_per_trial: int = 5, cache_path: str | None = None, stream=None) -> dict:
+        t = Tuning()
+        path = cache_path.encode() if cache_path else None
+        check(lib().sw_autotune(self.ctx, ctypes.byref(self.state), steps_per_trial, path,
+                                _stream_handle(stream), ctypes.byref(t)), "sw_autotune")
+        return t.as_dict()
 
     def fill_halo(self, stream=None):
         check(lib().sw_fill_halo(self.ctx, ctypes.byref(self.state), _stream_handle(stream)), "sw_fill_halo")
