@@ -150,6 +150,8 @@ def main():
     ap.add_argument("--no-also", action="store_true", help="skip the secondary 4096^2 FP32/FP64 runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "sw_tune_cache.txt"))
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 3 GiB device-to-device copy (counter calibration) and exit")
     ap.add_argument("--tuning", default=None,
                     help="fixed launch shape 'variant,rows,vec,occupancy' instead of the autotuner")
     args = ap.parse_args()
@@ -159,6 +161,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        # a plain copy of known size: 3 GiB read + 3 GiB written per dispatch
+        a = torch.ones(3 * 2 ** 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(6):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4}))
+        return
     from paper_1107_2157_amd import ics, sw
     sw.lib()    # fails loudly if the HIP library is not built
     os.makedirs(os.path.dirname(args.tune_cache), exist_ok=True)
