@@ -149,7 +149,9 @@ def main():
     ap.add_argument("--workload", default="swe16384-f32-periodic", choices=sorted(WORKLOADS))
     ap.add_argument("--no-also", action="store_true", help="skip the secondary 4096^2 FP32/FP64 runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "sw_tune_cache.txt"))
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1107_2157_amd", "tune_cache_gfx950.txt"),
+                    help="autotuner cache (launch shapes found by sw_autotune on MI355X; missing keys are tuned "
+                         "and appended)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 3 GiB device-to-device copy (counter calibration) and exit")
     ap.add_argument("--tuning", default=None,
@@ -172,7 +174,6 @@ def main():
         return
     from paper_1107_2157_amd import ics, sw
     sw.lib()    # fails loudly if the HIP library is not built
-    os.makedirs(os.path.dirname(args.tune_cache), exist_ok=True)
 
     steps = args.steps or WORKLOADS[args.workload][4]
     fixed = tuple(int(x) for x in args.tuning.split(",")) if args.tuning else None
@@ -216,7 +217,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_step_fused", "kernel_us": main_run["kernel_us"],
                      "alg_bytes_per_launch": main_run["alg_bytes_per_launch"],
-                     "copy_gbs_measured": copy_bw, "frac_of_copy": achieved / copy_bw},
+                     "torch_copy_gbs": copy_bw},
         "also": also,
     }
     if not args.no_cpu:

@@ -151,6 +151,8 @@ typedef struct {
     int32_t rows;       /* fused: rows per tile (>= 1) */
     int32_t vec;        /* fused: cells per lane; SW_F32: 2 or 4, SW_F64: 1 or 2 */
     int32_t occupancy;  /* fused: register budget in waves per SIMD: 0 (compiler's choice), 3 or 4 */
+    int32_t prefetch;   /* fused: rows loaded ahead of the row being updated: 1, 2 or 3 */
+    int32_t order;      /* fused: tile order: 0 row-block-major per XCD, 1 vertically grouped per XCD, 2 plain */
 } sw_tuning;
 
 /* Errors: SW_EINVAL for a NULL argument or an unsupported combination. */

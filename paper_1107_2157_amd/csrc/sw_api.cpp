@@ -185,7 +185,7 @@ sw_status sw_create(sw_grid grid, sw_halo halo, double g, double dx, const sw_op
     c->dx = dx;
     c->dy = dy;
     c->layout = lay;
-    c->tuning = sw_tuning{0, 0, 0, 0};
+    c->tuning = sw_tuning{0, 0, 0, 0, 0, 0};
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipMalloc((void **)&c->sc, sizeof(SwScalars));
     if (e == hipSuccess) e = hipMemset(c->sc, 0, sizeof(SwScalars));
@@ -226,9 +226,13 @@ sw_status resolve_tuning(const sw_ctx *ctx, const sw_tuning &in, SwTuning *out) 
     out->vec = in.vec ? in.vec : sw_fused_default_vec((int)ctx->opts.dtype);
     out->rows = in.rows ? in.rows : sw_fused_default_rows(ctx->grid.nx, ctx->grid.ny, out->vec);
     out->minw = in.occupancy;
+    out->pd = in.prefetch ? in.prefetch : 2;
+    out->order = in.order;
+    if (in.order < 0 || in.order > 2) return fail(SW_EINVAL, "tuning: order = %d", in.order);
     if (in.rows < 0) return fail(SW_EINVAL, "tuning: rows = %d", in.rows);
-    if (variant == 2 && !sw_fused_supported((int)ctx->opts.dtype, out->vec, out->minw))
-        return fail(SW_EINVAL, "tuning: vec %d / occupancy %d not available for this dtype", out->vec, out->minw);
+    if (variant == 2 && !sw_fused_supported((int)ctx->opts.dtype, out->vec, out->minw, out->pd))
+        return fail(SW_EINVAL, "tuning: vec %d / occupancy %d / prefetch %d not available for this dtype", out->vec,
+                    out->minw, out->pd);
     return SW_OK;
 }
 }  // namespace
@@ -259,7 +263,7 @@ sw_status sw_get_tuning(const sw_ctx *ctx, sw_tuning *out) {
     SwTuning r;
     sw_status st = resolve_tuning(ctx, ctx->tuning, &r);
     if (st != SW_OK) return st;
-    *out = sw_tuning{r.variant, r.rows, r.vec, r.minw};
+    *out = sw_tuning{r.variant, r.rows, r.vec, r.minw, r.pd, r.order};
     return SW_OK;
 }
 

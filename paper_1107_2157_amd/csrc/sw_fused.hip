@@ -32,41 +32,62 @@ template <typename T> __device__ __forceinline__ T fast_sqrt(T x);
 template <> __device__ __forceinline__ float fast_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <> __device__ __forceinline__ double fast_sqrt<double>(double x) { return sqrt(x); }
 
-template <typename T, int VEC> __device__ __forceinline__ void vload(const T *p, T o[VEC]);
-template <> __device__ __forceinline__ void vload<float, 4>(const float *p, float o[4]) {
-    float4 v = *reinterpret_cast<const float4 *>(p);
-    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
-}
-template <> __device__ __forceinline__ void vload<float, 2>(const float *p, float o[2]) {
-    float2 v = *reinterpret_cast<const float2 *>(p);
-    o[0] = v.x; o[1] = v.y;
-}
-template <> __device__ __forceinline__ void vload<double, 2>(const double *p, double o[2]) {
-    double2 v = *reinterpret_cast<const double2 *>(p);
-    o[0] = v.x; o[1] = v.y;
-}
-template <> __device__ __forceinline__ void vload<double, 4>(const double *p, double o[4]) {
-    double2 v = *reinterpret_cast<const double2 *>(p);
-    double2 w = *reinterpret_cast<const double2 *>(p + 2);
-    o[0] = v.x; o[1] = v.y; o[2] = w.x; o[3] = w.y;
+// Buffer (V#) access: a scalar resource descriptor per plane and tile, a
+// loop-invariant 32-bit byte offset per lane (VGPR) and the row's byte
+// offset (SGPR).  Marching to the next row changes only the scalar offset.
+// Out-of-range accesses are bounds-checked by the hardware (loads return 0,
+// stores are dropped).
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;   // GFX9 descriptor dword 3 (32-bit data format)
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kRsrcWord3);
 }
 
-template <> __device__ __forceinline__ void vload<double, 1>(const double *p, double o[1]) { o[0] = *p; }
+template <typename T, int VEC> __device__ __forceinline__ void bload(rsrc_t r, unsigned vo, unsigned so, T o[VEC]);
+template <> __device__ __forceinline__ void bload<float, 2>(rsrc_t r, unsigned vo, unsigned so, float o[2]) {
+    u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+    o[0] = __uint_as_float(v.x); o[1] = __uint_as_float(v.y);
+}
+template <> __device__ __forceinline__ void bload<float, 4>(rsrc_t r, unsigned vo, unsigned so, float o[4]) {
+    u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+    o[0] = __uint_as_float(v.x); o[1] = __uint_as_float(v.y); o[2] = __uint_as_float(v.z); o[3] = __uint_as_float(v.w);
+}
+template <> __device__ __forceinline__ void bload<double, 1>(rsrc_t r, unsigned vo, unsigned so, double o[1]) {
+    u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+    o[0] = __hiloint2double((int)v.y, (int)v.x);
+}
+template <> __device__ __forceinline__ void bload<double, 2>(rsrc_t r, unsigned vo, unsigned so, double o[2]) {
+    u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+    o[0] = __hiloint2double((int)v.y, (int)v.x); o[1] = __hiloint2double((int)v.w, (int)v.z);
+}
+__device__ __forceinline__ float bload1(rsrc_t r, unsigned vo, unsigned so, float) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+}
+__device__ __forceinline__ double bload1(rsrc_t r, unsigned vo, unsigned so, double) {
+    u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+    return __hiloint2double((int)v.y, (int)v.x);
+}
 
-template <typename T, int VEC> __device__ __forceinline__ void vstore(T *p, const T o[VEC]);
-template <> __device__ __forceinline__ void vstore<double, 1>(double *p, const double o[1]) { *p = o[0]; }
-template <> __device__ __forceinline__ void vstore<float, 4>(float *p, const float o[4]) {
-    *reinterpret_cast<float4 *>(p) = make_float4(o[0], o[1], o[2], o[3]);
+template <typename T, int VEC> __device__ __forceinline__ void bstore(rsrc_t r, unsigned vo, unsigned so, const T o[VEC]);
+template <> __device__ __forceinline__ void bstore<float, 2>(rsrc_t r, unsigned vo, unsigned so, const float o[2]) {
+    u32x2 v = {__float_as_uint(o[0]), __float_as_uint(o[1])};
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, so, 0);
 }
-template <> __device__ __forceinline__ void vstore<float, 2>(float *p, const float o[2]) {
-    *reinterpret_cast<float2 *>(p) = make_float2(o[0], o[1]);
+template <> __device__ __forceinline__ void bstore<float, 4>(rsrc_t r, unsigned vo, unsigned so, const float o[4]) {
+    u32x4 v = {__float_as_uint(o[0]), __float_as_uint(o[1]), __float_as_uint(o[2]), __float_as_uint(o[3])};
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, vo, so, 0);
 }
-template <> __device__ __forceinline__ void vstore<double, 2>(double *p, const double o[2]) {
-    *reinterpret_cast<double2 *>(p) = make_double2(o[0], o[1]);
+template <> __device__ __forceinline__ void bstore<double, 1>(rsrc_t r, unsigned vo, unsigned so, const double o[1]) {
+    u32x2 v = {(unsigned)__double2loint(o[0]), (unsigned)__double2hiint(o[0])};
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, so, 0);
 }
-template <> __device__ __forceinline__ void vstore<double, 4>(double *p, const double o[4]) {
-    *reinterpret_cast<double2 *>(p) = make_double2(o[0], o[1]);
-    *reinterpret_cast<double2 *>(p + 2) = make_double2(o[2], o[3]);
+template <> __device__ __forceinline__ void bstore<double, 2>(rsrc_t r, unsigned vo, unsigned so, const double o[2]) {
+    u32x4 v = {(unsigned)__double2loint(o[0]), (unsigned)__double2hiint(o[0]), (unsigned)__double2loint(o[1]),
+               (unsigned)__double2hiint(o[1])};
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, vo, so, 0);
 }
 
 // Cross-lane moves along the wave.  DPP wave_shr:1 / wave_shl:1 (GFX9
@@ -115,17 +136,31 @@ template <typename T> __device__ __forceinline__ void yface_flux(T yh, T yp, T y
 template <bool B> using bconst = std::integral_constant<bool, B>;
 
 // MINW: register budget expressed as waves per SIMD (0 = compiler's choice).
-template <typename T, int VEC, int MINW>
-__global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_step_fused(SwLaunch a, int rows, int nstrips, int ntiles) {
+// PD: rows loaded ahead of the row being processed (software pipeline depth).
+template <typename T, int VEC, int MINW, int PD>
+__global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_step_fused(SwLaunch a, int rows, int nstrips, int nrb,
+                                                                           int order) {
     constexpr int W = 64 * VEC;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // XCD-aware tile order: blocks are dispatched round-robin over the 8
-    // XCDs, so block b runs on XCD b % 8.  Give every XCD a contiguous run of
-    // the row-major tile sequence, so the tiles that share halo rows and edge
-    // columns meet in the same L2.
+    // Tile order.  Blocks are dispatched round-robin over the 8 XCDs (block
+    // b on XCD b % 8); orders 0 and 1 give every XCD a contiguous run of the
+    // tile sequence so that tiles sharing halo rows and edge columns meet in
+    // the same L2.  Order 0: row-block-major sequence.  Order 1: groups of 4
+    // row blocks, strip-major inside a group, so the 4 waves of a block take
+    // 4 vertically adjacent tiles of one strip.  Order 2: plain block order.
     const int per_xcd = gridDim.x >> 3;
-    const int tile = (((int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3)) << 2) + wave;
+    const int seq = order == 2 ? (int)blockIdx.x : (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+    const int tile = (seq << 2) + wave;
+    int s, rb;
+    if (order == 1) {
+        const int grp = tile / (nstrips * 4), rem = tile - grp * (nstrips * 4);
+        s = rem >> 2;
+        rb = grp * 4 + (rem & 3);
+    } else {
+        s = tile % nstrips;
+        rb = tile / nstrips;
+    }
     const double dt = step_dt(a);
     const T k = (T)(0.5 * a.g), g = (T)a.g;
     const T lx = (T)(0.5 * dt / a.dx), ly = (T)(0.5 * dt / a.dy);
@@ -135,34 +170,49 @@ __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_step_fused(SwLau
     T smax = T(0);
     bool bad = false;
 
-    if (tile < ntiles) {
-        const int s = tile % nstrips, rb = tile / nstrips;
+    if (rb < nrb) {
         const int c0 = s * W, j0 = rb * rows, j1 = min(j0 + rows, ny);
         const unsigned c = (unsigned)(c0 + VEC * lane);
         const bool in_row = (int)c <= nx;                    // the vector stays inside the row's allocation
         const bool full = (int)c + VEC <= nx;                // all VEC cells are interior
-        const unsigned ec = lane == 0 ? (unsigned)c0 : (unsigned)(c0 + W + 1);   // edge column + 1
-        const bool edge_ok = lane == 0 || (lane == 63 && c0 + W <= nx);
+        // Edge loads: lanes 0..31 read the column left of the strip, lanes
+        // 32..63 the column right of it (two addresses per instruction);
+        // lane 0 and lane 63 use them.  Past the right end of the grid the
+        // right edge is never needed and reads the left one instead.
+        const bool right_ok = c0 + W <= nx;
+        const unsigned ec = (lane < 32 || !right_ok) ? (unsigned)c0 : (unsigned)(c0 + W + 1);   // column + 1
+        // Lanes past the end of the row read the strip's first vector; their
+        // cells are never stored and never enter the CFL max.  All loads are
+        // unconditional (rows past the tile are clamped to its last row) so
+        // that the compiler can count the loads in flight exactly and keep
+        // the prefetched rows outstanding while it computes.
+        const unsigned cl = in_row ? c : (unsigned)c0;
         const T elx = lane == 0 ? lx : -lx;                  // lane 0 needs L of its edge, lane 63 needs R
         const bool tile_at_wall = s == 0 || c0 + W >= nx || j0 == 0 || j1 >= ny;
-        const T *I[3] = {(const T *)a.in[0], (const T *)a.in[1], (const T *)a.in[2]};
         T *O[3] = {(T *)a.out[0], (T *)a.out[1], (T *)a.out[2]};
+        // Descriptors of this tile: they start at cell (-1, j0 - 1) and span
+        // rows j0 - 1 .. j1; a row's byte offset is (j - j0 + 1) * pitch * size.
+        const int64_t tile_base = (int64_t)(j0 - 1) * pitch - 1;
+        const int64_t span = (int64_t)(j1 - j0 + 2) * pitch * (int64_t)sizeof(T);
+        const unsigned nrec = span > 0x7fffffff ? 0x7fffffffu : (unsigned)span;
+        const rsrc_t rin0 = make_rsrc((const T *)a.in[0] + tile_base, nrec);
+        const rsrc_t rin1 = make_rsrc((const T *)a.in[1] + tile_base, nrec);
+        const rsrc_t rin2 = make_rsrc((const T *)a.in[2] + tile_base, nrec);
+        const rsrc_t rout[3] = {make_rsrc(O[0] + tile_base, nrec), make_rsrc(O[1] + tile_base, nrec),
+                                make_rsrc(O[2] + tile_base, nrec)};
+        const unsigned row_bytes = (unsigned)(pitch * (int64_t)sizeof(T));
+        const unsigned lb = (cl + 1) * (unsigned)sizeof(T);   // lane's vector
+        const unsigned eb = ec * (unsigned)sizeof(T);         // lane's edge cell (ec is column + 1)
+        const unsigned sb = (c + 1) * (unsigned)sizeof(T);    // lane's store vector
 
         auto load_row = [&](int j, T h[VEC], T p[VEC], T q[VEC], T e[3]) {
-            const int64_t ro = (int64_t)j * pitch;
-            if (in_row) {
-                vload<T, VEC>(I[0] + ro + c, h);
-                vload<T, VEC>(I[1] + ro + c, p);
-                vload<T, VEC>(I[2] + ro + c, q);
-            } else {
-#pragma unroll
-                for (int m = 0; m < VEC; ++m) { h[m] = T(1); p[m] = T(0); q[m] = T(0); }
-            }
-            if (edge_ok) {
-                e[0] = (I[0] + ro - 1)[ec]; e[1] = (I[1] + ro - 1)[ec]; e[2] = (I[2] + ro - 1)[ec];
-            } else {
-                e[0] = T(1); e[1] = T(0); e[2] = T(0);
-            }
+            const unsigned so = (unsigned)(j - j0 + 1) * row_bytes;
+            bload<T, VEC>(rin0, lb, so, h);
+            bload<T, VEC>(rin1, lb, so, p);
+            bload<T, VEC>(rin2, lb, so, q);
+            e[0] = bload1(rin0, eb, so, T(0));
+            e[1] = bload1(rin1, eb, so, T(0));
+            e[2] = bload1(rin2, eb, so, T(0));
         };
 
         // Carried from one row to the next (lane's VEC cells):
@@ -204,8 +254,9 @@ __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_step_fused(SwLau
             if (EMIT) {
                 const int64_t ro = (int64_t)jout * pitch;
                 if (full) {
+                    const unsigned so = (unsigned)(jout - j0 + 1) * row_bytes;
 #pragma unroll
-                    for (int kk = 0; kk < 3; ++kk) vstore<T, VEC>(O[kk] + ro + c, out[kk]);
+                    for (int kk = 0; kk < 3; ++kk) bstore<T, VEC>(rout[kk], sb, so, out[kk]);
 #pragma unroll
                     for (int m = 0; m < VEC; ++m) {
                         T sp = fmax(fabs(out[1][m]), fabs(out[2][m])) * fast_rcp(out[0][m]) +
@@ -276,36 +327,42 @@ __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_step_fused(SwLau
         };
 
         // Prologue: row j0 - 1 gives B; row j0 gives G_{j0-1/2}, B and S.
-        T ah[VEC], ap[VEC], aq[VEC], ae[3];
-        T bh[VEC], bp[VEC], bq[VEC], be[3];
-        load_row(j0 - 1, ah, ap, aq, ae);
-        load_row(j0, bh, bp, bq, be);
-        row_pass(bconst<false>{}, bconst<false>{}, ah, ap, aq, ae, false, 0);
-        row_pass(bconst<true>{}, bconst<false>{}, bh, bp, bq, be, true, 0);
-        load_row(j0 + 1, ah, ap, aq, ae);
-        // March: two rows per trip so the prefetched row alternates between
-        // the register sets a and b without copies.
-        for (int j = j0; j < j1; j += 2) {
-            if (j + 2 <= j1) load_row(j + 2, bh, bp, bq, be);
-            row_pass(bconst<true>{}, bconst<true>{}, ah, ap, aq, ae, j + 1 < j1, j);
-            if (j + 1 >= j1) break;
-            if (j + 3 <= j1) load_row(j + 3, ah, ap, aq, ae);
-            row_pass(bconst<true>{}, bconst<true>{}, bh, bp, bq, be, j + 2 < j1, j + 1);
+        // Raw rows j0+1 .. j1 pass through a ring of PD + 1 register sets:
+        // row r sits in set (r - j0 - 1) % (PD + 1), loaded PD rows before
+        // it is used.
+        T rh[PD + 1][VEC], rp[PD + 1][VEC], rq[PD + 1][VEC], re[PD + 1][3];
+        load_row(j0 - 1, rh[0], rp[0], rq[0], re[0]);
+        load_row(j0, rh[1 % (PD + 1)], rp[1 % (PD + 1)], rq[1 % (PD + 1)], re[1 % (PD + 1)]);
+        row_pass(bconst<false>{}, bconst<false>{}, rh[0], rp[0], rq[0], re[0], false, 0);
+        row_pass(bconst<true>{}, bconst<false>{}, rh[1 % (PD + 1)], rp[1 % (PD + 1)], rq[1 % (PD + 1)],
+                 re[1 % (PD + 1)], true, 0);
+#pragma unroll
+        for (int u = 0; u < PD; ++u) load_row(min(j0 + 1 + u, j1), rh[u], rp[u], rq[u], re[u]);
+        for (int jb = j0; jb < j1; jb += PD + 1) {
+#pragma unroll
+            for (int u = 0; u <= PD; ++u) {
+                const int j = jb + u;          // output row; its upper neighbour j+1 is in set u
+                if (j >= j1) break;
+                const int slot = (u + PD) % (PD + 1);
+                load_row(min(j + 1 + PD, j1), rh[slot], rp[slot], rq[slot], re[slot]);
+                row_pass(bconst<true>{}, bconst<true>{}, rh[u], rp[u], rq[u], re[u], j + 1 < j1, j);
+            }
         }
     }
     step_epilogue(a, (double)smax, bad, dt, blockIdx.x == 0 && wave == 0, (int)blockIdx.x * 4 + wave);
 }
 
-template <typename T, int VEC, int MINW>
-hipError_t launch_fused_t(const SwLaunch &a, int rows, hipStream_t s) {
+template <typename T, int VEC, int MINW, int PD>
+hipError_t launch_fused_t(const SwLaunch &a, int rows, int order, hipStream_t s) {
     constexpr int W = 64 * VEC;
     const int nstrips = (a.nx + W - 1) / W;
     const int nrb = (a.ny + rows - 1) / rows;
-    const int64_t ntiles = (int64_t)nstrips * nrb;
+    // tiles covered by the grid: order 1 rounds the row blocks up to groups of 4
+    const int64_t ntiles = (int64_t)nstrips * (order == 1 ? (nrb + 3) / 4 * 4 : nrb);
     int64_t blocks = (ntiles + 3) / 4;
     blocks = (blocks + 7) / 8 * 8;
-    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    k_step_fused<T, VEC, MINW><<<(unsigned)blocks, 256, 0, s>>>(a, rows, nstrips, (int)ntiles);
+    if (blocks > 0x3fffffff) return hipErrorInvalidValue;
+    k_step_fused<T, VEC, MINW, PD><<<(unsigned)blocks, 256, 0, s>>>(a, rows, nstrips, nrb, order);
     return hipGetLastError();
 }
 
@@ -322,22 +379,31 @@ int sw_fused_default_rows(int nx, int ny, int vec) {
 
 int sw_fused_default_vec(int dtype) { return dtype ? 2 : 4; }
 
-bool sw_fused_supported(int dtype, int vec, int minw) {
-    if (minw != 0 && minw != 3 && minw != 4) return false;
-    return dtype ? (vec == 1 || vec == 2) : (vec == 2 || vec == 4);
+// The instantiated launch shapes: (dtype, cells per lane, register budget,
+// prefetch depth).
+#define SW_FUSED_SHAPES(X)                                                                      \
+    X(float, 2, 0, 1) X(float, 2, 0, 2) X(float, 2, 0, 3) X(float, 2, 3, 1) X(float, 2, 3, 2)  \
+    X(float, 2, 3, 3) X(float, 2, 4, 1) X(float, 2, 4, 2) X(float, 2, 4, 3) X(float, 4, 0, 1)  \
+    X(float, 4, 0, 2) X(float, 4, 0, 3) X(float, 4, 3, 1) X(float, 4, 3, 2)                      \
+    X(double, 1, 0, 1) X(double, 1, 0, 2) X(double, 1, 0, 3) X(double, 1, 3, 1)                 \
+    X(double, 1, 3, 2) X(double, 1, 3, 3) X(double, 1, 4, 1) X(double, 1, 4, 2)                 \
+    X(double, 1, 4, 3) X(double, 2, 0, 1) X(double, 2, 0, 2) X(double, 2, 0, 3)                 \
+    X(double, 2, 3, 1) X(double, 2, 3, 2)
+
+bool sw_fused_supported(int dtype, int vec, int minw, int pd) {
+#define SW_FUSED_SUP(T, V, M, P) \
+    if ((dtype == 1) == (sizeof(T) == 8) && vec == V && minw == M && pd == P) return true;
+    SW_FUSED_SHAPES(SW_FUSED_SUP)
+#undef SW_FUSED_SUP
+    return false;
 }
 
-hipError_t sw_launch_fused_cfg(const SwLaunch &a, int rows, int vec, int minw, hipStream_t s) {
-    if (a.scheme != 0 || rows < 1 || !sw_fused_supported(a.dtype, vec, minw)) return hipErrorInvalidValue;
-#define SW_FUSED_CASE(T, V, M) \
-    if (vec == V && minw == M) return launch_fused_t<T, V, M>(a, rows, s);
-    if (a.dtype) {
-        SW_FUSED_CASE(double, 2, 0) SW_FUSED_CASE(double, 2, 3) SW_FUSED_CASE(double, 2, 4)
-        SW_FUSED_CASE(double, 1, 0) SW_FUSED_CASE(double, 1, 3) SW_FUSED_CASE(double, 1, 4)
-    } else {
-        SW_FUSED_CASE(float, 4, 0) SW_FUSED_CASE(float, 4, 3) SW_FUSED_CASE(float, 4, 4)
-        SW_FUSED_CASE(float, 2, 0) SW_FUSED_CASE(float, 2, 3) SW_FUSED_CASE(float, 2, 4)
-    }
+hipError_t sw_launch_fused_cfg(const SwLaunch &a, int rows, int vec, int minw, int pd, int order, hipStream_t s) {
+    if (a.scheme != 0 || rows < 1 || order < 0 || order > 2) return hipErrorInvalidValue;
+#define SW_FUSED_CASE(T, V, M, P) \
+    if ((a.dtype == 1) == (sizeof(T) == 8) && vec == V && minw == M && pd == P) \
+        return launch_fused_t<T, V, M, P>(a, rows, order, s);
+    SW_FUSED_SHAPES(SW_FUSED_CASE)
 #undef SW_FUSED_CASE
     return hipErrorInvalidValue;
 }

@@ -47,9 +47,12 @@ struct SwTuning {
     int rows;        // fused: rows per tile
     int vec;         // fused: cells per lane
     int minw;        // fused: register budget as waves per SIMD (0 = compiler's choice)
+    int pd;          // fused: rows prefetched ahead
+    int order;       // fused: tile order (0 XCD row-major, 1 XCD grouped columns of 4, 2 plain)
 };
 hipError_t sw_launch_step(const SwLaunch &a, const SwTuning &t, hipStream_t s);
-hipError_t sw_launch_fused_cfg(const SwLaunch &a, int rows, int vec, int minw, hipStream_t s);
+hipError_t sw_launch_fused_cfg(const SwLaunch &a, int rows, int vec, int minw, int pd, int order,
+                               hipStream_t s);
 int sw_fused_default_rows(int nx, int ny, int vec);
 int sw_fused_default_vec(int dtype);
-bool sw_fused_supported(int dtype, int vec, int minw);
+bool sw_fused_supported(int dtype, int vec, int minw, int pd);

@@ -147,6 +147,6 @@ hipError_t sw_launch_fill_halo(const SwLaunch &a, hipStream_t s) {
 }
 
 hipError_t sw_launch_step(const SwLaunch &a, const SwTuning &t, hipStream_t s) {
-    if (t.variant == 2) return sw_launch_fused_cfg(a, t.rows, t.vec, t.minw, s);
+    if (t.variant == 2) return sw_launch_fused_cfg(a, t.rows, t.vec, t.minw, t.pd, t.order, s);
     return a.dtype ? launch_step_cell<double>(a, s) : launch_step_cell<float>(a, s);
 }

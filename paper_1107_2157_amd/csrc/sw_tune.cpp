@@ -7,7 +7,7 @@
 // trial and at the end, so tuning leaves the simulation where it was.  Every
 // fused shape produces bitwise identical cells, so the choice affects speed
 // only.  Results are cached in a text file, one line per key
-//   <arch>:<CUs>:<dtype>:<scheme>:<nx>x<ny> variant rows vec occupancy us_per_step
+//   <arch>:<CUs>:<dtype>:<scheme>:<nx>x<ny> variant rows vec occupancy prefetch order us_per_step
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -48,7 +48,7 @@ bool cache_lookup(const char *path, const std::string &key, sw_tuning *t) {
         std::string k;
         sw_tuning c{};
         double us;
-        if (is >> k >> c.variant >> c.rows >> c.vec >> c.occupancy >> us && k == key) {
+        if (is >> k >> c.variant >> c.rows >> c.vec >> c.occupancy >> c.prefetch >> c.order >> us && k == key) {
             *t = c;       // the last entry for a key wins
             found = true;
         }
@@ -59,7 +59,8 @@ bool cache_lookup(const char *path, const std::string &key, sw_tuning *t) {
 void cache_store(const char *path, const std::string &key, const sw_tuning &t, double us) {
     if (!path || !*path) return;
     std::ofstream f(path, std::ios::app);
-    f << key << " " << t.variant << " " << t.rows << " " << t.vec << " " << t.occupancy << " " << us << "\n";
+    f << key << " " << t.variant << " " << t.rows << " " << t.vec << " " << t.occupancy << " " << t.prefetch << " "
+      << t.order << " " << us << "\n";
 }
 
 }  // namespace
@@ -91,7 +92,7 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
 
     std::vector<sw_tuning> cands;
     if (opts.scheme != SW_SCHEME_PAPER) {
-        cands.push_back(sw_tuning{1, 0, 0, 0});
+        cands.push_back(sw_tuning{1, 0, 0, 0, 0, 0});
     } else {
         const int vecs_f32[] = {2, 4}, vecs_f64[] = {1, 2};
         const int *vecs = opts.dtype == SW_F64 ? vecs_f64 : vecs_f32;
@@ -99,7 +100,11 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
         const int occs[] = {0, 3, 4};
         for (int vi = 0; vi < 2; ++vi)
             for (int occ : occs)
-                for (int rows : rows_list) cands.push_back(sw_tuning{2, rows, vecs[vi], occ});
+                for (int pd = 1; pd <= 3; ++pd)
+                    if (sw_fused_supported((int)opts.dtype, vecs[vi], occ, pd))
+                        for (int rows : rows_list)
+                            for (int order = 0; order <= 1; ++order)
+                                cands.push_back(sw_tuning{2, rows, vecs[vi], occ, pd, order});
     }
 
     // save buf[cur] (whole planes, halo included) and the time scalars
@@ -140,13 +145,19 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
         if (sw_set_tuning(ctx, &cands[i]) != SW_OK) continue;
         if ((he = restore()) != hipSuccess) break;
         if (sw_step(ctx, state, 1, stream) != SW_OK) continue;   // warm (code load, caches)
+        // per-step time = (T(1 + k) - T(1)) / k: the per-call prologue cancels
+        float ms1 = 0.f, msk = 0.f;
         if ((he = hipEventRecord(e0, s)) != hipSuccess) break;
-        if (sw_step(ctx, state, steps_per_trial, stream) != SW_OK) continue;
+        if (sw_step(ctx, state, 1, stream) != SW_OK) continue;
         if ((he = hipEventRecord(e1, s)) != hipSuccess) break;
         if ((he = hipEventSynchronize(e1)) != hipSuccess) break;
-        float ms = 0.f;
-        if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-        double us = 1000.0 * ms / steps_per_trial;
+        if ((he = hipEventElapsedTime(&ms1, e0, e1)) != hipSuccess) break;
+        if ((he = hipEventRecord(e0, s)) != hipSuccess) break;
+        if (sw_step(ctx, state, 1 + steps_per_trial, stream) != SW_OK) continue;
+        if ((he = hipEventRecord(e1, s)) != hipSuccess) break;
+        if ((he = hipEventSynchronize(e1)) != hipSuccess) break;
+        if ((he = hipEventElapsedTime(&msk, e0, e1)) != hipSuccess) break;
+        double us = 1000.0 * (msk - ms1) / steps_per_trial;
         if (us < best_us) {
             best_us = us;
             best = cands[i];

@@ -57,7 +57,7 @@ class Layout(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("rows", ctypes.c_int32), ("vec", ctypes.c_int32),
-                ("occupancy", ctypes.c_int32)]
+                ("occupancy", ctypes.c_int32), ("prefetch", ctypes.c_int32), ("order", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -187,8 +187,9 @@ class Solver:
     def set_variant(self, variant: int):
         check(lib().sw_set_variant(self.ctx, variant), "sw_set_variant")
 
-    def set_tuning(self, variant=0, rows=0, vec=0, occupancy=0):
-        check(lib().sw_set_tuning(self.ctx, ctypes.byref(Tuning(variant, rows, vec, occupancy))), "sw_set_tuning")
+    def set_tuning(self, variant=0, rows=0, vec=0, occupancy=0, prefetch=0, order=0):
+        check(lib().sw_set_tuning(self.ctx, ctypes.byref(Tuning(variant, rows, vec, occupancy, prefetch, order))),
+              "sw_set_tuning")
 
     def get_tuning(self) -> dict:
         t = Tuning()

@@ -101,24 +101,32 @@ def test_step_zero_and_cur_flip():
 
 def test_fused_tunings_bitwise_identical():
     """Every fused launch shape (cells per lane, rows per tile, register
-    budget) computes each cell with the same arithmetic: results are bitwise
-    equal, including the halo and the simulated time."""
+    budget, prefetch depth) computes each cell with the same arithmetic:
+    results are bitwise equal, including the halo and the simulated time."""
     nx, ny = 531, 190
     for dtype, vecs in (("f32", (2, 4)), ("f64", (1, 2))):
         st = ics.bumps_state(nx, ny, seed=31, periodic=False, count=5)
         ref = None
+        ran = 0
         for vec in vecs:
-            for rows in (7, 16, 64):
-                for occ in (0, 3, 4):
-                    announce(f"tuning {dtype} vec={vec} rows={rows} occ={occ}")
-                    s = sw.Solver(nx, ny, dtype=dtype)
-                    s.set_tuning(variant=sw.VARIANT_FUSED, rows=rows, vec=vec, occupancy=occ)
-                    s.set_state(*st)
-                    s.step(25)
-                    out = [a.numpy() for a in s.get_state(halo=True)] + [s.sync_status()]
-                    if ref is None:
-                        ref = out
-                    else:
-                        for x, y in zip(ref[:3], out[:3]):
-                            assert np.array_equal(x, y), (dtype, vec, rows, occ)
-                        assert ref[3] == out[3]
+            for occ in (0, 3, 4):
+                for pd in (1, 2, 3):
+                    for rows, order in ((7, 0), (16, 1), (64, 2), (5, 1)):
+                        s = sw.Solver(nx, ny, dtype=dtype)
+                        try:
+                            s.set_tuning(variant=sw.VARIANT_FUSED, rows=rows, vec=vec, occupancy=occ, prefetch=pd, order=order)
+                        except sw.SwError as e:
+                            assert e.status == sw.EINVAL
+                            continue
+                        announce(f"tuning {dtype} vec={vec} occ={occ} pd={pd} rows={rows}")
+                        s.set_state(*st)
+                        s.step(25)
+                        out = [a.numpy() for a in s.get_state(halo=True)] + [s.sync_status()]
+                        ran += 1
+                        if ref is None:
+                            ref = out
+                        else:
+                            for x, y in zip(ref[:3], out[:3]):
+                                assert np.array_equal(x, y), (dtype, vec, occ, pd, rows)
+                            assert ref[3] == out[3]
+        assert ran >= 30
