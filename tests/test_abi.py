@@ -1,0 +1,77 @@
+"""The C ABI on the CPU (no GPU needed): the library loads, exports every
+symbol `include/sw.h` declares, and rejects invalid arguments before any HIP
+call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1107_2157_amd import sw
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "sw.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(sw_\w+)\s*\(", text, re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_symbols()
+    assert len(names) >= 14
+    lib = sw.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(sw.SIGNATURES), "binding and header disagree"
+
+
+def test_layout_rules():
+    for dtype, eb in (("f32", 4), ("f64", 8)):
+        for nx in (1, 63, 64, 65, 300, 4096, 16384):
+            L = sw.layout_query(nx, 7, dtype)
+            assert L.elem_bytes == eb
+            assert (L.origin * eb) % 256 == 0 and (L.pitch * eb) % 256 == 0
+            assert L.pitch >= nx + 2 + (256 // eb) - 1          # left ghost + interior + right ghost
+            assert (L.origin - 1) % L.pitch + nx + 1 < L.pitch  # right ghost inside the row
+            assert L.plane_elems == L.pitch * 9
+            assert (L.pitch * eb) % 65536 != 0
+
+
+@pytest.mark.parametrize("nx,ny,dtype", [(0, 5, 0), (5, 0, 0), (-3, 4, 1), (5, 5, 7), (2 ** 30 + 1, 4, 0)])
+def test_layout_rejects(nx, ny, dtype):
+    out = sw.Layout()
+    assert sw.lib().sw_layout_query(sw.Grid(nx, ny), dtype, ctypes.byref(out)) == sw.EINVAL
+
+
+def create(nx=8, ny=8, halo=(1, 1, 1, 1), g=9.8, dx=1.0, **kw):
+    o = dict(dtype=sw.F32, bc_x=0, bc_y=0, scheme=0, dy=0.0, cfl=0.5, dt_fixed=0.0)
+    o.update(kw)
+    opts = sw.Opts(o["dtype"], o["bc_x"], o["bc_y"], o["scheme"], o["dy"], o["cfl"], o["dt_fixed"])
+    ctx = ctypes.c_void_p()
+    st = sw.lib().sw_create(sw.Grid(nx, ny), sw.Halo(*halo), g, dx, ctypes.byref(opts), ctypes.byref(ctx))
+    return st, sw.lib().sw_last_error_detail().decode()
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(nx=0), sw.EINVAL), (dict(g=0.0), sw.EINVAL), (dict(dx=-1.0), sw.EINVAL),
+    (dict(cfl=0.0, dt_fixed=0.0), sw.EINVAL), (dict(cfl=0.5, dt_fixed=0.1), sw.EINVAL),
+    (dict(bc_x=3), sw.EINVAL), (dict(scheme=5), sw.EINVAL), (dict(dtype=2), sw.EINVAL),
+    (dict(halo=(2, 1, 1, 1)), sw.ENOTSUP), (dict(halo=(-1, 1, 1, 1)), sw.EINVAL),
+    (dict(cfl=float("nan")), sw.EINVAL),
+])
+def test_create_validates_before_any_hip_call(kw, status):
+    st, detail = create(**kw)
+    assert st == status, detail
+    assert detail
+
+
+def test_null_arguments():
+    L = sw.lib()
+    assert L.sw_step(None, None, 1, None) == sw.EINVAL
+    assert L.sw_fill_halo(None, None, None) == sw.EINVAL
+    assert L.sw_sync_status(None, None, None, None, None) == sw.EINVAL
+    assert L.sw_set_tuning(None, None) == sw.EINVAL
+    assert L.sw_get_tuning(None, None) == sw.EINVAL
+    assert L.sw_destroy(None) == sw.OK
+    assert L.sw_strerror(sw.EUNSTABLE).decode().startswith("unstable")
