@@ -149,7 +149,7 @@ sw_status sw_set_variant(sw_ctx *ctx, int32_t variant);
 typedef struct {
     int32_t variant;    /* 0 auto, 1 per-cell baseline, 2 fused */
     int32_t rows;       /* fused: rows per tile (>= 1) */
-    int32_t vec;        /* fused: cells per lane; SW_F32: 2 or 4, SW_F64: 1 or 2 */
+    int32_t vec;        /* fused: cells per lane; SW_F32: 1, 2 or 4, SW_F64: 1 or 2 */
     int32_t occupancy;  /* fused: register budget in waves per SIMD: 0 (compiler's choice), 3 or 4 */
     int32_t prefetch;   /* fused: rows loaded ahead of the row being updated: 1, 2 or 3 */
     int32_t order;      /* fused: tile order: 0 row-block-major per XCD, 1 vertically grouped per XCD, 2 plain */
@@ -171,6 +171,53 @@ sw_status sw_get_tuning(const sw_ctx *ctx, sw_tuning *out);
  * Errors: SW_EINVAL, SW_ENOMEM, SW_EHIP, SW_ENOTSUP (no candidate ran). */
 sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per_trial, const char *cache_path, void *stream,
                       sw_tuning *best);
+
+/* ---------------------------------------------------------------------------
+ * Batched mode: n independent grids of possibly different sizes (same g, dx,
+ * options and scheme, paper scheme only), all advanced together.  Each grid
+ * keeps its own CFL dt, simulated time and sticky flag; a grid advanced in a
+ * batch is bitwise identical to the same grid advanced alone with the same
+ * launch shape.  One kernel launch per time step covers every grid (a tile
+ * table over all grids); sw_batch_step replays the whole call as one
+ * hipGraph launch (captured on first use per (nsteps, buffer, tuning)).
+ * The caller owns the arena (device memory); the library owns the tile
+ * table, per-grid scalars, graphs and a capture stream. */
+typedef struct sw_batch sw_batch;
+
+/* Validates every grid like sw_create (no HIP call until then), then
+ * allocates the per-grid scalars.  Errors: SW_EINVAL, SW_ENOTSUP (halo,
+ * transverse scheme), SW_ENOMEM, SW_EHIP. */
+sw_status sw_batch_create(int32_t n, const sw_grid *grids, sw_halo halo, double g, double dx, const sw_opts *opts,
+                          sw_batch **out);
+sw_status sw_batch_destroy(sw_batch *batch);
+/* Bytes of device memory the caller allocates for the arena. */
+sw_status sw_batch_arena_bytes(const sw_batch *batch, size_t *bytes);
+/* Attach a 256-byte aligned device arena of sw_batch_arena_bytes bytes.
+ * Resets the current buffer to 0.  Errors: SW_EINVAL, SW_EHIP. */
+sw_status sw_batch_bind(sw_batch *batch, void *arena);
+/* Grid i's planes inside the arena, as an sw_state (cur = the batch's
+ * current buffer) plus its layout (may be NULL): for writing initial states
+ * and reading results. */
+sw_status sw_batch_view(const sw_batch *batch, int32_t i, sw_state *view, sw_layout *layout);
+/* Async: materialise every grid's halo of the current buffer. */
+sw_status sw_batch_fill_halo(sw_batch *batch, void *stream);
+/* Async: advance every grid by nsteps (>= 0); the current buffer flips
+ * when nsteps is odd.  Errors (synchronous): SW_EINVAL, SW_EHIP. */
+sw_status sw_batch_step(sw_batch *batch, int32_t nsteps, void *stream);
+/* Synchronise, then per grid (arrays of n entries, each may be NULL): time,
+ * steps and the sticky flag.  Returns SW_EUNSTABLE if any grid is flagged. */
+sw_status sw_batch_sync_status(sw_batch *batch, void *stream, double *t, int64_t *steps, int32_t *unstable);
+sw_status sw_batch_reset_time(sw_batch *batch, void *stream);
+/* Launch shape for every grid (variant must be 0 or 2; order: 0 = LPT
+ * tile table, largest grids first; 1 = round-robin over grids). */
+sw_status sw_batch_set_tuning(sw_batch *batch, const sw_tuning *tuning);
+sw_status sw_batch_get_tuning(const sw_batch *batch, sw_tuning *out);
+/* 1 (default): one hipGraph launch per sw_batch_step call; 0: eager launches. */
+sw_status sw_batch_set_graph(sw_batch *batch, int32_t enable);
+/* Like sw_autotune over the batch (saves/restores the current buffer and
+ * the per-grid scalars; allocates a temporary copy of one buffer region). */
+sw_status sw_batch_autotune(sw_batch *batch, int32_t steps_per_trial, const char *cache_path, void *stream,
+                            sw_tuning *best);
 
 const char *sw_strerror(sw_status status);
 const char *sw_last_error_detail(void);

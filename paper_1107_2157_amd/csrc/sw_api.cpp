@@ -26,13 +26,18 @@ namespace {
 
 thread_local std::string g_detail;
 
-sw_status fail(sw_status s, const char *fmt, ...) {
+sw_status vfail(sw_status s, const char *fmt, va_list ap) {
     char buf[512];
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    g_detail = buf;
+    return s;
+}
+
+sw_status fail(sw_status s, const char *fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vfail(s, fmt, ap);
     va_end(ap);
-    g_detail = buf;
     return s;
 }
 
@@ -127,6 +132,50 @@ sw_status sw_ctx_describe(const sw_ctx *ctx, sw_grid *grid, sw_opts *opts, sw_la
     return use_device(ctx);
 }
 
+// Shared with the batched mode: record an error detail and return the status.
+sw_status sw_fail(sw_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vfail(s, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+// Validate one grid's creation arguments (no HIP call); resolve the options
+// (defaults, dy) and compute the layout.
+sw_status sw_validate_opts(sw_grid grid, sw_halo halo, double g, double dx, const sw_opts *opts, sw_opts *resolved,
+                           sw_layout *layout) {
+    sw_opts o;
+    if (opts) {
+        o = *opts;
+    } else {
+        o.dtype = SW_F32;
+        o.bc_x = o.bc_y = SW_BC_REFLECT;
+        o.scheme = SW_SCHEME_PAPER;
+        o.dy = 0.0;
+        o.cfl = 0.5;
+        o.dt_fixed = 0.0;
+    }
+    sw_status st = layout_for(grid, o.dtype, layout);
+    if (st != SW_OK) return st;
+    if (!(g > 0) || !(dx > 0)) return fail(SW_EINVAL, "create: g = %g and dx = %g must be > 0", g, dx);
+    o.dy = o.dy > 0 ? o.dy : dx;
+    if ((o.bc_x != SW_BC_REFLECT && o.bc_x != SW_BC_PERIODIC) || (o.bc_y != SW_BC_REFLECT && o.bc_y != SW_BC_PERIODIC))
+        return fail(SW_EINVAL, "create: unknown boundary condition");
+    if (o.scheme != SW_SCHEME_PAPER && o.scheme != SW_SCHEME_TRANSVERSE)
+        return fail(SW_EINVAL, "create: unknown scheme %d", (int)o.scheme);
+    if ((o.cfl > 0) == (o.dt_fixed > 0))
+        return fail(SW_EINVAL, "create: exactly one of cfl (%g) and dt_fixed (%g) must be > 0", o.cfl, o.dt_fixed);
+    if (!(o.cfl >= 0) || !(o.dt_fixed >= 0)) return fail(SW_EINVAL, "create: cfl / dt_fixed not a number");
+    if (halo.left < 0 || halo.right < 0 || halo.down < 0 || halo.up < 0)
+        return fail(SW_EINVAL, "create: negative halo width");
+    if (halo.left != 1 || halo.right != 1 || halo.down != 1 || halo.up != 1)
+        return fail(SW_ENOTSUP, "create: halo [%d,%d,%d,%d]; the scheme uses [1,1,1,1]", halo.left, halo.right,
+                    halo.down, halo.up);
+    *resolved = o;
+    return SW_OK;
+}
+
 extern "C" {
 
 const char *sw_strerror(sw_status s) {
@@ -149,33 +198,10 @@ sw_status sw_create(sw_grid grid, sw_halo halo, double g, double dx, const sw_op
     if (!out) return fail(SW_EINVAL, "create: NULL output");
     *out = nullptr;
     sw_opts o;
-    if (opts) {
-        o = *opts;
-    } else {
-        o.dtype = SW_F32;
-        o.bc_x = o.bc_y = SW_BC_REFLECT;
-        o.scheme = SW_SCHEME_PAPER;
-        o.dy = 0.0;
-        o.cfl = 0.5;
-        o.dt_fixed = 0.0;
-    }
     sw_layout lay;
-    sw_status st = layout_for(grid, o.dtype, &lay);
+    sw_status st = sw_validate_opts(grid, halo, g, dx, opts, &o, &lay);
     if (st != SW_OK) return st;
-    if (!(g > 0) || !(dx > 0)) return fail(SW_EINVAL, "create: g = %g and dx = %g must be > 0", g, dx);
-    double dy = o.dy > 0 ? o.dy : dx;
-    if ((o.bc_x != SW_BC_REFLECT && o.bc_x != SW_BC_PERIODIC) || (o.bc_y != SW_BC_REFLECT && o.bc_y != SW_BC_PERIODIC))
-        return fail(SW_EINVAL, "create: unknown boundary condition");
-    if (o.scheme != SW_SCHEME_PAPER && o.scheme != SW_SCHEME_TRANSVERSE)
-        return fail(SW_EINVAL, "create: unknown scheme %d", (int)o.scheme);
-    if ((o.cfl > 0) == (o.dt_fixed > 0))
-        return fail(SW_EINVAL, "create: exactly one of cfl (%g) and dt_fixed (%g) must be > 0", o.cfl, o.dt_fixed);
-    if (!(o.cfl >= 0) || !(o.dt_fixed >= 0)) return fail(SW_EINVAL, "create: cfl / dt_fixed not a number");
-    if (halo.left < 0 || halo.right < 0 || halo.down < 0 || halo.up < 0)
-        return fail(SW_EINVAL, "create: negative halo width");
-    if (halo.left != 1 || halo.right != 1 || halo.down != 1 || halo.up != 1)
-        return fail(SW_ENOTSUP, "create: halo [%d,%d,%d,%d]; the scheme uses [1,1,1,1]", halo.left, halo.right,
-                    halo.down, halo.up);
+    const double dy = o.dy;
     sw_ctx *c = new (std::nothrow) sw_ctx{};
     if (!c) return fail(SW_ENOMEM, "create: host allocation");
     c->grid = grid;

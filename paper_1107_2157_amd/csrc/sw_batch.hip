@@ -1,0 +1,152 @@
+// Batched step kernels: many independent grids of uneven sizes advance one
+// time step per launch.  A device tile table lists (grid, strip, row block)
+// for every grid; each wave takes one tile, reads the tile's grid descriptor
+// and that grid's dt, and runs the same per-tile body as the single-grid
+// kernel (sw_tile.h), so a grid advanced in a batch is bitwise identical to
+// the same grid advanced alone.  Each grid keeps its own CFL ring slots,
+// time and sticky flag.
+#include "sw_batch_internal.h"
+#include "sw_tile.h"
+
+using namespace sw;
+using namespace sw::tile;
+
+namespace {
+
+// dt of grid `grid` for step `step` (wave-wide).
+__device__ __forceinline__ double batch_dt(const SwBatchLaunch &a, int grid) {
+    if (a.dt_fixed > 0) return a.dt_fixed;
+    const int lane = threadIdx.x & 63;
+    double v = lane < kBatchStripes ? __longlong_as_double((long long)a.sc[grid].smax[a.step % 3][lane]) : 0.0;
+    return a.cfl * fmin(a.dx, a.dy) / wave_max(v);
+}
+
+// Wave-wide: this wave's tile, XCD-aware (block b runs on XCD b % 8; every
+// XCD takes a contiguous run of the tile table).
+__device__ __forceinline__ int batch_tile_index() {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int per_xcd = gridDim.x >> 3;
+    return ((((int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3)) << 2) + wave);
+}
+
+__device__ __forceinline__ void batch_reduce(const SwBatchLaunch &a, int grid, int slot, int stripe, double smax,
+                                             bool bad) {
+    smax = wave_max(smax);
+    unsigned long long anybad = __ballot(bad);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&a.sc[grid].smax[slot][stripe & (kBatchStripes - 1)], (unsigned long long)__double_as_longlong(smax));
+        if (anybad) atomicOr(&a.sc[grid].unstable, 1u);
+    }
+}
+
+template <typename T, int VEC, int MINW, int PD>
+__global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_batch_step(SwBatchLaunch a) {
+    const int tile = batch_tile_index();
+    if (tile >= a.ntiles) return;                 // whole wave leaves: no barriers are used
+    const SwBatchTile tt = a.tiles[tile];
+    const SwBatchGrid &gd = a.grids[tt.grid];
+    const double dt = batch_dt(a, tt.grid);
+    TileArgs t;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        t.in[k] = gd.plane[a.cur][k];
+        t.out[k] = const_cast<void *>(gd.plane[a.cur ^ 1][k]);
+    }
+    t.pitch = gd.pitch;
+    t.nx = gd.nx;
+    t.ny = gd.ny;
+    t.bc_x = a.bc_x;
+    t.bc_y = a.bc_y;
+    t.s = tt.s;
+    t.rb = tt.rb;
+    t.rows = a.rows;
+    T smax = T(0);
+    bool bad = false;
+    fused_tile<T, VEC, PD>(t, dt, a.g, a.dx, a.dy, smax, bad);
+    batch_reduce(a, tt.grid, (a.step + 1) % 3, tile, (double)smax, bad);
+    if (tt.s == 0 && tt.rb == 0) {               // the grid's first tile keeps its books
+        const int lane = threadIdx.x & 63;
+        if (lane < kBatchStripes) atomicExch(&a.sc[tt.grid].smax[(a.step + 2) % 3][lane], 0ull);
+        if (lane == 0) {
+            a.sc[tt.grid].t += dt;
+            a.sc[tt.grid].last_dt = dt;
+            a.sc[tt.grid].steps += 1;
+        }
+    }
+}
+
+// Once per call: ghosts of U^cur for every grid and the max signal speed
+// into ring slot 0.  One wave per tile, lanes across the tile's columns.
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_prologue(SwBatchLaunch a, int tile_cols) {
+    const int tile = batch_tile_index();
+    if (tile >= a.ntiles) return;
+    const SwBatchTile tt = a.tiles[tile];
+    const SwBatchGrid &gd = a.grids[tt.grid];
+    const int lane = threadIdx.x & 63;
+    T *P[3] = {(T *)gd.plane[a.cur][0], (T *)gd.plane[a.cur][1], (T *)gd.plane[a.cur][2]};
+    const T g = (T)a.g;
+    const int j0 = tt.rb * a.rows, j1 = min(j0 + a.rows, gd.ny);
+    const int c0 = tt.s * tile_cols, c1 = min(c0 + tile_cols, gd.nx);
+    double smax = 0.0;
+    bool bad = false;
+    for (int j = j0; j < j1; ++j)
+        for (int i = c0 + lane; i < c1; i += 64) {
+            const int64_t off = (int64_t)j * gd.pitch + i;
+            U3<T> c = {P[0][off], P[1][off], P[2][off]};
+            T sp = signal_speed(c, g);
+            bad |= !(sp <= finite_max<T>());
+            smax = fmax(smax, (double)sp);
+            if (i == 0 || i == gd.nx - 1 || j == 0 || j == gd.ny - 1)
+                write_ghosts(P, gd.pitch, gd.nx, gd.ny, a.bc_x, a.bc_y, i, j, c);
+        }
+    batch_reduce(a, tt.grid, 0, tile, smax, bad);
+}
+
+__global__ void k_batch_reset(SwBatchScalars *sc, int n, int clear_time) {
+    const int gi = blockIdx.x;
+    if (gi >= n) return;
+    if (threadIdx.x < 3 * kBatchStripes)
+        sc[gi].smax[threadIdx.x / kBatchStripes][threadIdx.x % kBatchStripes] = 0ull;
+    if (clear_time && threadIdx.x == 0) {
+        sc[gi].t = 0.0;
+        sc[gi].last_dt = 0.0;
+        sc[gi].steps = 0;
+        sc[gi].unstable = 0u;
+    }
+}
+
+unsigned batch_blocks(int ntiles) {
+    int64_t blocks = ((int64_t)ntiles + 3) / 4;
+    return (unsigned)((blocks + 7) / 8 * 8);
+}
+
+template <typename T, int VEC, int MINW, int PD>
+hipError_t launch_batch_t(const SwBatchLaunch &a, hipStream_t s) {
+    k_batch_step<T, VEC, MINW, PD><<<batch_blocks(a.ntiles), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t sw_batch_launch_reset(SwBatchScalars *sc, int n, int clear_time, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_batch_reset<<<n, 64, 0, s>>>(sc, n, clear_time);
+    return hipGetLastError();
+}
+
+hipError_t sw_batch_launch_prologue(const SwBatchLaunch &a, int vec, hipStream_t s) {
+    if (a.ntiles <= 0) return hipSuccess;
+    if (a.dtype) k_batch_prologue<double><<<batch_blocks(a.ntiles), 256, 0, s>>>(a, 64 * vec);
+    else k_batch_prologue<float><<<batch_blocks(a.ntiles), 256, 0, s>>>(a, 64 * vec);
+    return hipGetLastError();
+}
+
+hipError_t sw_batch_launch_step(const SwBatchLaunch &a, int vec, int minw, int pd, hipStream_t s) {
+    if (a.ntiles <= 0) return hipSuccess;
+#define SW_BATCH_CASE(T, V, M, P) \
+    if ((a.dtype == 1) == (sizeof(T) == 8) && vec == V && minw == M && pd == P) return launch_batch_t<T, V, M, P>(a, s);
+    SW_FUSED_SHAPES(SW_BATCH_CASE)
+#undef SW_BATCH_CASE
+    return hipErrorInvalidValue;
+}

@@ -1,0 +1,49 @@
+// Internal interface of the batched step (host <-> kernels).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "sw_internal.h"
+
+constexpr int kBatchStripes = 16;
+
+// Per-grid device scalars (CFL ring slots striped over 16 words, time, flag).
+struct SwBatchScalars {
+    unsigned long long smax[3][kBatchStripes];
+    double t;
+    double last_dt;
+    long long steps;
+    unsigned int unstable;
+    unsigned int pad;
+};
+
+// Per-grid descriptor: plane pointers at interior cell (0, 0) of both buffers.
+struct SwBatchGrid {
+    const void *plane[2][3];
+    int64_t pitch;
+    int32_t nx, ny;
+};
+
+// One tile of the table: grid, strip, row block.
+struct SwBatchTile {
+    int32_t grid;
+    int32_t s;
+    int32_t rb;
+    int32_t pad;
+};
+
+struct SwBatchLaunch {
+    const SwBatchTile *tiles;
+    const SwBatchGrid *grids;
+    SwBatchScalars *sc;
+    int32_t ntiles;
+    int32_t cur;      // buffer holding U^n for every grid
+    int32_t step;     // ring position
+    int32_t rows;     // rows per tile
+    double g, dx, dy, cfl, dt_fixed;
+    int32_t bc_x, bc_y, dtype, pad;
+};
+
+hipError_t sw_batch_launch_reset(SwBatchScalars *sc, int n, int clear_time, hipStream_t s);
+hipError_t sw_batch_launch_prologue(const SwBatchLaunch &a, int vec, hipStream_t s);
+hipError_t sw_batch_launch_step(const SwBatchLaunch &a, int vec, int minw, int pd, hipStream_t s);

@@ -1,147 +1,16 @@
-// Fused row-marching step kernel for gfx950.
-//
-// One wavefront owns a tile of W = 64 * VEC columns x R rows of the interior.
-// Lane l holds VEC consecutive cells of a row (one 16-byte load per plane).
-// The wave marches up its rows with a register window:
-//   - the new row j+1 arrives (its load was issued one iteration earlier);
-//   - per-cell fluxes F, G and the half-step contributions
-//       L = U/2 + lx F, R = U/2 - lx F   (x: face = L_left + R_right)
-//       B = U/2 + ly G, T = U/2 - ly G   (y: face = B_below + T_above)
-//     are formed once per cell (lx = dt/2dx, ly = dt/2dy);
-//   - x faces of row j+1 use the neighbour lanes' L/R through cross-lane
-//     moves (the strip's outer neighbours come from two edge loads) and give
-//     the x part of the update S = U - dt/dx (F_{i+1/2} - F_{i-1/2});
-//   - the y face j+1/2 = B_j + T_{j+1} gives G_{j+1/2}; row j is finished as
-//     S_j - dt/dy (G_{j+1/2} - G_{j-1/2}) and stored, with its ghost copies if
-//     it is an edge cell, and its signal speed enters the CFL max.
-// Face states never leave registers; every input cell is loaded once per
-// tile (plus one halo row above and below and two edge columns).
-#include <type_traits>
-
-#include "sw_common.h"
+// Single-grid fused step kernel for gfx950 (per-tile body in sw_tile.h).
+#include "sw_tile.h"
 
 using namespace sw;
+using namespace sw::tile;
 
 namespace {
-
-template <typename T> __device__ __forceinline__ T fast_rcp(T x);
-template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> __device__ __forceinline__ double fast_rcp<double>(double x) { return 1.0 / x; }
-
-template <typename T> __device__ __forceinline__ T fast_sqrt(T x);
-template <> __device__ __forceinline__ float fast_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
-template <> __device__ __forceinline__ double fast_sqrt<double>(double x) { return sqrt(x); }
-
-// Buffer (V#) access: a scalar resource descriptor per plane and tile, a
-// loop-invariant 32-bit byte offset per lane (VGPR) and the row's byte
-// offset (SGPR).  Marching to the next row changes only the scalar offset.
-// Out-of-range accesses are bounds-checked by the hardware (loads return 0,
-// stores are dropped).
-typedef __amdgpu_buffer_rsrc_t rsrc_t;
-constexpr int kRsrcWord3 = 0x00020000;   // GFX9 descriptor dword 3 (32-bit data format)
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ rsrc_t make_rsrc(const void *base, unsigned bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kRsrcWord3);
-}
-
-template <typename T, int VEC> __device__ __forceinline__ void bload(rsrc_t r, unsigned vo, unsigned so, T o[VEC]);
-template <> __device__ __forceinline__ void bload<float, 2>(rsrc_t r, unsigned vo, unsigned so, float o[2]) {
-    u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
-    o[0] = __uint_as_float(v.x); o[1] = __uint_as_float(v.y);
-}
-template <> __device__ __forceinline__ void bload<float, 4>(rsrc_t r, unsigned vo, unsigned so, float o[4]) {
-    u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
-    o[0] = __uint_as_float(v.x); o[1] = __uint_as_float(v.y); o[2] = __uint_as_float(v.z); o[3] = __uint_as_float(v.w);
-}
-template <> __device__ __forceinline__ void bload<double, 1>(rsrc_t r, unsigned vo, unsigned so, double o[1]) {
-    u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
-    o[0] = __hiloint2double((int)v.y, (int)v.x);
-}
-template <> __device__ __forceinline__ void bload<double, 2>(rsrc_t r, unsigned vo, unsigned so, double o[2]) {
-    u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
-    o[0] = __hiloint2double((int)v.y, (int)v.x); o[1] = __hiloint2double((int)v.w, (int)v.z);
-}
-__device__ __forceinline__ float bload1(rsrc_t r, unsigned vo, unsigned so, float) {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
-}
-__device__ __forceinline__ double bload1(rsrc_t r, unsigned vo, unsigned so, double) {
-    u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
-    return __hiloint2double((int)v.y, (int)v.x);
-}
-
-template <typename T, int VEC> __device__ __forceinline__ void bstore(rsrc_t r, unsigned vo, unsigned so, const T o[VEC]);
-template <> __device__ __forceinline__ void bstore<float, 2>(rsrc_t r, unsigned vo, unsigned so, const float o[2]) {
-    u32x2 v = {__float_as_uint(o[0]), __float_as_uint(o[1])};
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, so, 0);
-}
-template <> __device__ __forceinline__ void bstore<float, 4>(rsrc_t r, unsigned vo, unsigned so, const float o[4]) {
-    u32x4 v = {__float_as_uint(o[0]), __float_as_uint(o[1]), __float_as_uint(o[2]), __float_as_uint(o[3])};
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, vo, so, 0);
-}
-template <> __device__ __forceinline__ void bstore<double, 1>(rsrc_t r, unsigned vo, unsigned so, const double o[1]) {
-    u32x2 v = {(unsigned)__double2loint(o[0]), (unsigned)__double2hiint(o[0])};
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, so, 0);
-}
-template <> __device__ __forceinline__ void bstore<double, 2>(rsrc_t r, unsigned vo, unsigned so, const double o[2]) {
-    u32x4 v = {(unsigned)__double2loint(o[0]), (unsigned)__double2hiint(o[0]), (unsigned)__double2loint(o[1]),
-               (unsigned)__double2hiint(o[1])};
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, vo, so, 0);
-}
-
-// Cross-lane moves along the wave.  DPP wave_shr:1 / wave_shl:1 (GFX9
-// whole-wave shifts) move a register one lane up / down; the lane with no
-// source keeps `edge` (bound_ctrl off), which is exactly the strip's outer
-// neighbour.
-__device__ __forceinline__ int dpp_prev(int x, int edge) { return __builtin_amdgcn_update_dpp(edge, x, 0x138, 0xf, 0xf, false); }
-__device__ __forceinline__ int dpp_next(int x, int edge) { return __builtin_amdgcn_update_dpp(edge, x, 0x130, 0xf, 0xf, false); }
-
-// Lane l receives x from lane l - 1; lane 0 receives `edge`.
-__device__ __forceinline__ float from_prev_lane(float x, float edge) {
-    return __int_as_float(dpp_prev(__float_as_int(x), __float_as_int(edge)));
-}
-__device__ __forceinline__ double from_prev_lane(double x, double edge) {
-    long long xi = __double_as_longlong(x), ei = __double_as_longlong(edge);
-    int lo = dpp_prev((int)xi, (int)ei), hi = dpp_prev((int)(xi >> 32), (int)(ei >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-// Lane l receives x from lane l + 1; lane 63 receives `edge`.
-__device__ __forceinline__ float from_next_lane(float x, float edge) {
-    return __int_as_float(dpp_next(__float_as_int(x), __float_as_int(edge)));
-}
-__device__ __forceinline__ double from_next_lane(double x, double edge) {
-    long long xi = __double_as_longlong(x), ei = __double_as_longlong(edge);
-    int lo = dpp_next((int)xi, (int)ei), hi = dpp_next((int)(xi >> 32), (int)(ei >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Flux through an x face from its half-step state X: F(X).
-template <typename T> __device__ __forceinline__ void xface_flux(T xh, T xp, T xq, T k, T f[3]) {
-    T r = fast_rcp(xh);
-    T u = xp * r;
-    f[0] = xp;
-    f[1] = fma(k * xh, xh, xp * u);
-    f[2] = xq * u;
-}
-// Flux through a y face from its half-step state Y: G(Y).
-template <typename T> __device__ __forceinline__ void yface_flux(T yh, T yp, T yq, T k, T f[3]) {
-    T r = fast_rcp(yh);
-    T v = yq * r;
-    f[0] = yq;
-    f[1] = yp * v;
-    f[2] = fma(k * yh, yh, yq * v);
-}
-
-template <bool B> using bconst = std::integral_constant<bool, B>;
 
 // MINW: register budget expressed as waves per SIMD (0 = compiler's choice).
 // PD: rows loaded ahead of the row being processed (software pipeline depth).
 template <typename T, int VEC, int MINW, int PD>
 __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_step_fused(SwLaunch a, int rows, int nstrips, int nrb,
                                                                            int order) {
-    constexpr int W = 64 * VEC;
-    const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // Tile order.  Blocks are dispatched round-robin over the 8 XCDs (block
     // b on XCD b % 8); orders 0 and 1 give every XCD a contiguous run of the
@@ -162,193 +31,17 @@ __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_step_fused(SwLau
         rb = tile / nstrips;
     }
     const double dt = step_dt(a);
-    const T k = (T)(0.5 * a.g), g = (T)a.g;
-    const T lx = (T)(0.5 * dt / a.dx), ly = (T)(0.5 * dt / a.dy);
-    const T mx = (T)(dt / a.dx), my = (T)(dt / a.dy);
-    const int nx = a.nx, ny = a.ny;
-    const int64_t pitch = a.pitch;
     T smax = T(0);
     bool bad = false;
-
     if (rb < nrb) {
-        const int c0 = s * W, j0 = rb * rows, j1 = min(j0 + rows, ny);
-        const unsigned c = (unsigned)(c0 + VEC * lane);
-        const bool in_row = (int)c <= nx;                    // the vector stays inside the row's allocation
-        const bool full = (int)c + VEC <= nx;                // all VEC cells are interior
-        // Edge loads: lanes 0..31 read the column left of the strip, lanes
-        // 32..63 the column right of it (two addresses per instruction);
-        // lane 0 and lane 63 use them.  Past the right end of the grid the
-        // right edge is never needed and reads the left one instead.
-        const bool right_ok = c0 + W <= nx;
-        const unsigned ec = (lane < 32 || !right_ok) ? (unsigned)c0 : (unsigned)(c0 + W + 1);   // column + 1
-        // Lanes past the end of the row read the strip's first vector; their
-        // cells are never stored and never enter the CFL max.  All loads are
-        // unconditional (rows past the tile are clamped to its last row) so
-        // that the compiler can count the loads in flight exactly and keep
-        // the prefetched rows outstanding while it computes.
-        const unsigned cl = in_row ? c : (unsigned)c0;
-        const T elx = lane == 0 ? lx : -lx;                  // lane 0 needs L of its edge, lane 63 needs R
-        const bool tile_at_wall = s == 0 || c0 + W >= nx || j0 == 0 || j1 >= ny;
-        T *O[3] = {(T *)a.out[0], (T *)a.out[1], (T *)a.out[2]};
-        // Descriptors of this tile: they start at cell (-1, j0 - 1) and span
-        // rows j0 - 1 .. j1; a row's byte offset is (j - j0 + 1) * pitch * size.
-        const int64_t tile_base = (int64_t)(j0 - 1) * pitch - 1;
-        const int64_t span = (int64_t)(j1 - j0 + 2) * pitch * (int64_t)sizeof(T);
-        const unsigned nrec = span > 0x7fffffff ? 0x7fffffffu : (unsigned)span;
-        const rsrc_t rin0 = make_rsrc((const T *)a.in[0] + tile_base, nrec);
-        const rsrc_t rin1 = make_rsrc((const T *)a.in[1] + tile_base, nrec);
-        const rsrc_t rin2 = make_rsrc((const T *)a.in[2] + tile_base, nrec);
-        const rsrc_t rout[3] = {make_rsrc(O[0] + tile_base, nrec), make_rsrc(O[1] + tile_base, nrec),
-                                make_rsrc(O[2] + tile_base, nrec)};
-        const unsigned row_bytes = (unsigned)(pitch * (int64_t)sizeof(T));
-        const unsigned lb = (cl + 1) * (unsigned)sizeof(T);   // lane's vector
-        const unsigned eb = ec * (unsigned)sizeof(T);         // lane's edge cell (ec is column + 1)
-        const unsigned sb = (c + 1) * (unsigned)sizeof(T);    // lane's store vector
-
-        auto load_row = [&](int j, T h[VEC], T p[VEC], T q[VEC], T e[3]) {
-            const unsigned so = (unsigned)(j - j0 + 1) * row_bytes;
-            bload<T, VEC>(rin0, lb, so, h);
-            bload<T, VEC>(rin1, lb, so, p);
-            bload<T, VEC>(rin2, lb, so, q);
-            e[0] = bload1(rin0, eb, so, T(0));
-            e[1] = bload1(rin1, eb, so, T(0));
-            e[2] = bload1(rin2, eb, so, T(0));
-        };
-
-        // Carried from one row to the next (lane's VEC cells):
-        T S[3][VEC];    // x part of the update of the row below: U - mx (F_{i+1/2} - F_{i-1/2})
-        T Bp[3][VEC];   // y-face contribution of the row below: U/2 + ly G
-        T Gd[3][VEC];   // G flux through the face below the current row
-
-        // One pass over a newly arrived row r (= j + 1): its y face with the
-        // row below gives G_{r-1/2}, which finishes row r - 1 (if EMIT); then
-        // r's own B and (if want_x) the x part S of its update.
-        auto row_pass = [&](auto face_c, auto emit_c, const T h[VEC], const T p[VEC], const T q[VEC],
-                            const T e[3], bool want_x, int jout) {
-            constexpr bool FACE = decltype(face_c)::value, EMIT = decltype(emit_c)::value;
-            T L[3][VEC], R[3][VEC], out[3][VEC];
-#pragma unroll
-            for (int m = 0; m < VEC; ++m) {
-                T r = fast_rcp(h[m]);
-                T u = p[m] * r, v = q[m] * r;
-                T kh = k * h[m];
-                T fp = fma(kh, h[m], p[m] * u);
-                T fq = q[m] * u;            // = hu hv / h: x flux of hv and y flux of hu
-                T gq = fma(kh, h[m], q[m] * v);
-                T hh = T(0.5) * h[m], hp = T(0.5) * p[m], hq = T(0.5) * q[m];
-                if (FACE) {
-                    T f[3];
-                    yface_flux<T>(Bp[0][m] + fma(-ly, q[m], hh), Bp[1][m] + fma(-ly, fq, hp),
-                               Bp[2][m] + fma(-ly, gq, hq), k, f);
-#pragma unroll
-                    for (int kk = 0; kk < 3; ++kk) {
-                        if (EMIT) out[kk][m] = fma(-my, f[kk] - Gd[kk][m], S[kk][m]);
-                        Gd[kk][m] = f[kk];
-                    }
-                }
-                Bp[0][m] = fma(ly, q[m], hh); Bp[1][m] = fma(ly, fq, hp); Bp[2][m] = fma(ly, gq, hq);
-                L[0][m] = fma(lx, p[m], hh); R[0][m] = fma(-lx, p[m], hh);
-                L[1][m] = fma(lx, fp, hp);   R[1][m] = fma(-lx, fp, hp);
-                L[2][m] = fma(lx, fq, hq);   R[2][m] = fma(-lx, fq, hq);
-            }
-            if (EMIT) {
-                const int64_t ro = (int64_t)jout * pitch;
-                if (full) {
-                    const unsigned so = (unsigned)(jout - j0 + 1) * row_bytes;
-#pragma unroll
-                    for (int kk = 0; kk < 3; ++kk) bstore<T, VEC>(rout[kk], sb, so, out[kk]);
-#pragma unroll
-                    for (int m = 0; m < VEC; ++m) {
-                        T sp = fmax(fabs(out[1][m]), fabs(out[2][m])) * fast_rcp(out[0][m]) +
-                               fast_sqrt(g * out[0][m]);
-                        bad |= !(sp <= finite_max<T>());
-                        smax = fmax(smax, sp);
-                    }
-                } else {
-#pragma unroll
-                    for (int m = 0; m < VEC; ++m) {
-                        if ((int)c + m < nx) {
-#pragma unroll
-                            for (int kk = 0; kk < 3; ++kk) O[kk][ro + c + m] = out[kk][m];
-                            T sp = fmax(fabs(out[1][m]), fabs(out[2][m])) * fast_rcp(out[0][m]) +
-                                   fast_sqrt(g * out[0][m]);
-                            bad |= !(sp <= finite_max<T>());
-                            smax = fmax(smax, sp);
-                        }
-                    }
-                }
-                if (tile_at_wall) {
-#pragma unroll
-                    for (int m = 0; m < VEC; ++m) {
-                        const int i = (int)c + m;
-                        if (i < nx && (i == 0 || i == nx - 1 || jout == 0 || jout == ny - 1))
-                            write_ghosts(O, pitch, nx, ny, a.bc_x, a.bc_y, i, jout,
-                                         U3<T>{out[0][m], out[1][m], out[2][m]});
-                    }
-                }
-            }
-            if (!want_x) return;
-            // the lane's edge cell: L (lane 0) or R (lane 63) of the column
-            // just outside the strip
-            T E[3];
-            {
-                T r = fast_rcp(e[0]);
-                T u = e[1] * r;
-                T fp = fma(k * e[0], e[0], e[1] * u);
-                T fq = e[2] * u;
-                E[0] = fma(elx, e[1], T(0.5) * e[0]);
-                E[1] = fma(elx, fp, T(0.5) * e[1]);
-                E[2] = fma(elx, fq, T(0.5) * e[2]);
-            }
-            T fl[3], fr[3];
-            {
-                T Lm[3];
-#pragma unroll
-                for (int kk = 0; kk < 3; ++kk) Lm[kk] = from_prev_lane(L[kk][VEC - 1], E[kk]);
-                xface_flux<T>(Lm[0] + R[0][0], Lm[1] + R[1][0], Lm[2] + R[2][0], k, fl);
-            }
-            const T *U[3] = {h, p, q};
-#pragma unroll
-            for (int m = 0; m < VEC; ++m) {
-                if (m + 1 < VEC) {
-                    xface_flux<T>(L[0][m] + R[0][m + 1], L[1][m] + R[1][m + 1], L[2][m] + R[2][m + 1], k, fr);
-                } else {
-                    T Rp[3];
-#pragma unroll
-                    for (int kk = 0; kk < 3; ++kk) Rp[kk] = from_next_lane(R[kk][0], E[kk]);
-                    xface_flux<T>(L[0][m] + Rp[0], L[1][m] + Rp[1], L[2][m] + Rp[2], k, fr);
-                }
-#pragma unroll
-                for (int kk = 0; kk < 3; ++kk) {
-                    S[kk][m] = fma(-mx, fr[kk] - fl[kk], U[kk][m]);
-                    fl[kk] = fr[kk];
-                }
-            }
-        };
-
-        // Prologue: row j0 - 1 gives B; row j0 gives G_{j0-1/2}, B and S.
-        // Raw rows j0+1 .. j1 pass through a ring of PD + 1 register sets:
-        // row r sits in set (r - j0 - 1) % (PD + 1), loaded PD rows before
-        // it is used.
-        T rh[PD + 1][VEC], rp[PD + 1][VEC], rq[PD + 1][VEC], re[PD + 1][3];
-        load_row(j0 - 1, rh[0], rp[0], rq[0], re[0]);
-        load_row(j0, rh[1 % (PD + 1)], rp[1 % (PD + 1)], rq[1 % (PD + 1)], re[1 % (PD + 1)]);
-        row_pass(bconst<false>{}, bconst<false>{}, rh[0], rp[0], rq[0], re[0], false, 0);
-        row_pass(bconst<true>{}, bconst<false>{}, rh[1 % (PD + 1)], rp[1 % (PD + 1)], rq[1 % (PD + 1)],
-                 re[1 % (PD + 1)], true, 0);
-#pragma unroll
-        for (int u = 0; u < PD; ++u) load_row(min(j0 + 1 + u, j1), rh[u], rp[u], rq[u], re[u]);
-        for (int jb = j0; jb < j1; jb += PD + 1) {
-#pragma unroll
-            for (int u = 0; u <= PD; ++u) {
-                const int j = jb + u;          // output row; its upper neighbour j+1 is in set u
-                if (j >= j1) break;
-                const int slot = (u + PD) % (PD + 1);
-                load_row(min(j + 1 + PD, j1), rh[slot], rp[slot], rq[slot], re[slot]);
-                row_pass(bconst<true>{}, bconst<true>{}, rh[u], rp[u], rq[u], re[u], j + 1 < j1, j);
-            }
-        }
+        TileArgs t;
+        for (int kk = 0; kk < 3; ++kk) { t.in[kk] = a.in[kk]; t.out[kk] = a.out[kk]; }
+        t.pitch = a.pitch;
+        t.nx = a.nx; t.ny = a.ny; t.bc_x = a.bc_x; t.bc_y = a.bc_y;
+        t.s = s; t.rb = rb; t.rows = rows;
+        fused_tile<T, VEC, PD>(t, dt, a.g, a.dx, a.dy, smax, bad);
     }
+
     step_epilogue(a, (double)smax, bad, dt, blockIdx.x == 0 && wave == 0, (int)blockIdx.x * 4 + wave);
 }
 
@@ -378,17 +71,6 @@ int sw_fused_default_rows(int nx, int ny, int vec) {
 }
 
 int sw_fused_default_vec(int dtype) { return dtype ? 2 : 4; }
-
-// The instantiated launch shapes: (dtype, cells per lane, register budget,
-// prefetch depth).
-#define SW_FUSED_SHAPES(X)                                                                      \
-    X(float, 2, 0, 1) X(float, 2, 0, 2) X(float, 2, 0, 3) X(float, 2, 3, 1) X(float, 2, 3, 2)  \
-    X(float, 2, 3, 3) X(float, 2, 4, 1) X(float, 2, 4, 2) X(float, 2, 4, 3) X(float, 4, 0, 1)  \
-    X(float, 4, 0, 2) X(float, 4, 0, 3) X(float, 4, 3, 1) X(float, 4, 3, 2)                      \
-    X(double, 1, 0, 1) X(double, 1, 0, 2) X(double, 1, 0, 3) X(double, 1, 3, 1)                 \
-    X(double, 1, 3, 2) X(double, 1, 3, 3) X(double, 1, 4, 1) X(double, 1, 4, 2)                 \
-    X(double, 1, 4, 3) X(double, 2, 0, 1) X(double, 2, 0, 2) X(double, 2, 0, 3)                 \
-    X(double, 2, 3, 1) X(double, 2, 3, 2)
 
 bool sw_fused_supported(int dtype, int vec, int minw, int pd) {
 #define SW_FUSED_SUP(T, V, M, P) \

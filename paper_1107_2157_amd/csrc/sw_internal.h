@@ -56,3 +56,15 @@ hipError_t sw_launch_fused_cfg(const SwLaunch &a, int rows, int vec, int minw, i
 int sw_fused_default_rows(int nx, int ny, int vec);
 int sw_fused_default_vec(int dtype);
 bool sw_fused_supported(int dtype, int vec, int minw, int pd);
+
+// The instantiated launch shapes: (dtype, cells per lane, register budget,
+// prefetch depth).
+#define SW_FUSED_SHAPES(X)                                                                      \
+    X(float, 1, 0, 1) X(float, 1, 0, 2) X(float, 1, 4, 2)                                        \
+    X(float, 2, 0, 1) X(float, 2, 0, 2) X(float, 2, 0, 3) X(float, 2, 3, 1) X(float, 2, 3, 2)  \
+    X(float, 2, 3, 3) X(float, 2, 4, 1) X(float, 2, 4, 2) X(float, 2, 4, 3) X(float, 4, 0, 1)  \
+    X(float, 4, 0, 2) X(float, 4, 0, 3) X(float, 4, 3, 1) X(float, 4, 3, 2)                      \
+    X(double, 1, 0, 1) X(double, 1, 0, 2) X(double, 1, 0, 3) X(double, 1, 3, 1)                 \
+    X(double, 1, 3, 2) X(double, 1, 3, 3) X(double, 1, 4, 1) X(double, 1, 4, 2)                 \
+    X(double, 1, 4, 3) X(double, 2, 0, 1) X(double, 2, 0, 2) X(double, 2, 0, 3)                 \
+    X(double, 2, 3, 1) X(double, 2, 3, 2)

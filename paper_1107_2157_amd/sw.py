@@ -87,6 +87,22 @@ SIGNATURES = {
     "sw_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "sw_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(State), ctypes.c_int32, ctypes.c_char_p,
                                    ctypes.c_void_p, ctypes.POINTER(Tuning)]),
+    "sw_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(Grid), Halo, ctypes.c_double, ctypes.c_double,
+                                       ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_void_p)]),
+    "sw_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sw_batch_arena_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "sw_batch_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sw_batch_view": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(State), ctypes.POINTER(Layout)]),
+    "sw_batch_fill_halo": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sw_batch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "sw_batch_sync_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
+    "sw_batch_reset_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sw_batch_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
+    "sw_batch_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
+    "sw_batch_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "sw_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_void_p,
+                                         ctypes.POINTER(Tuning)]),
     "sw_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sw_last_error_detail": (ctypes.c_char_p, []),
 }
@@ -218,3 +234,101 @@ class Solver:
 
     def reset_time(self, stream=None):
         check(lib().sw_reset_time(self.ctx, _stream_handle(stream)), "sw_reset_time")
+
+
+class Batch:
+    """Many independent grids advanced together (sw_batch_*): one device
+    arena (a torch uint8 tensor), one launch per step for all grids, the
+    whole call replayed as one hipGraph."""
+
+    def __init__(self, sides, g: float = 9.8, dx: float = 1.0, dtype="f32", bc_x: int = REFLECT,
+                 bc_y: int = REFLECT, dy: float = 0.0, cfl: float = 0.5, dt_fixed: float = 0.0, device="cuda"):
+        shapes = [(s, s) if isinstance(s, int) else tuple(s) for s in sides]
+        self.n = len(shapes)
+        self.shapes = shapes
+        self.dtype = _DT[dtype]
+        self.torch_dtype = _TORCH_DT[self.dtype]
+        grids = (Grid * self.n)(*[Grid(nx, ny) for nx, ny in shapes])
+        opts = Opts(self.dtype, bc_x, bc_y, SCHEME_PAPER, dy, cfl, dt_fixed)
+        h = ctypes.c_void_p()
+        check(lib().sw_batch_create(self.n, grids, Halo(1, 1, 1, 1), g, dx, ctypes.byref(opts), ctypes.byref(h)),
+              "sw_batch_create")
+        self.handle = h
+        nbytes = ctypes.c_size_t()
+        check(lib().sw_batch_arena_bytes(h, ctypes.byref(nbytes)), "sw_batch_arena_bytes")
+        self.arena = torch.zeros(nbytes.value, dtype=torch.uint8, device=device)
+        check(lib().sw_batch_bind(h, ctypes.c_void_p(self.arena.data_ptr())), "sw_batch_bind")
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.sw_batch_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    def _view(self, i):
+        st, lay = State(), Layout()
+        check(lib().sw_batch_view(self.handle, i, ctypes.byref(st), ctypes.byref(lay)), "sw_batch_view")
+        return st, lay
+
+    def halo_view(self, i: int, k: int, buf: int | None = None) -> torch.Tensor:
+        st, L = self._view(i)
+        b = st.cur if buf is None else buf
+        base = st.plane[b][k] - self.arena.data_ptr()
+        eb = L.elem_bytes
+        nx, ny = self.shapes[i]
+        flat = self.arena[base: base + L.plane_elems * eb].view(self.torch_dtype)
+        # as_strided's storage offset is absolute within the arena's storage
+        return torch.as_strided(flat, (ny + 2, nx + 2), (L.pitch, 1),
+                                flat.storage_offset() + L.origin - L.pitch - 1)
+
+    def interior(self, i: int, k: int, buf: int | None = None) -> torch.Tensor:
+        return self.halo_view(i, k, buf)[1:-1, 1:-1]
+
+    def set_state(self, i: int, h, hu, hv):
+        for k, a in enumerate((h, hu, hv)):
+            self.interior(i, k).copy_(torch.as_tensor(a).to(self.torch_dtype))
+
+    def get_state(self, i: int, halo: bool = False):
+        torch.cuda.synchronize()
+        f = self.halo_view if halo else self.interior
+        return tuple(f(i, k).to("cpu", torch.float64) for k in range(3))
+
+    def set_tuning(self, variant=0, rows=0, vec=0, occupancy=0, prefetch=0, order=0):
+        check(lib().sw_batch_set_tuning(self.handle, ctypes.byref(Tuning(variant, rows, vec, occupancy, prefetch,
+                                                                          order))), "sw_batch_set_tuning")
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        check(lib().sw_batch_get_tuning(self.handle, ctypes.byref(t)), "sw_batch_get_tuning")
+        return t.as_dict()
+
+    def set_graph(self, enable: bool):
+        check(lib().sw_batch_set_graph(self.handle, 1 if enable else 0), "sw_batch_set_graph")
+
+    def autotune(self, steps_per_trial: int = 3, cache_path: str | None = None, stream=None) -> dict:
+        t = Tuning()
+        path = cache_path.encode() if cache_path else None
+        check(lib().sw_batch_autotune(self.handle, steps_per_trial, path, _stream_handle(stream), ctypes.byref(t)),
+              "sw_batch_autotune")
+        return t.as_dict()
+
+    def fill_halo(self, stream=None):
+        check(lib().sw_batch_fill_halo(self.handle, _stream_handle(stream)), "sw_batch_fill_halo")
+
+    def step(self, nsteps: int, stream=None):
+        check(lib().sw_batch_step(self.handle, nsteps, _stream_handle(stream)), "sw_batch_step")
+
+    def sync_status(self, stream=None, raise_unstable=True):
+        """Per-grid (t, steps, unstable) arrays."""
+        t = (ctypes.c_double * self.n)()
+        n = (ctypes.c_int64 * self.n)()
+        u = (ctypes.c_int32 * self.n)()
+        st = lib().sw_batch_sync_status(self.handle, _stream_handle(stream), t, n, u)
+        if st != EUNSTABLE or raise_unstable:
+            check(st, "sw_batch_sync_status")
+        return list(t), list(n), list(u)
+
+    def reset_time(self, stream=None):
+        check(lib().sw_batch_reset_time(self.handle, _stream_handle(stream)), "sw_batch_reset_time")

@@ -1,0 +1,125 @@
+"""Batched mode on the GPU (through the C ABI): every grid of a batch equals
+the same grid advanced alone, bitwise; small grids match the oracle; graph
+replays equal eager launches; per-grid dt, time and sticky flags."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1107_2157_amd import ics, sw
+from swtest import G, announce, rel_maxnorm
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(64, 64), (130, 65), (200, 64), (1, 1), (300, 17), (17, 300), (257, 129), (64, 1024)]
+
+
+def states(shapes, seed0, periodic):
+    out = []
+    for k, (nx, ny) in enumerate(shapes):
+        h, _, _ = ics.bumps_state(nx, ny, seed=seed0 + k, periodic=periodic)
+        _, hu, hv = ics.random_state(nx, ny, seed=seed0 + k, amp_h=0.0, amp_m=0.02)
+        out.append((h, hu, hv))
+    return out
+
+
+def make_batch(shapes, sts, dtype, bc, tuning, graph=True, **kw):
+    b = sw.Batch(shapes, dtype=dtype, bc_x=bc, bc_y=bc, **kw)
+    b.set_tuning(**tuning)
+    b.set_graph(graph)
+    for i, st in enumerate(sts):
+        b.set_state(i, *st)
+    return b
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("bc", [sw.REFLECT, sw.PERIODIC])
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_equals_each_grid_alone(dtype, bc, graph):
+    tun = dict(variant=2, rows=16, vec=2, occupancy=0, prefetch=2, order=0)
+    sts = states(SHAPES, 100, bc == sw.PERIODIC)
+    announce(f"batch {dtype} bc{bc} graph{graph}")
+    b = make_batch(SHAPES, sts, dtype, bc, tun, graph)
+    b.step(7)
+    b.step(4)
+    t_b, n_b, _ = b.sync_status()
+    for i, (nx, ny) in enumerate(SHAPES):
+        s = sw.Solver(nx, ny, dtype=dtype, bc_x=bc, bc_y=bc)
+        s.set_tuning(**tun)
+        s.set_state(*sts[i])
+        s.step(7)
+        s.step(4)
+        t_s, _, n_s = s.sync_status()
+        got = b.get_state(i, halo=True)
+        ref = s.get_state(halo=True)
+        for x, y in zip(got, ref):
+            assert np.array_equal(x.numpy(), y.numpy()), (i, nx, ny)
+        assert n_b[i] == n_s == 11 and t_b[i] == t_s
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_batch_matches_oracle(dtype, tol):
+    shapes = [(96, 80), (33, 150), (128, 128)]
+    sts = states(shapes, 300, False)
+    b = make_batch(shapes, sts, dtype, sw.REFLECT, dict(variant=2))
+    b.step(60)
+    b.sync_status()
+    for i, st in enumerate(sts):
+        st = [a.to(torch.float32).to(torch.float64) if dtype == "f32" else a for a in st]
+        H, U, V, _ = oracle.run(*(a.numpy() for a in st), 60, g=G)
+        err = rel_maxnorm(b.get_state(i), (H[1:-1, 1:-1], U[1:-1, 1:-1], V[1:-1, 1:-1]))
+        assert err <= tol, (i, err)
+
+
+def test_graph_replays_equal_eager():
+    """The cached graph is replayed several times with eager work and
+    synchronisations between the replays; every replay equals an eager
+    batch run step for step."""
+    shapes = [(128, 64), (64, 200), (320, 96)]
+    sts = states(shapes, 500, True)
+    tun = dict(variant=2, rows=8, vec=2, order=1)
+    bg = make_batch(shapes, sts, "f32", sw.PERIODIC, tun, graph=True)
+    be = make_batch(shapes, sts, "f32", sw.PERIODIC, tun, graph=False)
+    for rep in range(4):
+        bg.step(5)
+        be.step(5)
+        torch.cuda.synchronize()
+        _ = (torch.ones(1000, device="cuda") * 2).sum().item()      # unrelated eager work
+        for i in range(len(shapes)):
+            for x, y in zip(bg.get_state(i), be.get_state(i)):
+                assert np.array_equal(x.numpy(), y.numpy()), (rep, i)
+        assert bg.sync_status() == be.sync_status()
+
+
+def test_tunings_bitwise_identical():
+    shapes = [(200, 130), (64, 64), (513, 70)]
+    sts = states(shapes, 700, False)
+    ref = None
+    for tun in (dict(rows=8, vec=1, order=0), dict(rows=16, vec=2, order=1, occupancy=4, prefetch=2),
+                dict(rows=32, vec=4, order=0, prefetch=3), dict(rows=5, vec=2, order=1, prefetch=1)):
+        b = make_batch(shapes, sts, "f32", sw.REFLECT, dict(variant=2, **tun))
+        b.step(13)
+        out = [[a.numpy() for a in b.get_state(i, halo=True)] for i in range(len(shapes))] + [b.sync_status()]
+        if ref is None:
+            ref = out
+        else:
+            for gi in range(len(shapes)):
+                for x, y in zip(ref[gi], out[gi]):
+                    assert np.array_equal(x, y), (tun, gi)
+            assert ref[-1] == out[-1]
+
+
+def test_per_grid_sticky_flag_and_dt():
+    shapes = [(64, 64), (64, 64), (128, 64)]
+    sts = states(shapes, 900, False)
+    h, hu, hv = sts[1]
+    h = h.clone()
+    h[10, 10] = -1.0
+    sts[1] = (h, hu, hv)
+    b = make_batch(shapes, sts, "f32", sw.REFLECT, dict(variant=2))
+    b.step(3)
+    t, n, u = b.sync_status(raise_unstable=False)
+    assert u == [0, 1, 0] and n == [3, 3, 3]
+    with pytest.raises(sw.Unstable):
+        b.sync_status()
+    assert t[0] != t[2]            # independent CFL dt per grid
