@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gcell-updates/s and % HBM roofline; surrogate speedup at L2(h)≤1e-2"
 HBM_PEAK_GBS = 8000.0
-FUSED_SRC = os.path.join(ROOT, "paper_1107_2157_amd", "csrc", "sw_fused.hip")
+FUSED_SRC = [os.path.join(ROOT, "paper_1107_2157_amd", "csrc", f) for f in ("sw_fused.hip", "sw_tile.h", "sw_common.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused_swe16384_f32.json")
 
 WORKLOADS = {
@@ -42,9 +42,12 @@ WORKLOADS = {
 }
 
 
-def source_hash(path: str) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_hash(paths) -> str:
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def make_solver(name, sw, ics, torch):
@@ -107,6 +110,50 @@ def run_workload(name, steps, warmup, sw, ics, torch, tune_cache, fixed=None):
     return out
 
 
+def run_batch(steps, sw, ics, torch, tune_cache, per_grid_steps):
+    """Batched workload: 512 grids, sides 64*(1 + floor(16u)) (seed 4), each
+    with its own 1-8 Gaussian bumps (seed 4000 + k), FP32, reflective walls.
+    One hipGraph launch per call covering every grid, against per-grid
+    launches (one sw_step call per grid on the same stream)."""
+    sides = ics.batch_sides(512)
+    cells = sum(s * s for s in sides)
+    b = sw.Batch(sides, dtype="f32")
+    for k, n in enumerate(sides):
+        b.set_state(k, *ics.bumps_state(n, n, seed=ics.SEED_BATCH_GRID0 + k, periodic=False, device="cuda"))
+    torch.cuda.synchronize()
+    tuning = b.autotune(steps_per_trial=3, cache_path=tune_cache)
+    b.step(2)                                          # warm: captures the graph for this call shape
+    b.step(steps)                                      # (captures the graph for `steps`)
+    t = timed(torch, lambda: b.step(steps))
+    finite = True
+    try:
+        b.sync_status()
+    except sw.Unstable:
+        finite = False
+    del b
+    torch.cuda.empty_cache()
+    # per-grid launches: every grid its own context and planes, `per_grid_steps` steps
+    solvers = []
+    for k, n in enumerate(sides):
+        s = sw.Solver(n, n, dtype="f32")
+        s.set_state(*ics.bumps_state(n, n, seed=ics.SEED_BATCH_GRID0 + k, periodic=False, device="cuda"))
+        solvers.append(s)
+    for s in solvers:
+        s.step(1)
+    t_pg = timed(torch, lambda: [s.step(per_grid_steps) for s in solvers])
+    del solvers
+    torch.cuda.empty_cache()
+    per_grid_rate = cells * per_grid_steps / t_pg / 1e9
+    rate = cells * steps / t / 1e9
+    return {"workload": "batch512-f32-reflect", "grids": 512, "cells_per_step": cells, "steps": steps,
+            "seconds": t, "gcells_per_s": rate, "ms_per_step": 1e3 * t / steps, "tuning": tuning,
+            "finite": finite, "per_grid_launches": {"steps": per_grid_steps, "seconds": t_pg,
+                                                     "gcells_per_s": per_grid_rate,
+                                                     "launches": 512 * (per_grid_steps + 2)},
+            "speedup_vs_per_grid": rate / per_grid_rate,
+            "hbm_frac": rate * 24 / HBM_PEAK_GBS}
+
+
 def copy_bandwidth(torch, nbytes):
     """Device copy of nbytes (read + write) with torch: attainable streaming BW."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -149,6 +196,7 @@ def main():
     ap.add_argument("--workload", default="swe16384-f32-periodic", choices=sorted(WORKLOADS))
     ap.add_argument("--no-also", action="store_true", help="skip the secondary 4096^2 FP32/FP64 runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 512-grid run")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1107_2157_amd", "tune_cache_gfx950.txt"),
                     help="autotuner cache (launch shapes found by sw_autotune on MI355X; missing keys are tuned "
                          "and appended)")
@@ -196,6 +244,9 @@ def main():
             also.append({k: r[k] for k in ("workload", "dtype", "steps", "gcells_per_s", "ms_per_step",
                                             "kernel_us", "finite", "tuning")} |
                         {"hbm_frac": r["alg_bytes_per_launch"] / (r["kernel_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS})
+
+    if not args.no_also and not args.no_batch and args.workload == "swe16384-f32-periodic":
+        also.append(run_batch(500, sw, ics, torch, args.tune_cache, per_grid_steps=50))
 
     line = {
         "metric": METRIC,
