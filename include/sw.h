@@ -208,6 +208,12 @@ sw_status sw_batch_step(sw_batch *batch, int32_t nsteps, void *stream);
  * steps and the sticky flag.  Returns SW_EUNSTABLE if any grid is flagged. */
 sw_status sw_batch_sync_status(sw_batch *batch, void *stream, double *t, int64_t *steps, int32_t *unstable);
 sw_status sw_batch_reset_time(sw_batch *batch, void *stream);
+/* Async, for batches whose grids all have the same size: copy every grid's
+ * interior of the current buffer to (export) or from (import) one dense
+ * device array [n][3][ny][nx] of the batch's dtype.  Import leaves the halos
+ * stale; sw_batch_step refills them.  Errors: SW_EINVAL (sizes differ, NULL). */
+sw_status sw_batch_export(sw_batch *batch, void *dense, void *stream);
+sw_status sw_batch_import(sw_batch *batch, const void *dense, void *stream);
 /* Launch shape for every grid (variant must be 0 or 2; order: 0 = LPT
  * tile table, largest grids first; 1 = round-robin over grids). */
 sw_status sw_batch_set_tuning(sw_batch *batch, const sw_tuning *tuning);
@@ -218,6 +224,76 @@ sw_status sw_batch_set_graph(sw_batch *batch, int32_t enable);
  * the per-grid scalars; allocates a temporary copy of one buffer region). */
 sw_status sw_batch_autotune(sw_batch *batch, int32_t steps_per_trial, const char *cache_path, void *stream,
                             sw_tuning *best);
+
+/* ---------------------------------------------------------------------------
+ * Learned surrogate (not part of the paper): a residual network that maps
+ * U^n to U^{n+jump} on H x W grids, jumping `jump` solver steps at a time:
+ *   x = normalise(U^n)  (channel c: (u_c - in_offset_c) / in_scale_c; the
+ *       input's one-cell halo holds the boundary ghosts);
+ *   delta = conv6(relu(conv5(... relu(conv1(x)))))   3x3 "same" convolutions,
+ *       3 -> 32 -> 32 -> 32 -> 32 -> 32 -> 3 channels, zero padding in the
+ *       hidden layers, BF16 weights and activations, FP32 accumulation;
+ *   U^{n+jump} = U^n + delta * out_scale   (residual added in FP32).
+ * Parameters: one FP32 master vector (device), layer after layer: weights
+ * W[co][tap][ci] (tap = 3 * ky + kx, cross-correlation) then biases b[co];
+ * 38 755 values.  Training (sw_surrogate_train_step) minimises the mean
+ * squared error of the normalised delta with Adam (beta 0.9 / 0.999, eps
+ * 1e-8), gradients by the library's own backward kernels. */
+typedef struct {
+    int32_t layers;      /* must be 6 */
+    int32_t hidden;      /* must be 32 */
+    int32_t jump;        /* solver steps replaced by one network application (even, e.g. 8) */
+    int32_t bc_x, bc_y;  /* sw_bc of the input ghosts (must match the batch it advances) */
+    int32_t reserved;
+    uint64_t seed;       /* weight initialisation (He-normal; output layer x 0.1) */
+} sw_net_cfg;
+
+/* Gate of a surrogate jump, per grid: the jump is rejected, and the plain
+ * solver takes it instead, if |M' - M| / M > mass_rel_tol (M = sum of h),
+ * if any depth <= hmin, or if any value is non-finite.  project_mass != 0
+ * first removes the mean of the predicted dh, so mass is kept exactly. */
+typedef struct {
+    double mass_rel_tol;
+    double hmin;
+    int32_t project_mass;
+    int32_t reserved;
+} sw_gate;
+
+typedef struct sw_net sw_net;
+
+/* Network for H x W grids (W a multiple of 64), up to max_batch grids per
+ * call; allocates its weights and activation workspace (about
+ * 12 * 32 * 2 * max_batch * (H + 2) * (W + 2) bytes).
+ * Errors: SW_EINVAL, SW_ENOTSUP (other depth / width), SW_ENOMEM, SW_EHIP. */
+sw_status sw_surrogate_create(const sw_net_cfg *cfg, int32_t H, int32_t W, int32_t max_batch, sw_net **out);
+sw_status sw_surrogate_destroy(sw_net *net);
+/* Device pointer to the FP32 master parameters and their count.  After
+ * writing them (e.g. loading saved weights) call sw_surrogate_sync_weights. */
+sw_status sw_surrogate_params(sw_net *net, float **master_dev, int64_t *count);
+sw_status sw_surrogate_sync_weights(sw_net *net, void *stream);
+/* Host arrays of 3 floats each; scales must be > 0. */
+sw_status sw_surrogate_set_norm(sw_net *net, const float in_offset[3], const float in_scale[3],
+                                const float out_scale[3]);
+/* Async.  u: device FP32 frames [B][3][H][W] (h, hu, hv); delta (device, may
+ * be NULL): the normalised prediction as FP32 [B][H][W][4] (4th channel 0). */
+sw_status sw_surrogate_forward(sw_net *net, const float *u, int32_t B, float *delta, void *stream);
+/* Device pointer to the last forward pass's activations: layer 0 = network
+ * input (BF16 NHWC, 8 channels, with halo), 1..5 = hidden layers (BF16 NHWC,
+ * 32 channels, with halo), 6 = delta (FP32 [B][H][W][4]). */
+sw_status sw_surrogate_activation(sw_net *net, int32_t layer, const void **ptr, int64_t *bytes);
+/* Async.  Loss (device float, may be NULL) and gradient (device, nparams
+ * floats, may be NULL) of the pair (u -> u8), without updating. */
+sw_status sw_surrogate_grad(sw_net *net, const float *u, const float *u8, int32_t B, float *grad, float *loss,
+                            void *stream);
+/* Async.  One Adam step on the pair (u -> u8) with learning rate lr. */
+sw_status sw_surrogate_train_step(sw_net *net, const float *u, const float *u8, int32_t B, float lr, float *loss,
+                                  void *stream);
+/* Async.  Advance every grid of an FP32 batch (all H x W, same boundary
+ * conditions) by nsteps (a multiple of jump) in jumps; each jump is gated per
+ * grid and rejected grids take jump solver steps instead.  fallbacks (device
+ * int32[n], may be NULL) is incremented per rejected jump.  No host sync. */
+sw_status sw_surrogate_advance(sw_net *net, sw_batch *solver, int32_t nsteps, const sw_gate *gate,
+                               int32_t *fallbacks, void *stream);
 
 const char *sw_strerror(sw_status status);
 const char *sw_last_error_detail(void);

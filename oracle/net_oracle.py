@@ -1,0 +1,156 @@
+"""CPU FP64 oracle of the learned surrogate (forward, loss, gradients).
+
+TEST INFRASTRUCTURE ONLY (tests, smoke check, benchmark baseline); shares
+nothing with the HIP path.  Written from the definition of the network:
+
+* input: ``x_c = (u_c - offset_c) / scale_c`` for ``u = (h, hu, hv)``, with a
+  one-cell halo holding the boundary ghosts (reflective: mirror with the
+  wall-normal momentum negated; periodic: wrap), arranged NHWC;
+* five hidden layers ``A_l = relu(conv3x3(A_{l-1}, W_l) + b_l)`` with zero
+  padding, then ``delta = conv3x3(A_5, W_6) + b_6`` (3 channels);
+* ``conv3x3(x, W)[p, co] = sum_{tap, ci} x[p + (tap // 3 - 1, tap % 3 - 1), ci] W[co, tap, ci]``
+  (cross-correlation; tap = 3 * ky + kx);
+* loss: mean over pixels and the three channels of ``(delta - target)^2``,
+  ``target = (u8 - u) / out_scale``;
+* gradients by the chain rule: ``dZ_6 = 2 (delta - target) / N``,
+  ``dW_l[co, tap, ci] = sum_p dZ_l[p, co] A_{l-1}[p + tap, ci]``,
+  ``db_l = sum_p dZ_l``, ``dA_{l-1}[q, ci] = sum_{tap, co} dZ_l[q - tap, co] W_l[co, tap, ci]``,
+  ``dZ_{l-1} = dA_{l-1} * (A_{l-1} > 0)``.
+
+``bf16=True`` rounds the tensors the GPU stores in BF16 (input, weights,
+hidden activations, gradient seeds and hidden-layer gradients) to BF16 after
+computing them, so the oracle sees the same quantised values; accumulation is
+FP64 throughout.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+LAYERS = [(3, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 3)]
+
+
+def nparams() -> int:
+    return sum(co * 9 * ci + co for ci, co in LAYERS)
+
+
+def unpack(params):
+    """Flat master vector -> [(W[co][9][ci], b[co])] per layer."""
+    p = np.asarray(params, dtype=np.float64)
+    out, off = [], 0
+    for ci, co in LAYERS:
+        w = p[off:off + co * 9 * ci].reshape(co, 9, ci)
+        off += co * 9 * ci
+        b = p[off:off + co]
+        off += co
+        out.append((w, b))
+    return out
+
+
+def bf16(a):
+    """Round to bfloat16 (nearest, ties to even) via FP32, as the GPU converts."""
+    f = np.asarray(a, dtype=np.float32)
+    bits = f.view(np.uint32).astype(np.uint64)
+    lsb = (bits >> 16) & 1
+    r = ((bits + 0x7FFF + lsb) >> 16) << 16
+    return (r.astype(np.uint32)).view(np.float32).astype(np.float64)
+
+
+def input_tensor(u, offset, scale, bc_x=0, bc_y=0, quant=True):
+    """[B][3][H][W] state -> normalised NHWC input with halo [B][H+2][W+2][3]."""
+    u = np.asarray(u, dtype=np.float32)
+    B, _, H, W = u.shape
+    ys = np.array([H - 1 if bc_y else 0] + list(range(H)) + [0 if bc_y else H - 1])
+    xs = np.array([W - 1 if bc_x else 0] + list(range(W)) + [0 if bc_x else W - 1])
+    fy = np.ones(H + 2, dtype=np.float32)
+    fx = np.ones(W + 2, dtype=np.float32)
+    if not bc_y:
+        fy[0] = fy[-1] = -1
+    if not bc_x:
+        fx[0] = fx[-1] = -1
+    g = u[:, :, ys][:, :, :, xs]                      # [B][3][H+2][W+2]
+    g = g.copy()
+    g[:, 1] *= fx[None, None, :]
+    g[:, 2] *= fy[None, :, None]
+    x = np.empty((B, H + 2, W + 2, 3), dtype=np.float32)
+    for c in range(3):
+        x[..., c] = (g[:, c] - np.float32(offset[c])) / np.float32(scale[c])
+    return bf16(x) if quant else x.astype(np.float64)
+
+
+def pad(a):
+    B, H, W, C = a.shape
+    out = np.zeros((B, H + 2, W + 2, C))
+    out[:, 1:-1, 1:-1] = a
+    return out
+
+
+def conv3x3(xh, w, b=None):
+    """xh: [B][H+2][W+2][ci] (halo), w: [co][9][ci] -> [B][H][W][co]."""
+    B, Hp, Wp, _ = xh.shape
+    H, W = Hp - 2, Wp - 2
+    out = np.zeros((B, H, W, w.shape[0]))
+    for tap in range(9):
+        dy, dx = tap // 3, tap % 3
+        out += np.tensordot(xh[:, dy:dy + H, dx:dx + W, :], w[:, tap, :], axes=([3], [1]))
+    if b is not None:
+        out += b
+    return out
+
+
+def forward(params, u, offset, scale, bc_x=0, bc_y=0, bf16_mode=True):
+    """Returns (activations with halo [x0, A1..A5], delta [B][H][W][3])."""
+    q = bf16 if bf16_mode else (lambda a: np.asarray(a, dtype=np.float64))
+    layers = [(q(w), b) for w, b in unpack(params)]
+    x = input_tensor(u, offset, scale, bc_x, bc_y, quant=bf16_mode)
+    acts = [x]
+    a = x
+    for l, (w, b) in enumerate(layers):
+        z = conv3x3(a, w, b)
+        if l == len(layers) - 1:
+            return acts, z
+        a = pad(q(np.maximum(z, 0.0)))
+        acts.append(a)
+
+
+def loss_and_grad(params, u, u8, offset, scale, out_scale, bc_x=0, bc_y=0, bf16_mode=True):
+    """MSE loss and the gradient (flat, master layout) of one pair."""
+    q = bf16 if bf16_mode else (lambda a: np.asarray(a, dtype=np.float64))
+    layers = [(q(w), b) for w, b in unpack(params)]
+    acts, delta = forward(params, u, offset, scale, bc_x, bc_y, bf16_mode)
+    u = np.asarray(u, dtype=np.float32)
+    u8 = np.asarray(u8, dtype=np.float32)
+    tgt = np.stack([(u8[:, c] - u[:, c]) / np.float32(out_scale[c]) for c in range(3)], axis=-1).astype(np.float64)
+    n = delta.shape[0] * delta.shape[1] * delta.shape[2] * 3
+    d = delta - tgt
+    loss = float(np.sum(d * d) / n)
+    dz = q(2.0 * d / n)
+    grads = [None] * len(layers)
+    for l in range(len(layers) - 1, -1, -1):
+        w, _ = layers[l]
+        a_in = acts[l]
+        H, W = dz.shape[1], dz.shape[2]
+        gw = np.zeros_like(w)
+        for tap in range(9):
+            dy, dx = tap // 3, tap % 3
+            gw[:, tap, :] = np.tensordot(dz, a_in[:, dy:dy + H, dx:dx + W, :], axes=([0, 1, 2], [0, 1, 2]))
+        gb = dz.sum(axis=(0, 1, 2))
+        grads[l] = (gw, gb)
+        if l == 0:
+            break
+        # dA[q] = sum_tap dZ[q - off(tap)] W[tap]: correlation of the padded dZ with the flipped kernel
+        wflip = w[:, ::-1, :].transpose(2, 1, 0)          # [ci][tap'][co], tap' = 8 - tap
+        da = conv3x3(pad(dz), wflip)
+        dz = q(da * (acts[l][:, 1:-1, 1:-1, :] > 0))
+    flat = np.concatenate([np.concatenate([gw.ravel(), gb]) for gw, gb in grads])
+    return loss, flat
+
+
+def init_params(seed: int, out_gain: float = 0.1):
+    """He-normal test weights (fan-in 9 * cin), small random biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for l, (ci, co) in enumerate(LAYERS):
+        sd = np.sqrt(2.0 / (9 * ci)) * (out_gain if l == len(LAYERS) - 1 else 1.0)
+        parts.append(rng.standard_normal(co * 9 * ci) * sd)
+        parts.append(rng.standard_normal(co) * 0.05)
+    return np.concatenate(parts)

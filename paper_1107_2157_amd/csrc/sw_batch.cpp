@@ -151,12 +151,18 @@ SwBatchLaunch launch_of(const sw_batch *b, const Resolved &r, int cur, int step)
     return a;
 }
 
-// reset + prologue + nsteps step launches on stream s, starting from buffer cur
-sw_status enqueue(const sw_batch *b, const Resolved &r, int nsteps, int cur, hipStream_t s) {
+// reset + prologue + nsteps step launches on stream s, starting from buffer
+// cur; active (device, optional) restricts the work to some grids
+sw_status enqueue(const sw_batch *b, const Resolved &r, int nsteps, int cur, hipStream_t s,
+                  const int32_t *active = nullptr) {
     BHIP(sw_batch_launch_reset(b->d_sc, b->n, 0, s));
-    BHIP(sw_batch_launch_prologue(launch_of(b, r, cur, 0), r.vec, s));
+    SwBatchLaunch p = launch_of(b, r, cur, 0);
+    p.active = active;
+    BHIP(sw_batch_launch_prologue(p, r.vec, s));
     for (int k = 0; k < nsteps; ++k) {
-        BHIP(sw_batch_launch_step(launch_of(b, r, cur, k), r.vec, r.minw, r.pd, s));
+        SwBatchLaunch a = launch_of(b, r, cur, k);
+        a.active = active;
+        BHIP(sw_batch_launch_step(a, r.vec, r.minw, r.pd, s));
         cur ^= 1;
     }
     return SW_OK;
@@ -174,6 +180,32 @@ sw_status check_bound(const sw_batch *b) {
 }
 
 }  // namespace
+
+int sw_batch_internal_info(const sw_batch *b, SwBatchInfo *info) {
+    if (!b || !info) return sw_fail(SW_EINVAL, "batch: NULL");
+    if (!b->arena) return sw_fail(SW_EINVAL, "batch: no arena bound");
+    info->d_grids = b->d_grids;
+    info->n = b->n;
+    info->cur = b->cur;
+    info->dtype = (int)b->opts.dtype;
+    info->bc_x = (int)b->opts.bc_x;
+    info->bc_y = (int)b->opts.bc_y;
+    info->same_nx = b->grids[0].nx;
+    info->same_ny = b->grids[0].ny;
+    for (auto &g : b->grids)
+        if (g.nx != info->same_nx || g.ny != info->same_ny) info->same_nx = info->same_ny = -1;
+    return SW_OK;
+}
+
+int sw_batch_internal_step_masked(sw_batch *b, int nsteps, const int32_t *active, hipStream_t s) {
+    sw_status st = check_bound(b);
+    if (st != SW_OK) return st;
+    if (nsteps < 0 || (nsteps & 1)) return sw_fail(SW_EINVAL, "batch: masked steps must be even (%d)", nsteps);
+    Resolved r;
+    if ((st = resolve(b, b->tuning, &r)) != SW_OK) return st;
+    if ((st = build_tiles(b, r)) != SW_OK) return st;
+    return enqueue(b, r, nsteps, b->cur, s, active);
+}
 
 extern "C" {
 
@@ -370,6 +402,23 @@ sw_status sw_batch_sync_status(sw_batch *b, void *stream, double *t, int64_t *st
     }
     if (any) return sw_fail(SW_EUNSTABLE, "batch: a grid produced h <= 0 or a non-finite value");
     return SW_OK;
+}
+
+static sw_status batch_copy(sw_batch *b, void *dense, int to_dense, void *stream) {
+    sw_status st = check_bound(b);
+    if (st != SW_OK) return st;
+    if (!dense) return sw_fail(SW_EINVAL, "batch export/import: NULL buffer");
+    for (auto &g : b->grids)
+        if (g.nx != b->grids[0].nx || g.ny != b->grids[0].ny)
+            return sw_fail(SW_EINVAL, "batch export/import: grids differ in size");
+    BHIP(sw_batch_launch_copy(b->d_grids, b->cur, b->n, b->grids[0].nx, b->grids[0].ny, (int)b->opts.dtype, dense,
+                              to_dense, (hipStream_t)stream));
+    return SW_OK;
+}
+
+sw_status sw_batch_export(sw_batch *b, void *dense, void *stream) { return batch_copy(b, dense, 1, stream); }
+sw_status sw_batch_import(sw_batch *b, const void *dense, void *stream) {
+    return batch_copy(b, const_cast<void *>(dense), 0, stream);
 }
 
 sw_status sw_batch_reset_time(sw_batch *b, void *stream) {

@@ -44,6 +44,7 @@ __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_batch_step(SwBat
     const int tile = batch_tile_index();
     if (tile >= a.ntiles) return;                 // whole wave leaves: no barriers are used
     const SwBatchTile tt = a.tiles[tile];
+    if (a.active && !a.active[tt.grid]) return;
     const SwBatchGrid &gd = a.grids[tt.grid];
     const double dt = batch_dt(a, tt.grid);
     TileArgs t;
@@ -82,6 +83,7 @@ __global__ __launch_bounds__(256) void k_batch_prologue(SwBatchLaunch a, int til
     const int tile = batch_tile_index();
     if (tile >= a.ntiles) return;
     const SwBatchTile tt = a.tiles[tile];
+    if (a.active && !a.active[tt.grid]) return;
     const SwBatchGrid &gd = a.grids[tt.grid];
     const int lane = threadIdx.x & 63;
     T *P[3] = {(T *)gd.plane[a.cur][0], (T *)gd.plane[a.cur][1], (T *)gd.plane[a.cur][2]};
@@ -116,6 +118,23 @@ __global__ void k_batch_reset(SwBatchScalars *sc, int n, int clear_time) {
     }
 }
 
+// Dense [n][3][ny][nx] <-> every grid's interior in buffer `cur`.
+template <typename T, bool EXPORT>
+__global__ __launch_bounds__(256) void k_batch_copy(const SwBatchGrid *grids, int cur, int n, int nx, int ny, T *dense) {
+    const int64_t per = (int64_t)3 * ny * nx;
+    const int64_t total = per * n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int g = (int)(i / per);
+        int64_t r = i - (int64_t)g * per;
+        const int k = (int)(r / ((int64_t)ny * nx));
+        r -= (int64_t)k * ny * nx;
+        const int y = (int)(r / nx), x = (int)(r - (int64_t)y * nx);
+        T *p = (T *)grids[g].plane[cur][k] + (int64_t)y * grids[g].pitch + x;
+        if (EXPORT) dense[i] = *p;
+        else *p = dense[i];
+    }
+}
+
 unsigned batch_blocks(int ntiles) {
     int64_t blocks = ((int64_t)ntiles + 3) / 4;
     return (unsigned)((blocks + 7) / 8 * 8);
@@ -128,6 +147,20 @@ hipError_t launch_batch_t(const SwBatchLaunch &a, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t sw_batch_launch_copy(const SwBatchGrid *grids, int cur, int n, int nx, int ny, int dtype, void *dense,
+                                int to_dense, hipStream_t s) {
+    int64_t blocks = ((int64_t)3 * n * nx * ny + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (dtype) {
+        if (to_dense) k_batch_copy<double, true><<<(unsigned)blocks, 256, 0, s>>>(grids, cur, n, nx, ny, (double *)dense);
+        else k_batch_copy<double, false><<<(unsigned)blocks, 256, 0, s>>>(grids, cur, n, nx, ny, (double *)dense);
+    } else {
+        if (to_dense) k_batch_copy<float, true><<<(unsigned)blocks, 256, 0, s>>>(grids, cur, n, nx, ny, (float *)dense);
+        else k_batch_copy<float, false><<<(unsigned)blocks, 256, 0, s>>>(grids, cur, n, nx, ny, (float *)dense);
+    }
+    return hipGetLastError();
+}
 
 hipError_t sw_batch_launch_reset(SwBatchScalars *sc, int n, int clear_time, hipStream_t s) {
     if (n <= 0) return hipSuccess;

@@ -42,8 +42,24 @@ struct SwBatchLaunch {
     int32_t rows;     // rows per tile
     double g, dx, dy, cfl, dt_fixed;
     int32_t bc_x, bc_y, dtype, pad;
+    const int32_t *active;   // optional per-grid mask: grids with 0 are skipped entirely
 };
 
 hipError_t sw_batch_launch_reset(SwBatchScalars *sc, int n, int clear_time, hipStream_t s);
 hipError_t sw_batch_launch_prologue(const SwBatchLaunch &a, int vec, hipStream_t s);
 hipError_t sw_batch_launch_step(const SwBatchLaunch &a, int vec, int minw, int pd, hipStream_t s);
+hipError_t sw_batch_launch_copy(const SwBatchGrid *grids, int cur, int n, int nx, int ny, int dtype, void *dense,
+                                int to_dense, hipStream_t s);
+
+// Host-side hooks of the batch object for the surrogate (sw_batch.cpp).
+struct sw_batch;
+struct SwBatchInfo {
+    const SwBatchGrid *d_grids;
+    int n, cur, dtype, bc_x, bc_y;
+    int same_nx, same_ny;          // common grid size, or -1 if sizes differ
+};
+int sw_batch_internal_info(const sw_batch *b, SwBatchInfo *info);   // returns sw_status
+// Eager: reset, prologue and nsteps steps for the grids with active[g] != 0
+// (device array), starting from the current buffer.  Does not flip the
+// batch's current buffer (nsteps must be even).
+int sw_batch_internal_step_masked(sw_batch *b, int nsteps, const int32_t *active, hipStream_t s);

@@ -44,10 +44,21 @@ __device__ __forceinline__ U3<T> add_transverse(U3<T> f, U3<T> lo0, U3<T> lo1, U
             fma(-l4, (hi0.q + hi1.q) - (lo0.q + lo1.q), f.q)};
 }
 
-// Largest signal speed of a cell: max(|u|, |v|) + sqrt(g h).
+// Reciprocal and square root of the step kernels: the hardware's
+// approximations in FP32 (v_rcp_f32, v_sqrt_f32, about 1 ulp), correctly
+// rounded division and sqrt in FP64.
+template <typename T> __device__ __forceinline__ T fast_rcp(T x);
+template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double fast_rcp<double>(double x) { return 1.0 / x; }
+template <typename T> __device__ __forceinline__ T fast_sqrt(T x);
+template <> __device__ __forceinline__ float fast_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <> __device__ __forceinline__ double fast_sqrt<double>(double x) { return sqrt(x); }
+
+// Largest signal speed of a cell: max(|u|, |v|) + sqrt(g h).  Every kernel
+// that feeds the CFL max uses this one formula, so a run split over several
+// calls takes bitwise the same dt as one call.
 template <typename T> __device__ __forceinline__ T signal_speed(U3<T> c, T g) {
-    T a = fmax(fabs(c.p), fabs(c.q)) / c.h;
-    return a + sqrt(g * c.h);
+    return fmax(fabs(c.p), fabs(c.q)) * fast_rcp(c.h) + fast_sqrt(g * c.h);
 }
 
 // Ghost cells fed by interior cell (i, j) holding c, under the boundary

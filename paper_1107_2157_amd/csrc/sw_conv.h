@@ -1,0 +1,78 @@
+// Internal interface of the learned surrogate's kernels (host <-> device).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "sw_batch_internal.h"
+
+enum { SW_CONV_RELU_BF16 = 0, SW_CONV_MASK_BF16 = 1, SW_CONV_F32 = 2 };
+
+// One 3x3 convolution launch (see sw_conv.hip for layouts).
+struct SwConvArgs {
+    const void *x;       // BF16 NHWC input with halo, CIN channels
+    const void *w;       // BF16 [COUT padded to 16][K padded to 32] implicit-GEMM weights
+    const float *bias;   // FP32 [COUT] (RELU and F32 modes)
+    void *y;             // BF16 NHWC output with halo, COUT channels (RELU / MASK modes)
+    float *yf;           // FP32 [B][H][W][4] output (F32 mode)
+    const void *mask;    // BF16 NHWC with halo, COUT channels: output kept where mask > 0 (MASK mode)
+    int B, H, W;
+};
+hipError_t sw_conv3x3(const SwConvArgs &a, int cin, int cout, int mode, hipStream_t s);
+
+// Per-channel affine normalisation of the state: x = (u - offset) / scale.
+struct SwNorm {
+    float in_off[3], in_scale[3], out_scale[3];
+};
+
+// Dense FP32 frames [B][3][H][W] -> network input X0 (BF16 NHWC, 8 channels,
+// halo = reflective / periodic ghost values) and, if u8 != nullptr, the target
+// (u8 - u) / out_scale as FP32 [B][H][W][4].
+hipError_t sw_sur_prep_dense(const float *u, const float *u8, int B, int H, int W, int bc_x, int bc_y, SwNorm nrm,
+                             void *x0, float *target, hipStream_t s);
+// Batch planes (current buffer, halo filled) of grids [0, B) -> X0.
+hipError_t sw_sur_prep_planes(const SwBatchGrid *grids, int cur, int B, int H, int W, SwNorm nrm, void *x0,
+                              hipStream_t s);
+// MSE loss over the three channels: per-block partial sums into partial[nblocks],
+// and dZ = 2 (pred - target) / (3 B H W) as BF16 NHWC with halo, 8 channels.
+hipError_t sw_sur_loss(const float *pred, const float *target, int B, int H, int W, float *partial, int nblocks,
+                       void *dz, hipStream_t s);
+hipError_t sw_sur_reduce_sum(const float *partial, int n, float *out, hipStream_t s);
+// Weight gradient of one layer: dW[co][tap][ci] = sum_p dZ[p][co] A[p + tap][ci],
+// db[co] = sum_p dZ[p][co], written into grad (logical layout, W then b).
+hipError_t sw_sur_wgrad(const void *dz, int coutp, int cout, const void *a, int cinp, int cin, int B, int H, int W,
+                        float *partial, int nblocks, float *grad_w, float *grad_b, hipStream_t s);
+// Adam on the FP32 master parameters and refresh of the BF16 forward /
+// input-gradient weight layouts.
+struct SwLayerDesc {
+    int cin, cinp, cout, coutp;   // real and padded channel counts
+    int64_t w_off, b_off;         // offsets in the master vector
+    void *wk;                     // BF16 [coutp16][kp] forward layout
+    void *wd;                     // BF16 [cin padded to 32][kp'] input-gradient layout (nullptr for layer 1)
+    int kp, kpd, cdp;             // forward K (padded), input-gradient K (padded), dgrad input channels (8 or 32)
+};
+struct SwAdam {
+    float lr, beta1, beta2, eps;
+    float c1, c2;                 // 1 / (1 - beta^t) bias corrections
+};
+hipError_t sw_sur_adam(float *master, float *m, float *v, const float *grad, int64_t n, SwAdam ad, hipStream_t s);
+hipError_t sw_sur_relayout(const float *master, const SwLayerDesc *layers, int nlayers, int64_t total_weights,
+                           hipStream_t s);
+
+// Rollout: per grid, sum of predicted dh (for the mass projection), the
+// update U' = U + denorm(delta) (- mean dh if projecting) written into the
+// other buffer, and the gate's mass / min-h / finiteness statistics.
+struct SwGateStats {
+    double mass_old, mass_new, dh_sum;
+    float hmin;
+    unsigned int nonfinite;
+    int fallback;
+    int pad;
+};
+hipError_t sw_sur_delta_sum(const float *delta, int B, int H, int W, SwGateStats *st, hipStream_t s);
+hipError_t sw_sur_apply(const float *delta, const SwBatchGrid *grids, int cur, int B, int H, int W, SwNorm nrm,
+                        int project, int bcx, int bcy, SwGateStats *st, hipStream_t s);
+hipError_t sw_sur_gate(SwGateStats *st, int B, double mass_tol, double hmin, int *active, int *fallbacks,
+                       hipStream_t s);
+// Accepted grids: copy the prediction (buffer cur ^ 1) into buffer cur.
+hipError_t sw_sur_accept(const SwBatchGrid *grids, int cur, int B, int H, int W, const int *active, hipStream_t s);
+hipError_t sw_sur_zero_stats(SwGateStats *st, int B, hipStream_t s);

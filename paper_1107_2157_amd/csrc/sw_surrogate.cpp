@@ -1,0 +1,344 @@
+// Learned surrogate, host side: a 6-layer 3x3 convolutional residual network
+// (3 -> 32 -> 32 -> 32 -> 32 -> 32 -> 3, ReLU, BF16 weights and activations,
+// FP32 accumulation) that maps U^n to U^{n+8}, trained by the library's own
+// forward / backward kernels, and its gated rollout on a batch of grids with
+// the plain solver as fallback.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <random>
+#include <vector>
+
+#include "../../include/sw.h"
+#include "sw_conv.h"
+
+sw_status sw_fail(sw_status s, const char *fmt, ...);
+
+#define SHIP(call)                                                                                  \
+    do {                                                                                            \
+        hipError_t e_ = (call);                                                                     \
+        if (e_ != hipSuccess) return sw_fail(SW_EHIP, "%s: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+namespace {
+constexpr int kLayers = 6;
+constexpr int kHidden = 32;
+constexpr int kLossBlocks = 1024;
+constexpr int kWgradBlocks = 1024;
+}  // namespace
+
+struct sw_net {
+    sw_net_cfg cfg{};
+    int H = 0, W = 0, maxB = 0, device = 0;
+    int64_t nparams = 0, nweights = 0;
+    float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    float *loss_partial = nullptr, *scratch_loss = nullptr;
+    float *wpartial = nullptr;
+    SwLayerDesc L[kLayers]{};
+    SwLayerDesc *L_dev = nullptr;
+    void *x0 = nullptr, *act[kLayers - 1] = {}, *dz[2] = {}, *dz6 = nullptr;
+    float *delta = nullptr, *target = nullptr;
+    SwGateStats *stats = nullptr;
+    int32_t *active = nullptr;
+    SwNorm nrm{};
+    int64_t adam_t = 0;
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+sw_status dalloc(sw_net *n, void **p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return sw_fail(e == hipErrorOutOfMemory ? SW_ENOMEM : SW_EHIP, "surrogate: %s", hipGetErrorString(e));
+    n->allocs.push_back(*p);
+    e = hipMemset(*p, 0, bytes);
+    if (e != hipSuccess) return sw_fail(SW_EHIP, "surrogate: %s", hipGetErrorString(e));
+    return SW_OK;
+}
+
+size_t act_bytes(const sw_net *n, int B, int ch) { return (size_t)B * (n->H + 2) * (n->W + 2) * ch * 2; }
+
+sw_status use_dev(const sw_net *n) {
+    int d = -1;
+    SHIP(hipGetDevice(&d));
+    if (d != n->device) SHIP(hipSetDevice(n->device));
+    return SW_OK;
+}
+
+sw_status conv(const sw_net *n, int layer, const void *x, void *y, float *yf, const void *mask, int B, int mode,
+               bool dgrad, hipStream_t s) {
+    const SwLayerDesc &L = n->L[layer];
+    SwConvArgs a{};
+    a.x = x;
+    a.y = y;
+    a.yf = yf;
+    a.mask = mask;
+    a.B = B;
+    a.H = n->H;
+    a.W = n->W;
+    if (!dgrad) {
+        a.w = L.wk;
+        a.bias = n->master + L.b_off;
+        SHIP(sw_conv3x3(a, L.cinp, L.cout, mode, s));
+    } else {
+        a.w = L.wd;
+        SHIP(sw_conv3x3(a, L.cdp, L.cin, mode, s));
+    }
+    return SW_OK;
+}
+
+// X0 -> act[0..4] -> delta
+sw_status forward(const sw_net *n, int B, hipStream_t s) {
+    sw_status st;
+    if ((st = conv(n, 0, n->x0, n->act[0], nullptr, nullptr, B, SW_CONV_RELU_BF16, false, s)) != SW_OK) return st;
+    for (int l = 1; l < kLayers - 1; ++l)
+        if ((st = conv(n, l, n->act[l - 1], n->act[l], nullptr, nullptr, B, SW_CONV_RELU_BF16, false, s)) != SW_OK)
+            return st;
+    return conv(n, kLayers - 1, n->act[kLayers - 2], nullptr, n->delta, nullptr, B, SW_CONV_F32, false, s);
+}
+
+// loss and gradients into n->grad (target already prepared)
+sw_status backward(sw_net *n, int B, float *loss_out, hipStream_t s) {
+    SHIP(sw_sur_loss(n->delta, n->target, B, n->H, n->W, n->loss_partial, kLossBlocks, n->dz6, s));
+    if (loss_out) SHIP(sw_sur_reduce_sum(n->loss_partial, kLossBlocks, loss_out, s));
+    const void *dz = n->dz6;
+    int dzc = 8;
+    for (int l = kLayers - 1; l >= 0; --l) {
+        const SwLayerDesc &L = n->L[l];
+        const void *a_in = l == 0 ? n->x0 : n->act[l - 1];
+        SHIP(sw_sur_wgrad(dz, dzc, L.cout, a_in, L.cinp, L.cin, B, n->H, n->W, n->wpartial, kWgradBlocks,
+                          n->grad + L.w_off, n->grad + L.b_off, s));
+        if (l == 0) break;
+        void *out = n->dz[l & 1];
+        sw_status st = conv(n, l, dz, out, nullptr, n->act[l - 1], B, SW_CONV_MASK_BF16, true, s);
+        if (st != SW_OK) return st;
+        dz = out;
+        dzc = 32;
+    }
+    return SW_OK;
+}
+
+sw_status relayout(sw_net *n, hipStream_t s) {
+    SHIP(sw_sur_relayout(n->master, n->L_dev, kLayers, n->nweights, s));
+    return SW_OK;
+}
+
+sw_status check_net(const sw_net *n, int B) {
+    if (!n) return sw_fail(SW_EINVAL, "surrogate: NULL network");
+    if (B < 1 || B > n->maxB) return sw_fail(SW_EINVAL, "surrogate: batch %d outside [1, %d]", B, n->maxB);
+    return use_dev(n);
+}
+
+}  // namespace
+
+extern "C" {
+
+sw_status sw_surrogate_create(const sw_net_cfg *cfg, int32_t H, int32_t W, int32_t max_batch, sw_net **out) {
+    if (!out || !cfg) return sw_fail(SW_EINVAL, "surrogate_create: NULL argument");
+    *out = nullptr;
+    if (cfg->layers != kLayers || cfg->hidden != kHidden)
+        return sw_fail(SW_ENOTSUP, "surrogate_create: only %d layers x %d channels", kLayers, kHidden);
+    if (cfg->jump < 2 || (cfg->jump & 1)) return sw_fail(SW_EINVAL, "surrogate_create: jump %d must be even", cfg->jump);
+    if ((cfg->bc_x != SW_BC_REFLECT && cfg->bc_x != SW_BC_PERIODIC) ||
+        (cfg->bc_y != SW_BC_REFLECT && cfg->bc_y != SW_BC_PERIODIC))
+        return sw_fail(SW_EINVAL, "surrogate_create: unknown boundary condition");
+    if (H < 1 || W < 64 || W % 64 != 0 || max_batch < 1 || (int64_t)H * W * max_batch > (int64_t)1 << 31)
+        return sw_fail(SW_EINVAL, "surrogate_create: grid %d x %d (W a multiple of 64), batch %d", H, W, max_batch);
+    auto *n = new (std::nothrow) sw_net();
+    if (!n) return sw_fail(SW_ENOMEM, "surrogate_create: host allocation");
+    n->cfg = *cfg;
+    n->H = H;
+    n->W = W;
+    n->maxB = max_batch;
+    sw_status st = hipGetDevice(&n->device) == hipSuccess ? SW_OK : sw_fail(SW_EHIP, "surrogate_create: no device");
+    // layer table: logical master layout W[co][tap][ci] then b[co], layer after layer
+    const int cins[kLayers] = {3, 32, 32, 32, 32, 32}, couts[kLayers] = {32, 32, 32, 32, 32, 3};
+    int64_t off = 0, nw = 0;
+    for (int l = 0; l < kLayers && st == SW_OK; ++l) {
+        SwLayerDesc &L = n->L[l];
+        L.cin = cins[l];
+        L.cout = couts[l];
+        L.cinp = L.cin <= 8 ? 8 : 32;
+        L.coutp = L.cout <= 8 ? 8 : 32;
+        L.kp = (L.cinp == 32 ? 9 : 3) * 32;
+        L.cdp = L.coutp;
+        L.kpd = (L.cdp == 32 ? 9 : 3) * 32;
+        L.w_off = off;
+        off += (int64_t)L.cout * 9 * L.cin;
+        nw += (int64_t)L.cout * 9 * L.cin;
+        L.b_off = off;
+        off += L.cout;
+        const int rows = (L.cout + 15) / 16 * 16;
+        st = dalloc(n, &L.wk, (size_t)rows * L.kp * 2);
+        if (st == SW_OK && l > 0) st = dalloc(n, &L.wd, (size_t)32 * L.kpd * 2);
+    }
+    n->nparams = off;
+    n->nweights = nw;
+    if (st == SW_OK) st = dalloc(n, (void **)&n->master, off * 4);
+    if (st == SW_OK) st = dalloc(n, (void **)&n->m, off * 4);
+    if (st == SW_OK) st = dalloc(n, (void **)&n->v, off * 4);
+    if (st == SW_OK) st = dalloc(n, (void **)&n->grad, off * 4);
+    if (st == SW_OK) st = dalloc(n, (void **)&n->loss_partial, kLossBlocks * 4);
+    if (st == SW_OK) st = dalloc(n, (void **)&n->scratch_loss, 64);
+    if (st == SW_OK) st = dalloc(n, (void **)&n->wpartial, (size_t)kWgradBlocks * (32 * 9 * 32 + 32) * 4);
+    if (st == SW_OK) st = dalloc(n, (void **)&n->L_dev, sizeof(n->L));
+    if (st == SW_OK) st = dalloc(n, &n->x0, act_bytes(n, max_batch, 8));
+    for (int l = 0; l < kLayers - 1 && st == SW_OK; ++l) st = dalloc(n, &n->act[l], act_bytes(n, max_batch, 32));
+    if (st == SW_OK) st = dalloc(n, &n->dz[0], act_bytes(n, max_batch, 32));
+    if (st == SW_OK) st = dalloc(n, &n->dz[1], act_bytes(n, max_batch, 32));
+    if (st == SW_OK) st = dalloc(n, &n->dz6, act_bytes(n, max_batch, 8));
+    if (st == SW_OK) st = dalloc(n, (void **)&n->delta, (size_t)max_batch * H * W * 16);
+    if (st == SW_OK) st = dalloc(n, (void **)&n->target, (size_t)max_batch * H * W * 16);
+    if (st == SW_OK) st = dalloc(n, (void **)&n->stats, (size_t)max_batch * sizeof(SwGateStats));
+    if (st == SW_OK) st = dalloc(n, (void **)&n->active, (size_t)max_batch * 4);
+    if (st == SW_OK && hipMemcpy(n->L_dev, n->L, sizeof(n->L), hipMemcpyHostToDevice) != hipSuccess)
+        st = sw_fail(SW_EHIP, "surrogate_create: layer table upload");
+    if (st == SW_OK) {
+        // He-normal weights from the seed (fan-in 9 * cin); the output layer
+        // starts 10x smaller so the untrained network is close to persistence
+        std::mt19937_64 rng(cfg->seed);
+        std::normal_distribution<double> nd(0.0, 1.0);
+        std::vector<float> p((size_t)off, 0.f);
+        for (int l = 0; l < kLayers; ++l) {
+            const SwLayerDesc &L = n->L[l];
+            const double sd = std::sqrt(2.0 / (9.0 * L.cin)) * (l == kLayers - 1 ? 0.1 : 1.0);
+            for (int64_t i = 0; i < (int64_t)L.cout * 9 * L.cin; ++i) p[L.w_off + i] = (float)(sd * nd(rng));
+        }
+        if (hipMemcpy(n->master, p.data(), off * 4, hipMemcpyHostToDevice) != hipSuccess)
+            st = sw_fail(SW_EHIP, "surrogate_create: weight upload");
+    }
+    if (st == SW_OK) st = relayout(n, nullptr);
+    if (st == SW_OK && hipDeviceSynchronize() != hipSuccess) st = sw_fail(SW_EHIP, "surrogate_create: sync");
+    for (int c = 0; c < 3; ++c) {
+        n->nrm.in_off[c] = c == 0 ? 1.f : 0.f;
+        n->nrm.in_scale[c] = c == 0 ? 0.25f : 0.25f * std::sqrt(9.8f);
+        n->nrm.out_scale[c] = n->nrm.in_scale[c];
+    }
+    if (st != SW_OK) {
+        sw_surrogate_destroy(n);
+        return st;
+    }
+    *out = n;
+    return SW_OK;
+}
+
+sw_status sw_surrogate_destroy(sw_net *n) {
+    if (!n) return SW_OK;
+    for (void *p : n->allocs) (void)hipFree(p);
+    delete n;
+    return SW_OK;
+}
+
+sw_status sw_surrogate_params(sw_net *n, float **master, int64_t *count) {
+    if (!n || !master || !count) return sw_fail(SW_EINVAL, "surrogate_params: NULL argument");
+    *master = n->master;
+    *count = n->nparams;
+    return SW_OK;
+}
+
+sw_status sw_surrogate_set_norm(sw_net *n, const float in_offset[3], const float in_scale[3],
+                                const float out_scale[3]) {
+    if (!n || !in_offset || !in_scale || !out_scale) return sw_fail(SW_EINVAL, "surrogate_set_norm: NULL argument");
+    for (int c = 0; c < 3; ++c) {
+        if (!(in_scale[c] > 0) || !(out_scale[c] > 0)) return sw_fail(SW_EINVAL, "surrogate_set_norm: scale <= 0");
+        n->nrm.in_off[c] = in_offset[c];
+        n->nrm.in_scale[c] = in_scale[c];
+        n->nrm.out_scale[c] = out_scale[c];
+    }
+    return SW_OK;
+}
+
+sw_status sw_surrogate_sync_weights(sw_net *n, void *stream) {
+    if (!n) return sw_fail(SW_EINVAL, "surrogate_sync_weights: NULL network");
+    sw_status st = use_dev(n);
+    if (st != SW_OK) return st;
+    return relayout(n, (hipStream_t)stream);
+}
+
+sw_status sw_surrogate_forward(sw_net *n, const float *u, int32_t B, float *delta, void *stream) {
+    sw_status st = check_net(n, B);
+    if (st != SW_OK) return st;
+    if (!u) return sw_fail(SW_EINVAL, "surrogate_forward: NULL input");
+    hipStream_t s = (hipStream_t)stream;
+    SHIP(sw_sur_prep_dense(u, nullptr, B, n->H, n->W, n->cfg.bc_x, n->cfg.bc_y, n->nrm, n->x0, nullptr, s));
+    if ((st = forward(n, B, s)) != SW_OK) return st;
+    if (delta) SHIP(hipMemcpyAsync(delta, n->delta, (size_t)B * n->H * n->W * 16, hipMemcpyDeviceToDevice, s));
+    return SW_OK;
+}
+
+sw_status sw_surrogate_activation(sw_net *n, int32_t layer, const void **ptr, int64_t *bytes) {
+    if (!n || !ptr) return sw_fail(SW_EINVAL, "surrogate_activation: NULL argument");
+    if (layer < 0 || layer > kLayers) return sw_fail(SW_EINVAL, "surrogate_activation: layer %d", layer);
+    if (layer == 0) *ptr = n->x0;
+    else if (layer < kLayers) *ptr = n->act[layer - 1];
+    else *ptr = n->delta;
+    if (bytes)
+        *bytes = layer == kLayers ? (int64_t)n->maxB * n->H * n->W * 16
+                                  : (int64_t)act_bytes(n, n->maxB, layer == 0 ? 8 : 32);
+    return SW_OK;
+}
+
+sw_status sw_surrogate_grad(sw_net *n, const float *u, const float *u8, int32_t B, float *grad, float *loss,
+                            void *stream) {
+    sw_status st = check_net(n, B);
+    if (st != SW_OK) return st;
+    if (!u || !u8) return sw_fail(SW_EINVAL, "surrogate_grad: NULL input");
+    hipStream_t s = (hipStream_t)stream;
+    SHIP(sw_sur_prep_dense(u, u8, B, n->H, n->W, n->cfg.bc_x, n->cfg.bc_y, n->nrm, n->x0, n->target, s));
+    if ((st = forward(n, B, s)) != SW_OK) return st;
+    if ((st = backward(n, B, loss, s)) != SW_OK) return st;
+    if (grad) SHIP(hipMemcpyAsync(grad, n->grad, n->nparams * 4, hipMemcpyDeviceToDevice, s));
+    return SW_OK;
+}
+
+sw_status sw_surrogate_train_step(sw_net *n, const float *u, const float *u8, int32_t B, float lr, float *loss,
+                                  void *stream) {
+    sw_status st = check_net(n, B);
+    if (st != SW_OK) return st;
+    if (!(lr > 0)) return sw_fail(SW_EINVAL, "surrogate_train_step: lr %g", lr);
+    if ((st = sw_surrogate_grad(n, u, u8, B, nullptr, loss, stream)) != SW_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    n->adam_t += 1;
+    SwAdam ad{lr, 0.9f, 0.999f, 1e-8f, 0.f, 0.f};
+    ad.c1 = (float)(1.0 / (1.0 - std::pow(0.9, (double)n->adam_t)));
+    ad.c2 = (float)(1.0 / (1.0 - std::pow(0.999, (double)n->adam_t)));
+    SHIP(sw_sur_adam(n->master, n->m, n->v, n->grad, n->nparams, ad, s));
+    return relayout(n, s);
+}
+
+sw_status sw_surrogate_advance(sw_net *n, sw_batch *solver, int32_t nsteps, const sw_gate *gate,
+                               int32_t *fallbacks, void *stream) {
+    if (!n || !solver || !gate) return sw_fail(SW_EINVAL, "surrogate_advance: NULL argument");
+    SwBatchInfo bi;
+    sw_status st = (sw_status)sw_batch_internal_info(solver, &bi);
+    if (st != SW_OK) return st;
+    if ((st = check_net(n, bi.n)) != SW_OK) return st;
+    if (bi.dtype != SW_F32) return sw_fail(SW_ENOTSUP, "surrogate_advance: the surrogate advances FP32 batches");
+    if (bi.same_nx != n->W || bi.same_ny != n->H)
+        return sw_fail(SW_EINVAL, "surrogate_advance: every grid must be %d x %d", n->W, n->H);
+    if (nsteps < 0 || nsteps % n->cfg.jump)
+        return sw_fail(SW_EINVAL, "surrogate_advance: nsteps %d is not a multiple of the jump %d", nsteps, n->cfg.jump);
+    if (bi.bc_x != n->cfg.bc_x || bi.bc_y != n->cfg.bc_y)
+        return sw_fail(SW_EINVAL, "surrogate_advance: boundary conditions differ from the network's");
+    hipStream_t s = (hipStream_t)stream;
+    const int B = bi.n, cur = bi.cur;
+    if ((st = sw_batch_fill_halo(solver, stream)) != SW_OK) return st;
+    for (int j = 0; j < nsteps / n->cfg.jump; ++j) {
+        SHIP(sw_sur_prep_planes(bi.d_grids, cur, B, n->H, n->W, n->nrm, n->x0, s));
+        if ((st = forward(n, B, s)) != SW_OK) return st;
+        SHIP(sw_sur_zero_stats(n->stats, B, s));
+        if (gate->project_mass) SHIP(sw_sur_delta_sum(n->delta, B, n->H, n->W, n->stats, s));
+        SHIP(sw_sur_apply(n->delta, bi.d_grids, cur, B, n->H, n->W, n->nrm, gate->project_mass, bi.bc_x, bi.bc_y,
+                          n->stats, s));
+        SHIP(sw_sur_gate(n->stats, B, gate->mass_rel_tol, gate->hmin, n->active, fallbacks, s));
+        // rejected grids: the plain solver takes the jump from U^n
+        if ((st = (sw_status)sw_batch_internal_step_masked(solver, n->cfg.jump, n->active, s)) != SW_OK) return st;
+        // accepted grids: the prediction becomes U^{n+jump}
+        SHIP(sw_sur_accept(bi.d_grids, cur, B, n->H, n->W, n->active, s));
+    }
+    return SW_OK;
+}
+
+}  // extern "C"

@@ -26,14 +26,6 @@ namespace sw {
 namespace tile {
 
 
-template <typename T> __device__ __forceinline__ T fast_rcp(T x);
-template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> __device__ __forceinline__ double fast_rcp<double>(double x) { return 1.0 / x; }
-
-template <typename T> __device__ __forceinline__ T fast_sqrt(T x);
-template <> __device__ __forceinline__ float fast_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
-template <> __device__ __forceinline__ double fast_sqrt<double>(double x) { return sqrt(x); }
-
 // Buffer (V#) access: a scalar resource descriptor per plane and tile, a
 // loop-invariant 32-bit byte offset per lane (VGPR) and the row's byte
 // offset (SGPR).  Marching to the next row changes only the scalar offset.
@@ -254,8 +246,7 @@ __device__ __forceinline__ void fused_tile(const TileArgs &t, double dt, double 
                     for (int kk = 0; kk < 3; ++kk) bstore<T, VEC>(rout[kk], sb, so, out[kk]);
 #pragma unroll
                     for (int m = 0; m < VEC; ++m) {
-                        T sp = fmax(fabs(out[1][m]), fabs(out[2][m])) * fast_rcp(out[0][m]) +
-                               fast_sqrt(g * out[0][m]);
+                        T sp = signal_speed(U3<T>{out[0][m], out[1][m], out[2][m]}, g);
                         bad |= !(sp <= finite_max<T>());
                         smax = fmax(smax, sp);
                     }
@@ -265,8 +256,7 @@ __device__ __forceinline__ void fused_tile(const TileArgs &t, double dt, double 
                         if ((int)c + m < nx) {
 #pragma unroll
                             for (int kk = 0; kk < 3; ++kk) O[kk][ro + c + m] = out[kk][m];
-                            T sp = fmax(fabs(out[1][m]), fabs(out[2][m])) * fast_rcp(out[0][m]) +
-                                   fast_sqrt(g * out[0][m]);
+                            T sp = signal_speed(U3<T>{out[0][m], out[1][m], out[2][m]}, g);
                             bad |= !(sp <= finite_max<T>());
                             smax = fmax(smax, sp);
                         }

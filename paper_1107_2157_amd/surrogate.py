@@ -1,0 +1,123 @@
+"""Training data, training loop and evaluation of the learned surrogate.
+
+Orchestration only: trajectories come from the library's batched solver,
+training steps and rollouts are library calls (``sw.Surrogate``); torch is
+used to hold tensors and to pick random training pairs.
+
+Workload (the surrogate configuration): H x W grids with reflective walls,
+initial states of 1-8 seeded Gaussian bumps (seeds ``ics.SEED_TRAJ0 + k``),
+trajectories of ``frames`` states (after 0 .. frames-1 solver steps), training
+pairs ``(U^t, U^{t+jump})`` for every ``t <= frames - 1 - jump``.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import torch
+
+from . import ics, sw
+
+IN_OFFSET = (1.0, 0.0, 0.0)
+IN_SCALE = (0.25, 0.25 * math.sqrt(9.8), 0.25 * math.sqrt(9.8))
+
+
+def initial_states(n: int, H: int, W: int, seed0: int, periodic: bool = False, device="cuda") -> torch.Tensor:
+    """Dense [n][3][H][W] FP32 bump states."""
+    out = torch.empty((n, 3, H, W), dtype=torch.float32, device=device)
+    for k in range(n):
+        h, hu, hv = ics.bumps_state(W, H, seed=seed0 + k, periodic=periodic, device=device)
+        out[k, 0], out[k, 1], out[k, 2] = h, hu, hv
+    return out
+
+
+def trajectories(n: int, H: int, W: int, frames: int, seed0: int = ics.SEED_TRAJ0, chunk: int = 256,
+                 bc: int = sw.REFLECT) -> torch.Tensor:
+    """Solver trajectories as a dense [frames][n][3][H][W] FP32 device tensor."""
+    out = torch.empty((frames, n, 3, H, W), dtype=torch.float32, device="cuda")
+    for c0 in range(0, n, chunk):
+        m = min(chunk, n - c0)
+        b = sw.Batch([(W, H)] * m, dtype="f32", bc_x=bc, bc_y=bc)
+        b.load(initial_states(m, H, W, seed0 + c0, periodic=bc == sw.PERIODIC))
+        b.export(out[0, c0:c0 + m])
+        for t in range(1, frames):
+            b.step(1)
+            b.export(out[t, c0:c0 + m])
+        b.sync_status()
+        del b
+    torch.cuda.synchronize()
+    return out
+
+
+def fit_out_scale(data: torch.Tensor, jump: int) -> tuple:
+    """RMS of U^{t+jump} - U^t per channel over the trajectories."""
+    d = data[jump:] - data[:-jump]
+    return tuple(max(float(d[:, :, c].pow(2).mean().sqrt()), 1e-6) for c in range(3))
+
+
+def sample_pairs(data: torch.Tensor, B: int, jump: int, gen: torch.Generator):
+    frames, n = data.shape[0], data.shape[1]
+    ti = torch.randint(0, frames - jump, (B,), generator=gen).to(data.device)
+    ni = torch.randint(0, n, (B,), generator=gen).to(data.device)
+    return data[ti, ni].contiguous(), data[ti + jump, ni].contiguous()
+
+
+def train(net: "sw.Surrogate", data: torch.Tensor, steps: int, B: int, lr: float, jump: int, seed: int = 0,
+          lr_final: float | None = None, log_every: int = 0):
+    """Adam steps on random pairs; cosine decay from lr to lr_final.
+    Returns the per-step losses."""
+    gen = torch.Generator().manual_seed(seed)
+    losses = torch.empty(steps, dtype=torch.float32, device="cuda")
+    lr_final = lr if lr_final is None else lr_final
+    t0 = time.perf_counter()
+    for k in range(steps):
+        u, u8 = sample_pairs(data, B, jump, gen)
+        lr_k = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * k / max(steps - 1, 1)))
+        loss = net.train_step(u, u8, lr_k)
+        losses[k] = loss[0]
+        if log_every and (k + 1) % log_every == 0:
+            print(f"[train] step {k + 1}/{steps} loss {float(losses[k]):.4e} "
+                  f"({time.perf_counter() - t0:.1f} s)", flush=True)
+    torch.cuda.synchronize()
+    return losses.cpu()
+
+
+def rel_l2_h(h, h_ref):
+    """||h - h_ref||_2 / ||h_ref||_2 per grid, and the stricter
+    ||h - h_ref||_2 / ||h_ref - mean(h_ref)||_2."""
+    d = (h - h_ref).flatten(1).double()
+    r = h_ref.flatten(1).double()
+    return (d.norm(dim=1) / r.norm(dim=1)), (d.norm(dim=1) / (r - r.mean(dim=1, keepdim=True)).norm(dim=1))
+
+
+def rollout(net, u0: torch.Tensor, nsteps: int, gate: dict | None = None, timed: bool = True):
+    """Surrogate rollout of a dense [n][3][H][W] state: returns (final state,
+    fallbacks per grid, seconds)."""
+    n, _, H, W = u0.shape
+    b = sw.Batch([(W, H)] * n, dtype="f32")
+    b.load(u0)
+    fb = torch.zeros(n, dtype=torch.int32, device="cuda")
+    gate = gate or {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net.advance(b, nsteps, fallbacks=fb, **gate)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    return b.export(), fb.cpu(), sec
+
+
+def solver_run(u0: torch.Tensor, nsteps: int):
+    """Plain batched solver from the same state: (final state, seconds)."""
+    n, _, H, W = u0.shape
+    b = sw.Batch([(W, H)] * n, dtype="f32")
+    b.load(u0)
+    b.step(nsteps)          # capture
+    b.load(u0)
+    b.reset_time()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(nsteps)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    b.sync_status()
+    return b.export(), sec

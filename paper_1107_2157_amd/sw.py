@@ -63,6 +63,17 @@ class Tuning(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class NetCfg(ctypes.Structure):
+    _fields_ = [("layers", ctypes.c_int32), ("hidden", ctypes.c_int32), ("jump", ctypes.c_int32),
+                ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class Gate(ctypes.Structure):
+    _fields_ = [("mass_rel_tol", ctypes.c_double), ("hmin", ctypes.c_double), ("project_mass", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class State(ctypes.Structure):
     _fields_ = [("plane", (ctypes.c_void_p * 3) * 2), ("cur", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
@@ -98,11 +109,31 @@ SIGNATURES = {
     "sw_batch_sync_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
     "sw_batch_reset_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sw_batch_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sw_batch_import": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sw_batch_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "sw_batch_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "sw_batch_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "sw_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_void_p,
                                          ctypes.POINTER(Tuning)]),
+    "sw_surrogate_create": (ctypes.c_int, [ctypes.POINTER(NetCfg), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_void_p)]),
+    "sw_surrogate_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sw_surrogate_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_int64)]),
+    "sw_surrogate_sync_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sw_surrogate_set_norm": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
+                                             ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+    "sw_surrogate_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.c_void_p]),
+    "sw_surrogate_activation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+                                               ctypes.POINTER(ctypes.c_int64)]),
+    "sw_surrogate_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sw_surrogate_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                               ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p]),
+    "sw_surrogate_advance": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Gate),
+                                            ctypes.c_void_p, ctypes.c_void_p]),
     "sw_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sw_last_error_detail": (ctypes.c_char_p, []),
 }
@@ -332,3 +363,130 @@ class Batch:
 
     def reset_time(self, stream=None):
         check(lib().sw_batch_reset_time(self.handle, _stream_handle(stream)), "sw_batch_reset_time")
+
+    def export(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        """All (equal-size) grids' current state as a dense [n][3][ny][nx] device tensor."""
+        nx, ny = self.shapes[0]
+        if out is None:
+            out = torch.empty((self.n, 3, ny, nx), dtype=self.torch_dtype, device="cuda")
+        check(lib().sw_batch_export(self.handle, ctypes.c_void_p(out.data_ptr()), _stream_handle()), "sw_batch_export")
+        return out
+
+    def load(self, dense: torch.Tensor):
+        """Set every grid's current state from a dense [n][3][ny][nx] device tensor."""
+        d = dense.to(self.torch_dtype).contiguous()
+        check(lib().sw_batch_import(self.handle, ctypes.c_void_p(d.data_ptr()), _stream_handle()), "sw_batch_import")
+        torch.cuda.synchronize()
+
+
+# per layer (cin, cout) of the surrogate; master layout: W[co][tap][ci] then b[co]
+SURROGATE_LAYERS = [(3, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 3)]
+
+
+_hip = None
+
+
+def _hip_d2d(dst: int, src: int, nbytes: int):
+    """Synchronous device-to-device copy (library-owned memory <-> tensors)."""
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+    rc = _hip.hipMemcpy(ctypes.c_void_p(dst), ctypes.c_void_p(src), nbytes, 3)
+    if rc != 0:
+        raise SwError(EHIP, "hipMemcpy", f"error {rc}")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Surrogate:
+    """The learned surrogate (sw_surrogate_*) for H x W grids."""
+
+    def __init__(self, H: int, W: int, max_batch: int, jump: int = 8, seed: int = 0,
+                 bc_x: int = REFLECT, bc_y: int = REFLECT):
+        cfg = NetCfg(6, 32, jump, bc_x, bc_y, 0, seed)
+        h = ctypes.c_void_p()
+        check(lib().sw_surrogate_create(ctypes.byref(cfg), H, W, max_batch, ctypes.byref(h)), "sw_surrogate_create")
+        self.handle, self.H, self.W, self.max_batch, self.jump = h, H, W, max_batch, jump
+        p, n = ctypes.c_void_p(), ctypes.c_int64()
+        check(lib().sw_surrogate_params(h, ctypes.byref(p), ctypes.byref(n)), "sw_surrogate_params")
+        self.nparams = n.value
+        self._master_ptr = p.value
+        self.loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.sw_surrogate_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    def get_params(self) -> torch.Tensor:
+        out = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        _hip_d2d(out.data_ptr(), self._master_ptr, self.nparams * 4)
+        return out
+
+    def set_params(self, params):
+        t = torch.as_tensor(params, dtype=torch.float32).to("cuda").contiguous()
+        assert t.numel() == self.nparams
+        torch.cuda.synchronize()
+        _hip_d2d(self._master_ptr, t.data_ptr(), self.nparams * 4)
+        check(lib().sw_surrogate_sync_weights(self.handle, _stream_handle()), "sw_surrogate_sync_weights")
+        torch.cuda.synchronize()
+
+    def set_norm(self, in_offset, in_scale, out_scale):
+        f3 = ctypes.c_float * 3
+        check(lib().sw_surrogate_set_norm(self.handle, f3(*in_offset), f3(*in_scale), f3(*out_scale)),
+              "sw_surrogate_set_norm")
+
+    def forward(self, u: torch.Tensor) -> torch.Tensor:
+        """u: [B][3][H][W] FP32 on the GPU -> normalised delta [B][H][W][4]."""
+        u = u.contiguous()
+        B = u.shape[0]
+        out = torch.empty((B, self.H, self.W, 4), dtype=torch.float32, device="cuda")
+        check(lib().sw_surrogate_forward(self.handle, _ptr(u), B, _ptr(out), _stream_handle()),
+              "sw_surrogate_forward")
+        return out
+
+    def activation(self, layer: int, B: int) -> torch.Tensor:
+        p, nb = ctypes.c_void_p(), ctypes.c_int64()
+        check(lib().sw_surrogate_activation(self.handle, layer, ctypes.byref(p), ctypes.byref(nb)),
+              "sw_surrogate_activation")
+        torch.cuda.synchronize()
+        if layer == 6:
+            n = B * self.H * self.W * 4
+            buf = torch.empty(n, dtype=torch.float32, device="cuda")
+            shape = (B, self.H, self.W, 4)
+            nbytes = n * 4
+        else:
+            ch = 8 if layer == 0 else 32
+            shape = (B, self.H + 2, self.W + 2, ch)
+            n = B * (self.H + 2) * (self.W + 2) * ch
+            buf = torch.empty(n, dtype=torch.bfloat16, device="cuda")
+            nbytes = n * 2
+        _hip_d2d(buf.data_ptr(), p.value, nbytes)
+        return buf.view(shape)
+
+    def grad(self, u, u8):
+        B = u.shape[0]
+        g = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
+        check(lib().sw_surrogate_grad(self.handle, _ptr(u.contiguous()), _ptr(u8.contiguous()), B, _ptr(g),
+                                      _ptr(self.loss), _stream_handle()), "sw_surrogate_grad")
+        return g, self.loss
+
+    def train_step(self, u, u8, lr: float):
+        B = u.shape[0]
+        check(lib().sw_surrogate_train_step(self.handle, _ptr(u), _ptr(u8), B, lr, _ptr(self.loss),
+                                            _stream_handle()), "sw_surrogate_train_step")
+        return self.loss
+
+    def advance(self, batch: "Batch", nsteps: int, mass_rel_tol=1e-4, hmin=0.0, project_mass=True,
+                fallbacks: torch.Tensor | None = None):
+        gate = Gate(mass_rel_tol, hmin, 1 if project_mass else 0, 0)
+        check(lib().sw_surrogate_advance(self.handle, batch.handle, nsteps, ctypes.byref(gate), _ptr(fallbacks),
+                                         _stream_handle()), "sw_surrogate_advance")

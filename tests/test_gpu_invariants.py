@@ -130,3 +130,34 @@ def test_fused_tunings_bitwise_identical():
                                 assert np.array_equal(x, y), (dtype, vec, occ, pd, rows)
                             assert ref[3] == out[3]
         assert ran >= 30
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_restart_and_checkpoint_are_bitwise(variant, dtype):
+    """30 steps in one call == 10 + 20 steps in two calls == 10 steps, a
+    checkpoint through the host, a fresh solver, 20 more steps."""
+    st = ics.bumps_state(300, 200, seed=8, periodic=True, count=6)
+    kw = dict(dtype=dtype, bc_x=sw.PERIODIC, bc_y=sw.PERIODIC, variant=variant)
+    a = sw.Solver(300, 200, **kw)
+    a.set_state(*st)
+    a.step(30)
+    ta = a.sync_status()[0]
+    b = sw.Solver(300, 200, **kw)
+    b.set_state(*st)
+    b.step(10)
+    b.step(20)
+    assert [x.numpy().tobytes() for x in a.get_state(halo=True)] == [x.numpy().tobytes() for x in b.get_state(halo=True)]
+    assert b.sync_status()[0] == ta
+    c1 = sw.Solver(300, 200, **kw)
+    c1.set_state(*st)
+    c1.step(10)
+    t1 = c1.sync_status()[0]
+    saved = c1.get_state()
+    c2 = sw.Solver(300, 200, **kw)
+    c2.set_state(*saved)
+    c2.step(20)
+    t2 = c2.sync_status()[0]
+    for x, y in zip(a.get_state(), c2.get_state()):
+        assert torch.equal(x, y)
+    assert abs((t1 + t2) - ta) <= 1e-12 * ta

@@ -1,0 +1,151 @@
+"""The learned surrogate on the GPU (through the C ABI): forward activations
+and gradients against the CPU FP64 oracle fed the same BF16-quantised
+tensors, training, the forced fallback, and what the trained network gains
+over the method without it."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import net_oracle as no
+from paper_1107_2157_amd import ics, surrogate, sw
+from swtest import announce
+
+pytestmark = pytest.mark.gpu
+
+OFF, SCALE = surrogate.IN_OFFSET, surrogate.IN_SCALE
+
+
+def states(n, H, W, seed):
+    u = surrogate.initial_states(n, H, W, seed)
+    g = torch.Generator().manual_seed(seed)
+    u[:, 1:] += 0.05 * (torch.rand((n, 2, H, W), generator=g) - 0.5).cuda()
+    return u
+
+
+def make_net(H, W, B, params, out_scale):
+    net = sw.Surrogate(H, W, B, jump=8, seed=1)
+    net.set_params(torch.tensor(params, dtype=torch.float32))
+    net.set_norm(OFF, SCALE, out_scale)
+    return net
+
+
+def test_forward_matches_oracle():
+    B, H, W = 2, 48, 64
+    p = no.init_params(11, out_gain=1.0)
+    out_scale = (0.05, 0.05, 0.05)
+    u = states(B, H, W, 21)
+    announce("surrogate forward parity")
+    net = make_net(H, W, B, p, out_scale)
+    delta = net.forward(u).cpu().numpy()
+    acts, ref_delta = no.forward(p, u.cpu().numpy(), OFF, SCALE, bf16_mode=True)
+    x0 = net.activation(0, B).float().cpu().numpy()
+    assert np.array_equal(x0[..., :3], acts[0]) and not np.any(x0[..., 3:])
+    for l in range(1, 6):
+        got = net.activation(l, B).float().cpu().numpy()
+        ref = acts[l]
+        mism = np.mean(got != ref)
+        rel = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        print(f"layer {l}: mismatch fraction {mism:.2e}, max rel {rel:.2e}")
+        assert mism < 2e-3 and rel < 2e-2
+    scale = np.max(np.abs(ref_delta))
+    err = np.abs(delta[..., :3] - ref_delta)
+    print(f"delta: max {err.max() / scale:.2e}, mean {err.mean() / scale:.2e}")
+    assert err.max() <= 1e-2 * scale and err.mean() <= 1e-4 * scale
+    assert not np.any(delta[..., 3])
+
+
+def test_gradient_matches_oracle():
+    B, H, W = 2, 40, 64
+    p = no.init_params(12, out_gain=1.0)
+    out_scale = (0.02, 0.03, 0.03)
+    u = states(B, H, W, 31)
+    u8 = u + 0.01 * torch.randn_like(u)
+    announce("surrogate gradient parity")
+    net = make_net(H, W, B, p, out_scale)
+    g, loss = net.grad(u, u8)
+    g = g.cpu().numpy().astype(np.float64)
+    ref_loss, ref = no.loss_and_grad(p, u.cpu().numpy(), u8.cpu().numpy(), OFF, SCALE, out_scale, bf16_mode=True)
+    assert abs(float(loss[0]) - ref_loss) <= 1e-4 * ref_loss
+    off = 0
+    for l, (ci, co) in enumerate(no.LAYERS):
+        for name, cnt in (("W", co * 9 * ci), ("b", co)):
+            a, r = g[off:off + cnt], ref[off:off + cnt]
+            rel = np.linalg.norm(a - r) / np.linalg.norm(r)
+            print(f"layer {l + 1} {name}: rel {rel:.2e}")
+            assert rel <= 2e-2, (l, name, rel)
+            off += cnt
+
+
+def test_export_import_roundtrip():
+    u = states(3, 40, 64, 5)
+    b = sw.Batch([(64, 40)] * 3, dtype="f32")
+    b.load(u)
+    assert torch.equal(b.export(), u)
+    for k in range(3):
+        h, hu, hv = b.get_state(k)
+        assert torch.equal(h, u[k, 0].cpu().double())
+
+
+@pytest.mark.parametrize("fault", ["nan_hv", "mass_drift", "dry_cell"])
+def test_forced_fallback_equals_solver(fault):
+    """A network that fails every gate leaves the plain solver's result,
+    bitwise, and every jump is counted as a fallback.  Each case trips one
+    check: a NaN hv output (the last bias of the output layer; a NaN in a
+    hidden layer would not do, since ReLU maps it to zero) only the
+    non-finite check sees; a constant dh with the mass projection off only
+    the mass-drift check; a large negative dh with the projection on (mass
+    kept) only the positivity check."""
+    n, H, W = 4, 64, 64
+    u0 = states(n, H, W, 41)
+    net = sw.Surrogate(H, W, n, jump=8, seed=3)
+    p = net.get_params()
+    gate = {}
+    if fault == "nan_hv":
+        p[-1] = float("nan")
+    elif fault == "mass_drift":
+        p[-3] += 1.0
+        gate = dict(project_mass=False)
+    else:
+        # dh swings far beyond the depth; the projection removes its mean,
+        # so the mass is kept and only negative depths are left to reject
+        w6 = p[-3 - 3 * 9 * 32:-3].view(3, 9, 32)
+        w6[0] *= 1.0e4
+        gate = dict(project_mass=True, mass_rel_tol=1.0)
+    net.set_params(p)
+    got, fb, _ = surrogate.rollout(net, u0, 24, gate)
+    ref, _ = surrogate.solver_run(u0, 24)
+    assert torch.equal(got, ref)
+    assert fb.tolist() == [3] * n
+
+
+def test_training_gains_over_untrained_and_persistence():
+    """Train on solver trajectories (64 x 64 grids), then roll out 64 steps
+    on held-out initial states: the trained network is closer to the plain
+    solver than the untrained one and than persistence (U^{n+8} := U^n)."""
+    H = W = 64
+    jump, frames = 8, 64
+    announce("surrogate training")
+    data = surrogate.trajectories(64, H, W, frames, seed0=70000)
+    out_scale = surrogate.fit_out_scale(data, jump)
+    net = sw.Surrogate(H, W, 32, jump=jump, seed=5)
+    net.set_norm(OFF, SCALE, out_scale)
+    untrained = net.get_params().clone()
+    losses = surrogate.train(net, data, steps=400, B=32, lr=2e-3, jump=jump, seed=1, lr_final=2e-4)
+    first, last = float(losses[:20].mean()), float(losses[-20:].mean())
+    print(f"loss {first:.3e} -> {last:.3e}")
+    assert last < 0.3 * first
+    u0 = surrogate.initial_states(16, H, W, 90000)
+    ref, _ = surrogate.solver_run(u0, 64)
+    gate = dict(mass_rel_tol=1e-4, project_mass=True)
+    trained, fb_t, _ = surrogate.rollout(net, u0, 64, gate)
+    e_trained = surrogate.rel_l2_h(trained[:, 0], ref[:, 0])
+    net.set_params(untrained)
+    untr, fb_u, _ = surrogate.rollout(net, u0, 64, gate)
+    e_untr = surrogate.rel_l2_h(untr[:, 0], ref[:, 0])
+    e_pers = surrogate.rel_l2_h(u0[:, 0], ref[:, 0])
+    print(f"rel L2(h): trained {e_trained[0].mean():.2e} (fallbacks {int(fb_t.sum())}), "
+          f"untrained {e_untr[0].mean():.2e} (fallbacks {int(fb_u.sum())}), persistence {e_pers[0].mean():.2e}; "
+          f"strict: trained {e_trained[1].mean():.2e}, persistence {e_pers[1].mean():.2e}")
+    assert e_trained[0].mean() < e_pers[0].mean()
+    assert e_trained[1].mean() < e_pers[1].mean()
+    assert float(e_trained[0].max()) <= 1e-2

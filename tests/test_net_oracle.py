@@ -1,0 +1,72 @@
+"""Pins of the surrogate's CPU FP64 oracle: the 3x3 convolution against
+scipy's 2-D correlation, the analytic gradient against central finite
+differences, the input ghosts against the solver oracle's boundary rule, and
+the BF16 rounding against torch's conversion."""
+import numpy as np
+import pytest
+import scipy.signal
+import torch
+
+import oracle
+from oracle import net_oracle as no
+from paper_1107_2157_amd import ics
+
+OFF = (1.0, 0.0, 0.0)
+SCALE = (0.25, 0.25 * 9.8 ** 0.5, 0.25 * 9.8 ** 0.5)
+
+
+def test_conv3x3_is_2d_correlation():
+    rng = np.random.default_rng(0)
+    xh = rng.standard_normal((2, 9, 11, 5))
+    w = rng.standard_normal((4, 9, 5))
+    b = rng.standard_normal(4)
+    got = no.conv3x3(xh, w, b)
+    for bb in range(2):
+        for co in range(4):
+            want = sum(scipy.signal.correlate2d(xh[bb, :, :, ci], w[co, :, ci].reshape(3, 3), mode="valid")
+                       for ci in range(5)) + b[co]
+            np.testing.assert_allclose(got[bb, :, :, co], want, rtol=1e-12, atol=1e-12)
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(1)
+    x = np.concatenate([rng.standard_normal(10000) * 10.0 ** rng.integers(-6, 6, 10000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.0078125, 1.01171875, 3.0e38, -2.5]])
+    want = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(no.bf16(x), want)
+
+
+@pytest.mark.parametrize("bcx,bcy", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_input_ghosts_follow_the_boundary_rule(bcx, bcy):
+    h, hu, hv = (a.numpy() for a in ics.random_state(7, 5, seed=2))
+    u = np.stack([h, hu, hv])[None].astype(np.float32)
+    x = no.input_tensor(u, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), bcx, bcy, quant=False)
+    H, U, V = (oracle.with_halo(a.astype(np.float32).astype(np.float64)) for a in (h, hu, hv))
+    oracle.fill_halo(H, U, V, bcx, bcy)
+    for c, ref in enumerate((H, U, V)):
+        np.testing.assert_array_equal(x[0, :, :, c], ref)
+
+
+def test_gradient_matches_central_differences():
+    rng = np.random.default_rng(3)
+    h, hu, hv = (a.numpy() for a in ics.random_state(7, 6, seed=4, amp_h=0.4, amp_m=0.1))
+    u = np.stack([h, hu, hv])[None]
+    u8 = u + 0.01 * rng.standard_normal(u.shape)
+    p = no.init_params(5, out_gain=1.0)
+    out_scale = (0.01, 0.02, 0.02)
+    loss, g = no.loss_and_grad(p, u, u8, OFF, SCALE, out_scale, bf16_mode=False)
+    idx = np.concatenate([rng.choice(no.nparams(), 80, replace=False),
+                          np.cumsum([co * 9 * ci + co for ci, co in no.LAYERS]) - 1])   # include last biases
+    eps = 1e-6
+    for i in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[i] += eps
+        pm[i] -= eps
+        lp, _ = no.loss_and_grad(pp, u, u8, OFF, SCALE, out_scale, bf16_mode=False)
+        lm, _ = no.loss_and_grad(pm, u, u8, OFF, SCALE, out_scale, bf16_mode=False)
+        fd = (lp - lm) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) * max(1.0, loss), (i, fd, g[i])
+
+
+def test_param_count():
+    assert no.nparams() == 38755
