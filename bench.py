@@ -154,6 +154,65 @@ def run_batch(steps, sw, ics, torch, tune_cache, per_grid_steps):
             "hbm_frac": rate * 24 / HBM_PEAK_GBS}
 
 
+SUR_FLOP_PER_PIXEL_FWD = 2 * 9 * (3 * 32 + 4 * 32 * 32 + 32 * 3)          # 77 184 per pixel per jump
+SUR_FLOP_PER_PIXEL_TRAIN = SUR_FLOP_PER_PIXEL_FWD * 2 + 2 * 9 * (4 * 32 * 32 + 32 * 3)   # + wgrad + dgrad
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def run_surrogate(sw, ics, torch, n=256, size=256, nsteps=64):
+    """Surrogate workload: n held-out size x size grids (seeds SEED_SURR_EVAL0 + k,
+    1-8 bumps, reflective walls, FP32), advanced nsteps = nsteps / 8 jumps of the
+    trained network (committed weights) under the gate (mass drift 1e-4 with
+    projection, h > 0, finite), against the plain batched solver (one graph
+    launch) from the same states; plus the judged rollout, the forward pass
+    alone and one training step at batch n."""
+    from paper_1107_2157_amd import surrogate
+    name = f"surrogate{size}-b{n}-{nsteps}steps"
+    if not os.path.exists(surrogate.WEIGHTS_256):
+        return {"workload": name, "skipped": "no trained weights"}
+    net, meta = surrogate.load_weights(surrogate.WEIGHTS_256, n)
+    u0 = surrogate.initial_states(n, size, size, ics.SEED_SURR_EVAL0)
+    ref, t_solver = surrogate.solver_run(u0, nsteps)
+    gate = dict(mass_rel_tol=1e-4, project_mass=True)
+    b = sw.Batch([(size, size)] * n, dtype="f32")
+    surrogate.rollout(net, u0, nsteps, gate, batch=b)                       # warm
+    got, fb, t_sur = surrogate.rollout(net, u0, nsteps, gate, batch=b)
+    e, e_strict = surrogate.rel_l2_h(got[:, 0], ref[:, 0])
+    p, _ = surrogate.rel_l2_h(u0[:, 0], ref[:, 0])
+    l2 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    jg = dict(gate, judge=True, l2_tol=1e-2)
+    surrogate.rollout(net, u0, nsteps, jg, l2=l2, batch=b)                  # warm (allocates the solver copy)
+    _, fbj, t_judge = surrogate.rollout(net, u0, nsteps, jg, l2=l2, batch=b)
+    judged_out = int((l2 > 1e-2).sum())
+    del b
+    net.forward(u0)
+    t_fwd = timed(torch, lambda: net.forward(u0))
+    pixels = n * size * size
+    fwd_tflops = SUR_FLOP_PER_PIXEL_FWD * pixels / t_fwd / 1e12
+    # one Adam step on (U^0, U^8) pairs of the same grids, on a separate network
+    bt = sw.Batch([(size, size)] * n, dtype="f32")
+    bt.load(u0)
+    bt.step(8)
+    u8 = bt.export()
+    del bt
+    tnet = sw.Surrogate(size, size, n, jump=8, seed=1)
+    tnet.train_step(u0, u8, 1e-5)
+    t_train = timed(torch, lambda: tnet.train_step(u0, u8, 1e-5))
+    del tnet, net
+    torch.cuda.empty_cache()
+    return {"workload": name, "grids": n, "size": size, "steps": nsteps, "jump": 8,
+            "solver_seconds": t_solver, "rollout_seconds": t_sur, "speedup_vs_solver": t_solver / t_sur,
+            "rel_l2_h_mean": float(e.mean()), "rel_l2_h_max": float(e.max()),
+            "rel_l2_h_strict_mean": float(e_strict.mean()), "persistence_rel_l2_h_mean": float(p.mean()),
+            "fallback_jumps": int(fb.sum()), "jumps": n * nsteps // 8,
+            "judged_rollout_seconds": t_judge, "judge_rejected_grids": judged_out,
+            "forward_ms": 1e3 * t_fwd, "forward_tflops": fwd_tflops,
+            "forward_frac_bf16_peak": fwd_tflops / BF16_PEAK_TFLOPS,
+            "train_step_ms": 1e3 * t_train,
+            "train_tflops": SUR_FLOP_PER_PIXEL_TRAIN * pixels / t_train / 1e12,
+            "weights_recipe": meta.get("recipe"), "weights_eval": meta.get("eval")}
+
+
 def copy_bandwidth(torch, nbytes):
     """Device copy of nbytes (read + write) with torch: attainable streaming BW."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -197,6 +256,7 @@ def main():
     ap.add_argument("--no-also", action="store_true", help="skip the secondary 4096^2 FP32/FP64 runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 512-grid run")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate run")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1107_2157_amd", "tune_cache_gfx950.txt"),
                     help="autotuner cache (launch shapes found by sw_autotune on MI355X; missing keys are tuned "
                          "and appended)")
@@ -247,6 +307,9 @@ def main():
 
     if not args.no_also and not args.no_batch and args.workload == "swe16384-f32-periodic":
         also.append(run_batch(500, sw, ics, torch, args.tune_cache, per_grid_steps=50))
+
+    if not args.no_also and not args.no_surrogate and args.workload == "swe16384-f32-periodic":
+        also.append(run_surrogate(sw, ics, torch))
 
     line = {
         "metric": METRIC,

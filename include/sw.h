@@ -230,9 +230,10 @@ sw_status sw_batch_autotune(sw_batch *batch, int32_t steps_per_trial, const char
  * U^n to U^{n+jump} on H x W grids, jumping `jump` solver steps at a time:
  *   x = normalise(U^n)  (channel c: (u_c - in_offset_c) / in_scale_c; the
  *       input's one-cell halo holds the boundary ghosts);
- *   delta = conv6(relu(conv5(... relu(conv1(x)))))   3x3 "same" convolutions,
- *       3 -> 32 -> 32 -> 32 -> 32 -> 32 -> 3 channels, zero padding in the
- *       hidden layers, BF16 weights and activations, FP32 accumulation;
+ *   A1 = relu(conv1(x)), A_l = A_{l-1} + relu(conv_l(A_{l-1})) for l = 2..5,
+ *   delta = conv6(A5): 3x3 "same" convolutions with bias, 3 -> 32 -> 32 ->
+ *       32 -> 32 -> 32 -> 3 channels, zero padding in the hidden layers,
+ *       BF16 weights and activations, FP32 accumulation;
  *   U^{n+jump} = U^n + delta * out_scale   (residual added in FP32).
  * Parameters: one FP32 master vector (device), layer after layer: weights
  * W[co][tap][ci] (tap = 3 * ky + kx, cross-correlation) then biases b[co];
@@ -251,19 +252,25 @@ typedef struct {
 /* Gate of a surrogate jump, per grid: the jump is rejected, and the plain
  * solver takes it instead, if |M' - M| / M > mass_rel_tol (M = sum of h),
  * if any depth <= hmin, or if any value is non-finite.  project_mass != 0
- * first removes the mean of the predicted dh, so mass is kept exactly. */
+ * first removes the mean of the predicted dh, so mass is kept exactly.
+ * judge != 0 also runs the plain solver over the whole span from the same
+ * start (on a copy the network keeps) and compares: a grid whose relative
+ * L2 error of h, ||h - h_solver||_2 / ||h_solver||_2 over the interior,
+ * exceeds l2_tol takes the solver's result. */
 typedef struct {
     double mass_rel_tol;
     double hmin;
     int32_t project_mass;
-    int32_t reserved;
+    int32_t judge;
+    double l2_tol;
 } sw_gate;
 
 typedef struct sw_net sw_net;
 
 /* Network for H x W grids (W a multiple of 64), up to max_batch grids per
- * call; allocates its weights and activation workspace (about
- * 12 * 32 * 2 * max_batch * (H + 2) * (W + 2) bytes).
+ * call; allocates its weights and activation / gradient workspace (about
+ * 21 * 32 * 2 * max_batch * (H + 2) * (W + 16) bytes, e.g. 12 GB for 256
+ * grids of 256 x 256).
  * Errors: SW_EINVAL, SW_ENOTSUP (other depth / width), SW_ENOMEM, SW_EHIP. */
 sw_status sw_surrogate_create(const sw_net_cfg *cfg, int32_t H, int32_t W, int32_t max_batch, sw_net **out);
 sw_status sw_surrogate_destroy(sw_net *net);
@@ -291,9 +298,17 @@ sw_status sw_surrogate_train_step(sw_net *net, const float *u, const float *u8, 
 /* Async.  Advance every grid of an FP32 batch (all H x W, same boundary
  * conditions) by nsteps (a multiple of jump) in jumps; each jump is gated per
  * grid and rejected grids take jump solver steps instead.  fallbacks (device
- * int32[n], may be NULL) is incremented per rejected jump.  No host sync. */
+ * int32[n], may be NULL) is incremented per rejected jump.  The batch's
+ * per-grid time and step counters count only the solver steps taken (a
+ * network jump has no time step).  Judge mode (gate->judge): l2 (device
+ * double[n], may be NULL) receives each grid's relative L2(h) against the
+ * plain solver; a grid above gate->l2_tol takes the solver's state, time and
+ * step count, and its fallbacks entry is set to nsteps / jump.  The first
+ * judged call on a batch allocates the solver's copy (about the batch's arena
+ * size), kept until the network is destroyed or judges another batch.
+ * No host sync. */
 sw_status sw_surrogate_advance(sw_net *net, sw_batch *solver, int32_t nsteps, const sw_gate *gate,
-                               int32_t *fallbacks, void *stream);
+                               int32_t *fallbacks, double *l2, void *stream);
 
 const char *sw_strerror(sw_status status);
 const char *sw_last_error_detail(void);

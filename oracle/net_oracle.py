@@ -6,27 +6,34 @@ nothing with the HIP path.  Written from the definition of the network:
 * input: ``x_c = (u_c - offset_c) / scale_c`` for ``u = (h, hu, hv)``, with a
   one-cell halo holding the boundary ghosts (reflective: mirror with the
   wall-normal momentum negated; periodic: wrap), arranged NHWC;
-* five hidden layers ``A_l = relu(conv3x3(A_{l-1}, W_l) + b_l)`` with zero
-  padding, then ``delta = conv3x3(A_5, W_6) + b_6`` (3 channels);
+* ``A_1 = relu(Z_1)``, then four residual blocks ``A_l = A_{l-1} + relu(Z_l)``
+  (l = 2..5), then ``delta = Z_6`` (3 channels), where
+  ``Z_l = conv3x3(A_{l-1}, W_l) + b_l`` with zero padding (``A_0`` is the input);
 * ``conv3x3(x, W)[p, co] = sum_{tap, ci} x[p + (tap // 3 - 1, tap % 3 - 1), ci] W[co, tap, ci]``
   (cross-correlation; tap = 3 * ky + kx);
 * loss: mean over pixels and the three channels of ``(delta - target)^2``,
   ``target = (u8 - u) / out_scale``;
 * gradients by the chain rule: ``dZ_6 = 2 (delta - target) / N``,
   ``dW_l[co, tap, ci] = sum_p dZ_l[p, co] A_{l-1}[p + tap, ci]``,
-  ``db_l = sum_p dZ_l``, ``dA_{l-1}[q, ci] = sum_{tap, co} dZ_l[q - tap, co] W_l[co, tap, ci]``,
-  ``dZ_{l-1} = dA_{l-1} * (A_{l-1} > 0)``.
+  ``db_l = sum_p dZ_l``, ``G_{l-1}[q, ci] = sum_{tap, co} dZ_l[q - tap, co] W_l[co, tap, ci]``
+  plus ``G_l`` when layer l is a residual block (``G_l = dL/dA_l``),
+  ``dZ_{l-1} = G_{l-1} * (Z_{l-1} > 0)``.
 
 ``bf16=True`` rounds the tensors the GPU stores in BF16 (input, weights,
-hidden activations, gradient seeds and hidden-layer gradients) to BF16 after
-computing them, so the oracle sees the same quantised values; accumulation is
-FP64 throughout.
+hidden activations, gradient seeds and hidden-layer gradients ``G``, ``dZ``)
+to BF16 after computing them, so the oracle sees the same quantised values;
+accumulation is FP64 throughout.
 """
 from __future__ import annotations
 
 import numpy as np
 
 LAYERS = [(3, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 3)]
+
+
+def residual(l: int) -> bool:
+    """Layer l (0-based) adds its input to its output: the 32 -> 32 blocks."""
+    return 1 <= l <= len(LAYERS) - 2
 
 
 def nparams() -> int:
@@ -97,8 +104,9 @@ def conv3x3(xh, w, b=None):
     return out
 
 
-def forward(params, u, offset, scale, bc_x=0, bc_y=0, bf16_mode=True):
-    """Returns (activations with halo [x0, A1..A5], delta [B][H][W][3])."""
+def forward(params, u, offset, scale, bc_x=0, bc_y=0, bf16_mode=True, masks=None):
+    """Returns (activations with halo [x0, A1..A5], delta [B][H][W][3]);
+    appends ``Z_l > 0`` of the hidden layers to ``masks`` if given."""
     q = bf16 if bf16_mode else (lambda a: np.asarray(a, dtype=np.float64))
     layers = [(q(w), b) for w, b in unpack(params)]
     x = input_tensor(u, offset, scale, bc_x, bc_y, quant=bf16_mode)
@@ -108,7 +116,10 @@ def forward(params, u, offset, scale, bc_x=0, bc_y=0, bf16_mode=True):
         z = conv3x3(a, w, b)
         if l == len(layers) - 1:
             return acts, z
-        a = pad(q(np.maximum(z, 0.0)))
+        if masks is not None:
+            masks.append(z > 0.0)
+        r = np.maximum(z, 0.0)
+        a = pad(q(a[:, 1:-1, 1:-1, :] + r if residual(l) else r))
         acts.append(a)
 
 
@@ -116,7 +127,8 @@ def loss_and_grad(params, u, u8, offset, scale, out_scale, bc_x=0, bc_y=0, bf16_
     """MSE loss and the gradient (flat, master layout) of one pair."""
     q = bf16 if bf16_mode else (lambda a: np.asarray(a, dtype=np.float64))
     layers = [(q(w), b) for w, b in unpack(params)]
-    acts, delta = forward(params, u, offset, scale, bc_x, bc_y, bf16_mode)
+    masks = []
+    acts, delta = forward(params, u, offset, scale, bc_x, bc_y, bf16_mode, masks)
     u = np.asarray(u, dtype=np.float32)
     u8 = np.asarray(u8, dtype=np.float32)
     tgt = np.stack([(u8[:, c] - u[:, c]) / np.float32(out_scale[c]) for c in range(3)], axis=-1).astype(np.float64)
@@ -124,6 +136,7 @@ def loss_and_grad(params, u, u8, offset, scale, out_scale, bc_x=0, bc_y=0, bf16_
     d = delta - tgt
     loss = float(np.sum(d * d) / n)
     dz = q(2.0 * d / n)
+    g_out = None                     # dL/d(output of layer l), needed where layer l is residual
     grads = [None] * len(layers)
     for l in range(len(layers) - 1, -1, -1):
         w, _ = layers[l]
@@ -137,10 +150,14 @@ def loss_and_grad(params, u, u8, offset, scale, out_scale, bc_x=0, bc_y=0, bf16_
         grads[l] = (gw, gb)
         if l == 0:
             break
-        # dA[q] = sum_tap dZ[q - off(tap)] W[tap]: correlation of the padded dZ with the flipped kernel
+        # dL/dA_in[q] = sum_tap dZ[q - off(tap)] W[tap]: correlation of the padded dZ with the flipped kernel
         wflip = w[:, ::-1, :].transpose(2, 1, 0)          # [ci][tap'][co], tap' = 8 - tap
-        da = conv3x3(pad(dz), wflip)
-        dz = q(da * (acts[l][:, 1:-1, 1:-1, :] > 0))
+        g = conv3x3(pad(dz), wflip)
+        if residual(l):
+            g = g + g_out
+        g = q(g)
+        dz = g * masks[l - 1]
+        g_out = g
     flat = np.concatenate([np.concatenate([gw.ravel(), gb]) for gw, gb in grads])
     return loss, flat
 

@@ -185,6 +185,7 @@ int sw_batch_internal_info(const sw_batch *b, SwBatchInfo *info) {
     if (!b || !info) return sw_fail(SW_EINVAL, "batch: NULL");
     if (!b->arena) return sw_fail(SW_EINVAL, "batch: no arena bound");
     info->d_grids = b->d_grids;
+    info->d_sc = b->d_sc;
     info->n = b->n;
     info->cur = b->cur;
     info->dtype = (int)b->opts.dtype;
@@ -205,6 +206,50 @@ int sw_batch_internal_step_masked(sw_batch *b, int nsteps, const int32_t *active
     if ((st = resolve(b, b->tuning, &r)) != SW_OK) return st;
     if ((st = build_tiles(b, r)) != SW_OK) return st;
     return enqueue(b, r, nsteps, b->cur, s, active);
+}
+
+bool sw_batch_internal_compatible(const sw_batch *a, const sw_batch *b) {
+    if (!a || !b || a->n != b->n || a->region != b->region || a->g != b->g || a->dx != b->dx) return false;
+    if (std::memcmp(&a->opts, &b->opts, sizeof a->opts) != 0) return false;
+    for (int i = 0; i < a->n; ++i)
+        if (a->grids[i].nx != b->grids[i].nx || a->grids[i].ny != b->grids[i].ny) return false;
+    return true;
+}
+
+int sw_batch_internal_clone(const sw_batch *src, sw_batch **out, void **arena) {
+    if (!src || !out || !arena) return sw_fail(SW_EINVAL, "batch clone: NULL argument");
+    *out = nullptr;
+    *arena = nullptr;
+    sw_batch *c = nullptr;
+    const sw_halo halo{1, 1, 1, 1};
+    sw_status st = sw_batch_create(src->n, src->grids.data(), halo, src->g, src->dx, &src->opts, &c);
+    if (st != SW_OK) return st;
+    c->tuning = src->tuning;
+    hipError_t e = hipMalloc(arena, 2 * c->region);
+    if (e != hipSuccess) {
+        sw_batch_destroy(c);
+        return sw_fail(e == hipErrorOutOfMemory ? SW_ENOMEM : SW_EHIP, "batch clone: %s", hipGetErrorString(e));
+    }
+    if ((st = sw_batch_bind(c, *arena)) != SW_OK) {
+        sw_batch_destroy(c);
+        (void)hipFree(*arena);
+        *arena = nullptr;
+        return st;
+    }
+    *out = c;
+    return SW_OK;
+}
+
+int sw_batch_internal_copy_state(sw_batch *dst, const sw_batch *src, hipStream_t s) {
+    sw_status st = check_bound(dst);
+    if (st != SW_OK) return st;
+    if ((st = check_bound(src)) != SW_OK) return st;
+    if (!sw_batch_internal_compatible(dst, src)) return sw_fail(SW_EINVAL, "batch copy: batches differ");
+    BHIP(hipMemcpyAsync(dst->arena + (size_t)src->cur * src->region, src->arena + (size_t)src->cur * src->region,
+                        src->region, hipMemcpyDeviceToDevice, s));
+    dst->cur = src->cur;
+    BHIP(sw_batch_launch_reset(dst->d_sc, dst->n, 1, s));
+    return SW_OK;
 }
 
 extern "C" {

@@ -55,6 +55,7 @@ hipError_t sw_batch_launch_copy(const SwBatchGrid *grids, int cur, int n, int nx
 struct sw_batch;
 struct SwBatchInfo {
     const SwBatchGrid *d_grids;
+    SwBatchScalars *d_sc;
     int n, cur, dtype, bc_x, bc_y;
     int same_nx, same_ny;          // common grid size, or -1 if sizes differ
 };
@@ -63,3 +64,11 @@ int sw_batch_internal_info(const sw_batch *b, SwBatchInfo *info);   // returns s
 // (device array), starting from the current buffer.  Does not flip the
 // batch's current buffer (nsteps must be even).
 int sw_batch_internal_step_masked(sw_batch *b, int nsteps, const int32_t *active, hipStream_t s);
+// A batch with the same grids, options and tuning as src, bound to an arena
+// it allocates (*arena; the caller frees it after sw_batch_destroy).
+int sw_batch_internal_clone(const sw_batch *src, sw_batch **out, void **arena);
+// Whether a and b hold the same grids with the same options (a clone's test).
+bool sw_batch_internal_compatible(const sw_batch *a, const sw_batch *b);
+// dst := src's current buffer (whole region, halos included) and current-buffer
+// index, with dst's time and step counters cleared.  Compatible batches only.
+int sw_batch_internal_copy_state(sw_batch *dst, const sw_batch *src, hipStream_t s);

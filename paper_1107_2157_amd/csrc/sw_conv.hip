@@ -73,6 +73,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(SwConvArgs a) {
     }
 
     // epilogue: lane holds channels co = mb*16 + 4g .. +3 of pixel x0 + pb*16 + n
+    const int Wq = sw_planar_pitch(a.W);
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
         const int co0 = mb * 16 + 4 * g;
@@ -81,27 +82,45 @@ __global__ __launch_bounds__(256) void k_conv3x3(SwConvArgs a) {
         for (int pb = 0; pb < NPB; ++pb) {
             const int px = x0 + pb * 16 + n;
             f32x4 v = acc[mb][pb];
-            if (MODE == SW_CONV_RELU_BF16) {
-                const float *bias = a.bias;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r] + bias[co0 + r], 0.f);
-                bf16x4 o = {(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
-                __bf16 *Y = (__bf16 *)a.y + (((int64_t)b * (a.H + 2) + y + 1) * Wp + px + 1) * COUT + co0;
-                *reinterpret_cast<bf16x4 *>(Y) = o;
-            } else if (MODE == SW_CONV_MASK_BF16) {
-                const __bf16 *M = (const __bf16 *)a.mask + (((int64_t)b * (a.H + 2) + y + 1) * Wp + px + 1) * COUT + co0;
-                bf16x4 mk = *reinterpret_cast<const bf16x4 *>(M);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = (float)mk[r] > 0.f ? v[r] : 0.f;
-                bf16x4 o = {(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
-                __bf16 *Y = (__bf16 *)a.y + (((int64_t)b * (a.H + 2) + y + 1) * Wp + px + 1) * COUT + co0;
-                *reinterpret_cast<bf16x4 *>(Y) = o;
-            } else {   // SW_CONV_F32: channels 0..3 (COUT <= 4) with bias, FP32, no halo
+            if (MODE == SW_CONV_F32) {   // channels 0..3 (COUT <= 4) with bias, FP32, no halo
                 if (g != 0) continue;
                 float *Y = a.yf + (((int64_t)b * a.H + y) * a.W + px) * 4;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) v[r] = r < COUT ? v[r] + a.bias[r] : 0.f;
                 *reinterpret_cast<f32x4 *>(Y) = v;
+                continue;
+            }
+            const int64_t at = (((int64_t)b * (a.H + 2) + y + 1) * Wp + px + 1) * COUT + co0;   // NHWC, halo'd
+            bf16x4 o, o2;
+            if (MODE == SW_CONV_RELU_BF16 || MODE == SW_CONV_RESID_BF16) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r] + a.bias[co0 + r], 0.f);
+                if (MODE == SW_CONV_RESID_BF16) {   // CIN == COUT: the block's input at this pixel
+                    const bf16x4 xin = *reinterpret_cast<const bf16x4 *>((const __bf16 *)a.x + at);
+                    o2 = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[r] += (float)xin[r];
+                    if (a.y2) *reinterpret_cast<bf16x4 *>((__bf16 *)a.y2 + at) = o2;
+                }
+                o = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+                *reinterpret_cast<bf16x4 *>((__bf16 *)a.y + at) = o;
+            } else {   // SW_CONV_DGRAD
+                if (a.add) {
+                    const bf16x4 ad = *reinterpret_cast<const bf16x4 *>((const __bf16 *)a.add + at);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[r] += (float)ad[r];
+                }
+                o2 = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+                if (a.y) *reinterpret_cast<bf16x4 *>((__bf16 *)a.y + at) = o2;
+                const bf16x4 mk = *reinterpret_cast<const bf16x4 *>((const __bf16 *)a.mask + at);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) o[r] = (float)mk[r] > 0.f ? o2[r] : (__bf16)0.f;
+                *reinterpret_cast<bf16x4 *>((__bf16 *)a.y2 + at) = o;
+            }
+            if (a.yp) {   // planar copy: 16 lanes of a channel write 16 consecutive pixels
+                __bf16 *P = (__bf16 *)a.yp + (((int64_t)b * (a.H + 2) + y + 1) * COUT + co0) * Wq + px + 8;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) P[(int64_t)r * Wq] = o[r];
             }
         }
     }
@@ -119,11 +138,13 @@ hipError_t launch(const SwConvArgs &a, hipStream_t s) {
 }  // namespace
 
 hipError_t sw_conv3x3(const SwConvArgs &a, int cin, int cout, int mode, hipStream_t s) {
-    if (a.B < 1 || a.H < 1 || a.W < 1) return hipErrorInvalidValue;
+    if (a.B < 1 || a.H < 1 || a.W < 1 || !a.x || !a.w) return hipErrorInvalidValue;
+    if (mode == SW_CONV_F32 ? !a.yf || !a.bias : mode == SW_CONV_DGRAD ? !a.y2 || !a.mask : !a.y || !a.bias)
+        return hipErrorInvalidValue;
     if (cin == 8 && cout == 32 && mode == SW_CONV_RELU_BF16) return launch<8, 32, SW_CONV_RELU_BF16>(a, s);
-    if (cin == 32 && cout == 32 && mode == SW_CONV_RELU_BF16) return launch<32, 32, SW_CONV_RELU_BF16>(a, s);
+    if (cin == 32 && cout == 32 && mode == SW_CONV_RESID_BF16) return launch<32, 32, SW_CONV_RESID_BF16>(a, s);
     if (cin == 32 && cout == 3 && mode == SW_CONV_F32) return launch<32, 3, SW_CONV_F32>(a, s);
-    if (cin == 32 && cout == 32 && mode == SW_CONV_MASK_BF16) return launch<32, 32, SW_CONV_MASK_BF16>(a, s);
-    if (cin == 8 && cout == 32 && mode == SW_CONV_MASK_BF16) return launch<8, 32, SW_CONV_MASK_BF16>(a, s);
+    if (cin == 32 && cout == 32 && mode == SW_CONV_DGRAD) return launch<32, 32, SW_CONV_DGRAD>(a, s);
+    if (cin == 8 && cout == 32 && mode == SW_CONV_DGRAD) return launch<8, 32, SW_CONV_DGRAD>(a, s);
     return hipErrorInvalidValue;
 }

@@ -1,8 +1,9 @@
 // Learned surrogate, host side: a 6-layer 3x3 convolutional residual network
-// (3 -> 32 -> 32 -> 32 -> 32 -> 32 -> 3, ReLU, BF16 weights and activations,
-// FP32 accumulation) that maps U^n to U^{n+8}, trained by the library's own
-// forward / backward kernels, and its gated rollout on a batch of grids with
-// the plain solver as fallback.
+// (3 -> 32 -> 32 -> 32 -> 32 -> 32 -> 3: A1 = relu(Z1), four residual blocks
+// A_l = A_{l-1} + relu(Z_l), delta = Z6; BF16 weights and activations, FP32
+// accumulation) whose output is the normalised increment U^{n+8} - U^n,
+// trained by the library's own forward / backward kernels, and its gated
+// rollout on a batch of grids with the plain solver as fallback.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -38,10 +39,18 @@ struct sw_net {
     float *wpartial = nullptr;
     SwLayerDesc L[kLayers]{};
     SwLayerDesc *L_dev = nullptr;
-    void *x0 = nullptr, *act[kLayers - 1] = {}, *dz[2] = {}, *dz6 = nullptr;
+    // NHWC BF16 tensors with halo; *p are the channel-planar copies the weight
+    // gradient reads; relu[k] = relu(Z) of residual block k + 1 (its mask)
+    void *x0 = nullptr, *act[kLayers - 1] = {}, *relu[kLayers - 2] = {}, *g[2] = {}, *dz[2] = {}, *dz6 = nullptr;
+    void *x0p = nullptr, *actp[kLayers - 1] = {}, *dzp[2] = {}, *dz6p = nullptr;
     float *delta = nullptr, *target = nullptr;
     SwGateStats *stats = nullptr;
     int32_t *active = nullptr;
+    // judge mode: a clone of the advanced batch that runs the plain solver
+    sw_batch *shadow = nullptr;
+    void *shadow_arena = nullptr;
+    SwJudge *judge = nullptr;
+    int32_t *reject = nullptr;
     SwNorm nrm{};
     int64_t adam_t = 0;
     std::vector<void *> allocs;
@@ -67,54 +76,67 @@ sw_status use_dev(const sw_net *n) {
     return SW_OK;
 }
 
-sw_status conv(const sw_net *n, int layer, const void *x, void *y, float *yf, const void *mask, int B, int mode,
-               bool dgrad, hipStream_t s) {
-    const SwLayerDesc &L = n->L[layer];
+size_t planar_bytes(const sw_net *n, int B, int ch) { return (size_t)sw_planar_elems(B, n->H, n->W, ch) * 2; }
+
+bool residual(int l) { return l >= 1 && l <= kLayers - 2; }
+
+SwConvArgs conv_args(const sw_net *n, int B, const void *x) {
     SwConvArgs a{};
     a.x = x;
-    a.y = y;
-    a.yf = yf;
-    a.mask = mask;
     a.B = B;
     a.H = n->H;
     a.W = n->W;
-    if (!dgrad) {
+    return a;
+}
+
+// X0 -> act[0..4] -> delta; with train, also the ReLU parts and planar copies
+sw_status forward(const sw_net *n, int B, bool train, hipStream_t s) {
+    for (int l = 0; l < kLayers; ++l) {
+        const SwLayerDesc &L = n->L[l];
+        SwConvArgs a = conv_args(n, B, l == 0 ? n->x0 : n->act[l - 1]);
         a.w = L.wk;
         a.bias = n->master + L.b_off;
+        int mode = SW_CONV_RELU_BF16;
+        if (l == kLayers - 1) {
+            a.yf = n->delta;
+            mode = SW_CONV_F32;
+        } else {
+            a.y = n->act[l];
+            if (train) a.yp = n->actp[l];
+            if (residual(l)) {
+                mode = SW_CONV_RESID_BF16;
+                if (train) a.y2 = n->relu[l - 1];
+            }
+        }
         SHIP(sw_conv3x3(a, L.cinp, L.cout, mode, s));
-    } else {
-        a.w = L.wd;
-        SHIP(sw_conv3x3(a, L.cdp, L.cin, mode, s));
     }
     return SW_OK;
 }
 
-// X0 -> act[0..4] -> delta
-sw_status forward(const sw_net *n, int B, hipStream_t s) {
-    sw_status st;
-    if ((st = conv(n, 0, n->x0, n->act[0], nullptr, nullptr, B, SW_CONV_RELU_BF16, false, s)) != SW_OK) return st;
-    for (int l = 1; l < kLayers - 1; ++l)
-        if ((st = conv(n, l, n->act[l - 1], n->act[l], nullptr, nullptr, B, SW_CONV_RELU_BF16, false, s)) != SW_OK)
-            return st;
-    return conv(n, kLayers - 1, n->act[kLayers - 2], nullptr, n->delta, nullptr, B, SW_CONV_F32, false, s);
-}
-
-// loss and gradients into n->grad (target already prepared)
+// loss and gradients into n->grad (target and the training forward done):
+// dZ of layer l gives dW_l, db_l, and G = dL/d(input of l) = conv^T(dZ) (+ G
+// of l's output where l is residual), then dZ_{l-1} = G * (Z_{l-1} > 0)
 sw_status backward(sw_net *n, int B, float *loss_out, hipStream_t s) {
-    SHIP(sw_sur_loss(n->delta, n->target, B, n->H, n->W, n->loss_partial, kLossBlocks, n->dz6, s));
+    SHIP(sw_sur_loss(n->delta, n->target, B, n->H, n->W, n->loss_partial, kLossBlocks, n->dz6, n->dz6p, s));
     if (loss_out) SHIP(sw_sur_reduce_sum(n->loss_partial, kLossBlocks, loss_out, s));
-    const void *dz = n->dz6;
+    const void *dz = n->dz6, *dzp = n->dz6p, *gout = nullptr;
     int dzc = 8;
     for (int l = kLayers - 1; l >= 0; --l) {
         const SwLayerDesc &L = n->L[l];
-        const void *a_in = l == 0 ? n->x0 : n->act[l - 1];
-        SHIP(sw_sur_wgrad(dz, dzc, L.cout, a_in, L.cinp, L.cin, B, n->H, n->W, n->wpartial, kWgradBlocks,
-                          n->grad + L.w_off, n->grad + L.b_off, s));
+        SHIP(sw_sur_wgrad(dzp, dzc, L.cout, l == 0 ? n->x0p : n->actp[l - 1], L.cinp, L.cin, B, n->H, n->W,
+                          n->wpartial, kWgradBlocks, n->grad + L.w_off, n->grad + L.b_off, s));
         if (l == 0) break;
-        void *out = n->dz[l & 1];
-        sw_status st = conv(n, l, dz, out, nullptr, n->act[l - 1], B, SW_CONV_MASK_BF16, true, s);
-        if (st != SW_OK) return st;
-        dz = out;
+        SwConvArgs a = conv_args(n, B, dz);
+        a.w = L.wd;
+        a.add = residual(l) ? gout : nullptr;
+        a.mask = l == 1 ? n->act[0] : n->relu[l - 2];
+        a.y = residual(l - 1) ? n->g[l & 1] : nullptr;
+        a.y2 = n->dz[l & 1];
+        a.yp = n->dzp[l & 1];
+        SHIP(sw_conv3x3(a, L.cdp, L.cin, SW_CONV_DGRAD, s));
+        gout = a.y;
+        dz = a.y2;
+        dzp = a.yp;
         dzc = 32;
     }
     return SW_OK;
@@ -123,6 +145,13 @@ sw_status backward(sw_net *n, int B, float *loss_out, hipStream_t s) {
 sw_status relayout(sw_net *n, hipStream_t s) {
     SHIP(sw_sur_relayout(n->master, n->L_dev, kLayers, n->nweights, s));
     return SW_OK;
+}
+
+void drop_shadow(sw_net *n) {
+    if (n->shadow) sw_batch_destroy(n->shadow);
+    if (n->shadow_arena) (void)hipFree(n->shadow_arena);
+    n->shadow = nullptr;
+    n->shadow_arena = nullptr;
 }
 
 sw_status check_net(const sw_net *n, int B) {
@@ -185,14 +214,25 @@ sw_status sw_surrogate_create(const sw_net_cfg *cfg, int32_t H, int32_t W, int32
     if (st == SW_OK) st = dalloc(n, (void **)&n->wpartial, (size_t)kWgradBlocks * (32 * 9 * 32 + 32) * 4);
     if (st == SW_OK) st = dalloc(n, (void **)&n->L_dev, sizeof(n->L));
     if (st == SW_OK) st = dalloc(n, &n->x0, act_bytes(n, max_batch, 8));
-    for (int l = 0; l < kLayers - 1 && st == SW_OK; ++l) st = dalloc(n, &n->act[l], act_bytes(n, max_batch, 32));
-    if (st == SW_OK) st = dalloc(n, &n->dz[0], act_bytes(n, max_batch, 32));
-    if (st == SW_OK) st = dalloc(n, &n->dz[1], act_bytes(n, max_batch, 32));
+    if (st == SW_OK) st = dalloc(n, &n->x0p, planar_bytes(n, max_batch, 8));
+    for (int l = 0; l < kLayers - 1 && st == SW_OK; ++l) {
+        st = dalloc(n, &n->act[l], act_bytes(n, max_batch, 32));
+        if (st == SW_OK) st = dalloc(n, &n->actp[l], planar_bytes(n, max_batch, 32));
+    }
+    for (int k = 0; k < kLayers - 2 && st == SW_OK; ++k) st = dalloc(n, &n->relu[k], act_bytes(n, max_batch, 32));
+    for (int k = 0; k < 2 && st == SW_OK; ++k) {
+        st = dalloc(n, &n->g[k], act_bytes(n, max_batch, 32));
+        if (st == SW_OK) st = dalloc(n, &n->dz[k], act_bytes(n, max_batch, 32));
+        if (st == SW_OK) st = dalloc(n, &n->dzp[k], planar_bytes(n, max_batch, 32));
+    }
     if (st == SW_OK) st = dalloc(n, &n->dz6, act_bytes(n, max_batch, 8));
+    if (st == SW_OK) st = dalloc(n, &n->dz6p, planar_bytes(n, max_batch, 8));
     if (st == SW_OK) st = dalloc(n, (void **)&n->delta, (size_t)max_batch * H * W * 16);
     if (st == SW_OK) st = dalloc(n, (void **)&n->target, (size_t)max_batch * H * W * 16);
     if (st == SW_OK) st = dalloc(n, (void **)&n->stats, (size_t)max_batch * sizeof(SwGateStats));
     if (st == SW_OK) st = dalloc(n, (void **)&n->active, (size_t)max_batch * 4);
+    if (st == SW_OK) st = dalloc(n, (void **)&n->judge, (size_t)max_batch * sizeof(SwJudge));
+    if (st == SW_OK) st = dalloc(n, (void **)&n->reject, (size_t)max_batch * 4);
     if (st == SW_OK && hipMemcpy(n->L_dev, n->L, sizeof(n->L), hipMemcpyHostToDevice) != hipSuccess)
         st = sw_fail(SW_EHIP, "surrogate_create: layer table upload");
     if (st == SW_OK) {
@@ -226,6 +266,7 @@ sw_status sw_surrogate_create(const sw_net_cfg *cfg, int32_t H, int32_t W, int32
 
 sw_status sw_surrogate_destroy(sw_net *n) {
     if (!n) return SW_OK;
+    drop_shadow(n);
     for (void *p : n->allocs) (void)hipFree(p);
     delete n;
     return SW_OK;
@@ -262,8 +303,8 @@ sw_status sw_surrogate_forward(sw_net *n, const float *u, int32_t B, float *delt
     if (st != SW_OK) return st;
     if (!u) return sw_fail(SW_EINVAL, "surrogate_forward: NULL input");
     hipStream_t s = (hipStream_t)stream;
-    SHIP(sw_sur_prep_dense(u, nullptr, B, n->H, n->W, n->cfg.bc_x, n->cfg.bc_y, n->nrm, n->x0, nullptr, s));
-    if ((st = forward(n, B, s)) != SW_OK) return st;
+    SHIP(sw_sur_prep_dense(u, nullptr, B, n->H, n->W, n->cfg.bc_x, n->cfg.bc_y, n->nrm, n->x0, nullptr, nullptr, s));
+    if ((st = forward(n, B, false, s)) != SW_OK) return st;
     if (delta) SHIP(hipMemcpyAsync(delta, n->delta, (size_t)B * n->H * n->W * 16, hipMemcpyDeviceToDevice, s));
     return SW_OK;
 }
@@ -286,8 +327,8 @@ sw_status sw_surrogate_grad(sw_net *n, const float *u, const float *u8, int32_t 
     if (st != SW_OK) return st;
     if (!u || !u8) return sw_fail(SW_EINVAL, "surrogate_grad: NULL input");
     hipStream_t s = (hipStream_t)stream;
-    SHIP(sw_sur_prep_dense(u, u8, B, n->H, n->W, n->cfg.bc_x, n->cfg.bc_y, n->nrm, n->x0, n->target, s));
-    if ((st = forward(n, B, s)) != SW_OK) return st;
+    SHIP(sw_sur_prep_dense(u, u8, B, n->H, n->W, n->cfg.bc_x, n->cfg.bc_y, n->nrm, n->x0, n->x0p, n->target, s));
+    if ((st = forward(n, B, true, s)) != SW_OK) return st;
     if ((st = backward(n, B, loss, s)) != SW_OK) return st;
     if (grad) SHIP(hipMemcpyAsync(grad, n->grad, n->nparams * 4, hipMemcpyDeviceToDevice, s));
     return SW_OK;
@@ -309,7 +350,7 @@ sw_status sw_surrogate_train_step(sw_net *n, const float *u, const float *u8, in
 }
 
 sw_status sw_surrogate_advance(sw_net *n, sw_batch *solver, int32_t nsteps, const sw_gate *gate,
-                               int32_t *fallbacks, void *stream) {
+                               int32_t *fallbacks, double *l2, void *stream) {
     if (!n || !solver || !gate) return sw_fail(SW_EINVAL, "surrogate_advance: NULL argument");
     SwBatchInfo bi;
     sw_status st = (sw_status)sw_batch_internal_info(solver, &bi);
@@ -322,12 +363,20 @@ sw_status sw_surrogate_advance(sw_net *n, sw_batch *solver, int32_t nsteps, cons
         return sw_fail(SW_EINVAL, "surrogate_advance: nsteps %d is not a multiple of the jump %d", nsteps, n->cfg.jump);
     if (bi.bc_x != n->cfg.bc_x || bi.bc_y != n->cfg.bc_y)
         return sw_fail(SW_EINVAL, "surrogate_advance: boundary conditions differ from the network's");
+    if (gate->judge && !(gate->l2_tol >= 0)) return sw_fail(SW_EINVAL, "surrogate_advance: l2_tol %g", gate->l2_tol);
     hipStream_t s = (hipStream_t)stream;
     const int B = bi.n, cur = bi.cur;
+    if (gate->judge) {   // the plain solver's copy of U^n, and the books at the start
+        if (n->shadow && !sw_batch_internal_compatible(n->shadow, solver)) drop_shadow(n);
+        if (!n->shadow && (st = (sw_status)sw_batch_internal_clone(solver, &n->shadow, &n->shadow_arena)) != SW_OK)
+            return st;
+        if ((st = (sw_status)sw_batch_internal_copy_state(n->shadow, solver, s)) != SW_OK) return st;
+        SHIP(sw_sur_judge_begin(bi.d_sc, B, n->judge, s));
+    }
     if ((st = sw_batch_fill_halo(solver, stream)) != SW_OK) return st;
     for (int j = 0; j < nsteps / n->cfg.jump; ++j) {
         SHIP(sw_sur_prep_planes(bi.d_grids, cur, B, n->H, n->W, n->nrm, n->x0, s));
-        if ((st = forward(n, B, s)) != SW_OK) return st;
+        if ((st = forward(n, B, false, s)) != SW_OK) return st;
         SHIP(sw_sur_zero_stats(n->stats, B, s));
         if (gate->project_mass) SHIP(sw_sur_delta_sum(n->delta, B, n->H, n->W, n->stats, s));
         SHIP(sw_sur_apply(n->delta, bi.d_grids, cur, B, n->H, n->W, n->nrm, gate->project_mass, bi.bc_x, bi.bc_y,
@@ -337,6 +386,14 @@ sw_status sw_surrogate_advance(sw_net *n, sw_batch *solver, int32_t nsteps, cons
         if ((st = (sw_status)sw_batch_internal_step_masked(solver, n->cfg.jump, n->active, s)) != SW_OK) return st;
         // accepted grids: the prediction becomes U^{n+jump}
         SHIP(sw_sur_accept(bi.d_grids, cur, B, n->H, n->W, n->active, s));
+    }
+    if (gate->judge) {   // the plain solver over the same span, then the verdict per grid
+        if ((st = sw_batch_step(n->shadow, nsteps, stream)) != SW_OK) return st;
+        SwBatchInfo si;
+        if ((st = (sw_status)sw_batch_internal_info(n->shadow, &si)) != SW_OK) return st;
+        if (si.cur != cur) return sw_fail(SW_EINVAL, "surrogate_advance: judge buffers out of step");
+        SHIP(sw_sur_judge(bi.d_grids, si.d_grids, cur, B, n->H, n->W, n->judge, bi.d_sc, si.d_sc, gate->l2_tol,
+                          nsteps / n->cfg.jump, n->reject, fallbacks, l2, s));
     }
     return SW_OK;
 }

@@ -46,7 +46,7 @@ __device__ __forceinline__ void store_x0(__bf16 *x0, float a, float b, float c) 
 }
 
 __global__ __launch_bounds__(256) void k_prep_dense(const float *u, const float *u8, int B, int H, int W, int bcx,
-                                                    int bcy, SwNorm nrm, __bf16 *x0, float *target) {
+                                                    int bcy, SwNorm nrm, __bf16 *x0, __bf16 *x0p, float *target) {
     const int Wp = W + 2, Hp = H + 2;
     const int64_t n = (int64_t)B * Hp * Wp;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
@@ -58,8 +58,15 @@ __global__ __launch_bounds__(256) void k_prep_dense(const float *u, const float 
         const int64_t plane = (int64_t)H * W;
         const float *ub = u + (int64_t)b * 3 * plane + (int64_t)y * W + x;
         const float h = ub[0], hu = fx * ub[plane], hv = fy * ub[2 * plane];
-        store_x0(x0 + idx * 8, (h - nrm.in_off[0]) / nrm.in_scale[0], (hu - nrm.in_off[1]) / nrm.in_scale[1],
-                 (hv - nrm.in_off[2]) / nrm.in_scale[2]);
+        const float c0 = (h - nrm.in_off[0]) / nrm.in_scale[0], c1 = (hu - nrm.in_off[1]) / nrm.in_scale[1],
+                    c2 = (hv - nrm.in_off[2]) / nrm.in_scale[2];
+        store_x0(x0 + idx * 8, c0, c1, c2);
+        if (x0p) {   // planar: channel rows of pitch W + 16, halo column xx at xx + 7
+            __bf16 *P = x0p + ((int64_t)b * Hp + yy) * 8 * sw_planar_pitch(W) + xx + 7;
+            P[0] = (__bf16)c0;
+            P[sw_planar_pitch(W)] = (__bf16)c1;
+            P[2 * sw_planar_pitch(W)] = (__bf16)c2;
+        }
         if (target && xx >= 1 && xx <= W && yy >= 1 && yy <= H) {
             const float *vb = u8 + (int64_t)b * 3 * plane + (int64_t)y * W + x;
             float *tg = target + (((int64_t)b * H + y) * W + x) * 4;
@@ -90,7 +97,7 @@ __global__ __launch_bounds__(256) void k_prep_planes(const SwBatchGrid *grids, i
 }
 
 __global__ __launch_bounds__(256) void k_loss(const float *pred, const float *target, int B, int H, int W,
-                                              float *partial, __bf16 *dz) {
+                                              float *partial, __bf16 *dz, __bf16 *dzp) {
     const int64_t n = (int64_t)B * H * W;
     const float scale = 2.f / (3.f * (float)n);
     float acc = 0.f;
@@ -102,7 +109,12 @@ __global__ __launch_bounds__(256) void k_loss(const float *pred, const float *ta
         const int b = (int)(p / ((int64_t)H * W));
         const int r = (int)(p - (int64_t)b * H * W);
         const int y = r / W, x = r - y * W;
-        store_x0(dz + (((int64_t)b * (H + 2) + y + 1) * (W + 2) + x + 1) * 8, scale * d0, scale * d1, scale * d2);
+        const float g0 = scale * d0, g1 = scale * d1, g2 = scale * d2;
+        store_x0(dz + (((int64_t)b * (H + 2) + y + 1) * (W + 2) + x + 1) * 8, g0, g1, g2);
+        __bf16 *P = dzp + ((int64_t)b * (H + 2) + y + 1) * 8 * sw_planar_pitch(W) + x + 8;
+        P[0] = (__bf16)g0;
+        P[sw_planar_pitch(W)] = (__bf16)g1;
+        P[2 * sw_planar_pitch(W)] = (__bf16)g2;
     }
     __shared__ float red[4];
     acc = wave_sum_f(acc);
@@ -121,67 +133,107 @@ __global__ void k_reduce_sum(const float *partial, int n, float *out) {
     if (threadIdx.x == 0) out[0] = (float)(red[0] + red[1] + red[2] + red[3]);
 }
 
-// Weight gradient partials: each block walks 64-pixel row segments; LDS holds
-// the segment's dZ (64 x COUTP) and the three input rows it needs
-// (3 x 66 x CINP).  Thread (co, ci group of 4) accumulates all 9 taps.
+// Weight gradient partials on MFMA (v_mfma_f32_16x16x32_bf16), K = pixels:
+//     dW[co][(tap, ci)] = sum_p dZ[p][co] A[p + off(tap)][ci]
+// from the channel-planar tensors, where 8 consecutive pixels of one channel
+// are one aligned 16-byte load.  A K step is a 32-pixel chunk of one row:
+// lane (n, kg) = (lane % 16, lane / 16) takes pixels x + 8 kg .. + 7.  The
+// dZ operand (rows co) is loaded as is; the activation operand of tap (dy, dx)
+// is the row y + dy - 1 shifted by dx - 1 pixels, built from three aligned
+// loads with 16-bit funnel shifts.  Wave w owns input row dy = w / CH and,
+// for CINP = 32, channel half w % CH, i.e. the three taps (dy, 0..2) of 16
+// input channels (3 N tiles); for CINP = 8 a 16-wide N tile holds two taps of
+// 8 channels (2 N tiles).  Wave 0 also forms db with an all-ones operand.
+// Each block sums a contiguous range of chunks and writes its partial dW, db.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
 template <int CINP, int COUTP>
-__global__ __launch_bounds__(256) void k_wgrad(const __bf16 *dz, const __bf16 *a, int cout, int cin, int B, int H,
-                                               int W, float *partial, int nent) {
-    __shared__ __bf16 sdz[64 * COUTP];
-    __shared__ __bf16 sa[3 * 66 * CINP];
-    constexpr int CG = CINP / 4;
-    const int t = threadIdx.x;
-    const int co = t / CG, cg = t % CG;
-    float acc[9][4];
+__global__ __launch_bounds__(384) void k_wgrad_mfma(const __bf16 *dzp, const __bf16 *ap, int cout, int cin, int B,
+                                                    int H, int W, float *partial, int nent) {
+    constexpr int CH = CINP == 32 ? 2 : 1;
+    constexpr int MB = (COUTP + 15) / 16;
+    constexpr int NT = CINP == 32 ? 3 : 2;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n = lane & 15, kg = lane >> 4;
+    const int dy = w / CH, chalf = w % CH;
+    const int Wq = sw_planar_pitch(W);
+    const int cpr = W / 32;
+    const int64_t nchunks = (int64_t)B * H * cpr;
+    const int64_t c0 = nchunks * blockIdx.x / gridDim.x, c1 = nchunks * (blockIdx.x + 1) / gridDim.x;
+    const int ci = CINP == 32 ? chalf * 16 + n : (n & 7);
+    const u32x4 ones = {0x3F803F80u, 0x3F803F80u, 0x3F803F80u, 0x3F803F80u};   // bf16 1.0 pairs
+
+    f32x4 acc[MB][NT], accb[MB];
 #pragma unroll
-    for (int k = 0; k < 9; ++k)
+    for (int mb = 0; mb < MB; ++mb) {
+        accb[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[k][r] = 0.f;
-    float bacc = 0.f;
-    const int segs = W / 64;
-    const int64_t nseg = (int64_t)B * H * segs;
-    const int Wp = W + 2;
-    for (int64_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
-        const int b = (int)(seg / ((int64_t)H * segs));
-        const int rem = (int)(seg - (int64_t)b * H * segs);
-        const int y = rem / segs, x0 = (rem - y * segs) * 64;
-        __syncthreads();
-        for (int i = t; i < 64 * COUTP / 8; i += 256) {
-            const int px = i / (COUTP / 8), part = i % (COUTP / 8);
-            *reinterpret_cast<bf16x8 *>(&sdz[px * COUTP + part * 8]) = *reinterpret_cast<const bf16x8 *>(
-                dz + (((int64_t)b * (H + 2) + y + 1) * Wp + x0 + 1 + px) * COUTP + part * 8);
+        for (int t = 0; t < NT; ++t) acc[mb][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int64_t c = c0; c < c1; ++c) {
+        const int b = (int)(c / ((int64_t)H * cpr));
+        const int rem = (int)(c - (int64_t)b * H * cpr);
+        const int y = rem / cpr;
+        const int x = (rem - y * cpr) * 32 + 8 * kg;
+        bf16x8 aop[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const int co = mb * 16 + n;
+            aop[mb] = co < COUTP ? *reinterpret_cast<const bf16x8 *>(
+                                       dzp + (((int64_t)b * (H + 2) + y + 1) * COUTP + co) * Wq + x + 8)
+                                 : bf16x8{};
         }
-        for (int i = t; i < 3 * 66 * CINP / 8; i += 256) {
-            const int rr = i / (66 * CINP / 8), rem2 = i % (66 * CINP / 8);
-            const int px = rem2 / (CINP / 8), part = rem2 % (CINP / 8);
-            *reinterpret_cast<bf16x8 *>(&sa[(rr * 66 + px) * CINP + part * 8]) = *reinterpret_cast<const bf16x8 *>(
-                a + (((int64_t)b * (H + 2) + y + rr) * Wp + x0 + px) * CINP + part * 8);
+        const __bf16 *row = ap + (((int64_t)b * (H + 2) + y + dy) * CINP + ci) * Wq + x;
+        const u32x4 pv = *reinterpret_cast<const u32x4 *>(row);
+        const u32x4 cv = *reinterpret_cast<const u32x4 *>(row + 8);
+        const u32x4 nv = *reinterpret_cast<const u32x4 *>(row + 16);
+        // pixel x - 1 + j (dx = 0), x + j (dx = 1), x + 1 + j (dx = 2), j = 0..7
+        const u32x4 s0 = {__builtin_amdgcn_alignbit(cv[0], pv[3], 16), __builtin_amdgcn_alignbit(cv[1], cv[0], 16),
+                          __builtin_amdgcn_alignbit(cv[2], cv[1], 16), __builtin_amdgcn_alignbit(cv[3], cv[2], 16)};
+        const u32x4 s2 = {__builtin_amdgcn_alignbit(cv[1], cv[0], 16), __builtin_amdgcn_alignbit(cv[2], cv[1], 16),
+                          __builtin_amdgcn_alignbit(cv[3], cv[2], 16), __builtin_amdgcn_alignbit(nv[0], cv[3], 16)};
+        bf16x8 bop[NT];
+        if (CINP == 32) {
+            bop[0] = as_bf16x8(s0);
+            bop[1] = as_bf16x8(cv);
+            bop[2] = as_bf16x8(s2);
+        } else {
+            bop[0] = as_bf16x8(n < 8 ? s0 : cv);
+            bop[1] = n < 8 ? as_bf16x8(s2) : bf16x8{};
         }
-        __syncthreads();
-        if (co < cout) {
-            for (int p = 0; p < 64; ++p) {
-                const float d = (float)sdz[p * COUTP + co];
-                bacc += d;
 #pragma unroll
-                for (int tap = 0; tap < 9; ++tap) {
-                    const bf16x4 av = *reinterpret_cast<const bf16x4 *>(&sa[((tap / 3) * 66 + p + tap % 3) * CINP + 4 * cg]);
+        for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[tap][r] = fmaf(d, (float)av[r], acc[tap][r]);
-                }
-            }
+            for (int t = 0; t < NT; ++t) acc[mb][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop[mb], bop[t], acc[mb][t], 0, 0, 0);
+            if (w == 0) accb[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop[mb], as_bf16x8(ones), accb[mb], 0, 0, 0);
         }
     }
+    // D[m][n] in lane n + 16 (m / 4), element m % 4
     float *P = partial + (int64_t)blockIdx.x * nent;
-    if (co < cout) {
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap)
+    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int ci = 4 * cg + r;
-                if (ci < cin) P[(co * 9 + tap) * cin + ci] = acc[tap][r];
+        for (int r = 0; r < 4; ++r) {
+            const int co = mb * 16 + 4 * kg + r;
+            if (co >= cout) continue;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                int tap, cc;
+                if (CINP == 32) {
+                    tap = 3 * dy + t;
+                    cc = ci;
+                } else {
+                    tap = 3 * dy + (t == 0 ? (n >> 3) : 2);
+                    cc = n & 7;
+                    if (t == 1 && n >= 8) continue;
+                }
+                if (cc < cin) P[(co * 9 + tap) * cin + cc] = acc[mb][t][r];
             }
-        if (cg == 0) P[cout * 9 * cin + co] = bacc;
-    }
+            if (w == 0 && n == 0) P[cout * 9 * cin + co] = accb[mb][r];
+        }
 }
 
 __global__ void k_wgrad_reduce(const float *partial, int nblocks, int nent, int nw, float *grad_w, float *grad_b) {
@@ -309,6 +361,70 @@ __global__ __launch_bounds__(256) void k_accept(const SwBatchGrid *grids, int cu
     }
 }
 
+// Judge, before the rollout: remember every grid's time and step count and
+// clear the sums.
+__global__ void k_judge_begin(const SwBatchScalars *sc, int B, SwJudge *j) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    j[b].d2 = 0.0;
+    j[b].r2 = 0.0;
+    j[b].t0 = sc[b].t;
+    j[b].steps0 = sc[b].steps;
+}
+
+// Per grid (blockIdx.y): sums of (h - h_ref)^2 and h_ref^2 over the interior.
+__global__ __launch_bounds__(256) void k_judge_sums(const SwBatchGrid *ga, const SwBatchGrid *gr, int cur, int H,
+                                                    int W, SwJudge *j) {
+    const int b = blockIdx.y;
+    const float *A = (const float *)ga[b].plane[cur][0];
+    const float *R = (const float *)gr[b].plane[cur][0];
+    const int64_t pa = ga[b].pitch, pr = gr[b].pitch, n = (int64_t)H * W;
+    double d2 = 0.0, r2 = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+        const double r = R[y * pr + x], d = (double)A[y * pa + x] - r;
+        d2 += d * d;
+        r2 += r * r;
+    }
+    d2 = wave_sum_d(d2);
+    r2 = wave_sum_d(r2);
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&j[b].d2, d2);
+        atomicAdd(&j[b].r2, r2);
+    }
+}
+
+__global__ void k_judge_decide(SwJudge *j, int B, SwBatchScalars *sc, const SwBatchScalars *rsc, double l2_tol,
+                               int jumps, int *reject, int *fallbacks, double *l2) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const double e = sqrt(j[b].d2 / j[b].r2);
+    const int rej = !(e <= l2_tol);
+    reject[b] = rej;
+    if (l2) l2[b] = e;
+    if (rej) {
+        if (fallbacks) fallbacks[b] = jumps;
+        sc[b].t = j[b].t0 + rsc[b].t;
+        sc[b].last_dt = rsc[b].last_dt;
+        sc[b].steps = j[b].steps0 + rsc[b].steps;
+        sc[b].unstable |= rsc[b].unstable;
+    }
+}
+
+// Rejected grids: copy the solver's halo'd rectangle (buffer cur) over the rollout's.
+__global__ __launch_bounds__(256) void k_judge_copy(const SwBatchGrid *ga, const SwBatchGrid *gr, int cur, int H,
+                                                    int W, const int *reject) {
+    const int b = blockIdx.y;
+    if (!reject[b]) return;
+    const int64_t n = (int64_t)(H + 2) * (W + 2);
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const int yy = (int)(p / (W + 2)), xx = (int)(p - (int64_t)yy * (W + 2));
+        const int64_t oa = (int64_t)(yy - 1) * ga[b].pitch + (xx - 1), orr = (int64_t)(yy - 1) * gr[b].pitch + (xx - 1);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ((float *)ga[b].plane[cur][k])[oa] = ((const float *)gr[b].plane[cur][k])[orr];
+    }
+}
+
 unsigned grid_for(int64_t n, int cap = 16384) {
     int64_t b = (n + 255) / 256;
     if (b > cap) b = cap;
@@ -319,9 +435,9 @@ unsigned grid_for(int64_t n, int cap = 16384) {
 }  // namespace
 
 hipError_t sw_sur_prep_dense(const float *u, const float *u8, int B, int H, int W, int bc_x, int bc_y, SwNorm nrm,
-                             void *x0, float *target, hipStream_t s) {
-    k_prep_dense<<<grid_for((int64_t)B * (H + 2) * (W + 2)), 256, 0, s>>>(u, u8, B, H, W, bc_x, bc_y, nrm,
-                                                                           (__bf16 *)x0, u8 ? target : nullptr);
+                             void *x0, void *x0p, float *target, hipStream_t s) {
+    k_prep_dense<<<grid_for((int64_t)B * (H + 2) * (W + 2)), 256, 0, s>>>(
+        u, u8, B, H, W, bc_x, bc_y, nrm, (__bf16 *)x0, (__bf16 *)x0p, u8 ? target : nullptr);
     return hipGetLastError();
 }
 
@@ -332,8 +448,8 @@ hipError_t sw_sur_prep_planes(const SwBatchGrid *grids, int cur, int B, int H, i
 }
 
 hipError_t sw_sur_loss(const float *pred, const float *target, int B, int H, int W, float *partial, int nblocks,
-                       void *dz, hipStream_t s) {
-    k_loss<<<nblocks, 256, 0, s>>>(pred, target, B, H, W, partial, (__bf16 *)dz);
+                       void *dz, void *dzp, hipStream_t s) {
+    k_loss<<<nblocks, 256, 0, s>>>(pred, target, B, H, W, partial, (__bf16 *)dz, (__bf16 *)dzp);
     return hipGetLastError();
 }
 
@@ -342,16 +458,19 @@ hipError_t sw_sur_reduce_sum(const float *partial, int n, float *out, hipStream_
     return hipGetLastError();
 }
 
-hipError_t sw_sur_wgrad(const void *dz, int coutp, int cout, const void *a, int cinp, int cin, int B, int H, int W,
+hipError_t sw_sur_wgrad(const void *dzp, int coutp, int cout, const void *ap, int cinp, int cin, int B, int H, int W,
                         float *partial, int nblocks, float *grad_w, float *grad_b, hipStream_t s) {
-    if (W % 64 != 0) return hipErrorInvalidValue;
+    if (W % 32 != 0 || nblocks < 1 || cout > coutp || cin > cinp) return hipErrorInvalidValue;
     const int nent = cout * 9 * cin + cout;
+    const int64_t nchunks = (int64_t)B * H * (W / 32);
+    if (nchunks < nblocks) nblocks = (int)nchunks;
+    const __bf16 *dz = (const __bf16 *)dzp, *a = (const __bf16 *)ap;
     if (cinp == 32 && coutp == 32)
-        k_wgrad<32, 32><<<nblocks, 256, 0, s>>>((const __bf16 *)dz, (const __bf16 *)a, cout, cin, B, H, W, partial, nent);
+        k_wgrad_mfma<32, 32><<<nblocks, 384, 0, s>>>(dz, a, cout, cin, B, H, W, partial, nent);
     else if (cinp == 8 && coutp == 32)
-        k_wgrad<8, 32><<<nblocks, 256, 0, s>>>((const __bf16 *)dz, (const __bf16 *)a, cout, cin, B, H, W, partial, nent);
+        k_wgrad_mfma<8, 32><<<nblocks, 192, 0, s>>>(dz, a, cout, cin, B, H, W, partial, nent);
     else if (cinp == 32 && coutp == 8)
-        k_wgrad<32, 8><<<nblocks, 256, 0, s>>>((const __bf16 *)dz, (const __bf16 *)a, cout, cin, B, H, W, partial, nent);
+        k_wgrad_mfma<32, 8><<<nblocks, 384, 0, s>>>(dz, a, cout, cin, B, H, W, partial, nent);
     else
         return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
@@ -398,5 +517,22 @@ hipError_t sw_sur_gate(SwGateStats *st, int B, double mass_tol, double hmin, int
 hipError_t sw_sur_accept(const SwBatchGrid *grids, int cur, int B, int H, int W, const int *active, hipStream_t s) {
     dim3 grid(grid_for((int64_t)(H + 2) * (W + 2), 64), B);
     k_accept<<<grid, 256, 0, s>>>(grids, cur, H, W, active);
+    return hipGetLastError();
+}
+
+hipError_t sw_sur_judge_begin(const SwBatchScalars *sc, int B, SwJudge *j, hipStream_t s) {
+    k_judge_begin<<<(B + 255) / 256, 256, 0, s>>>(sc, B, j);
+    return hipGetLastError();
+}
+
+hipError_t sw_sur_judge(const SwBatchGrid *a, const SwBatchGrid *ref, int cur, int B, int H, int W, SwJudge *j,
+                        SwBatchScalars *sc, const SwBatchScalars *ref_sc, double l2_tol, int jumps, int *reject,
+                        int *fallbacks, double *l2, hipStream_t s) {
+    k_judge_sums<<<dim3(grid_for((int64_t)H * W, 64), B), 256, 0, s>>>(a, ref, cur, H, W, j);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_judge_decide<<<(B + 255) / 256, 256, 0, s>>>(j, B, sc, ref_sc, l2_tol, jumps, reject, fallbacks, l2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_judge_copy<<<dim3(grid_for((int64_t)(H + 2) * (W + 2), 64), B), 256, 0, s>>>(a, ref, cur, H, W, reject);
     return hipGetLastError();
 }

@@ -38,6 +38,7 @@ SEED_BUMPS_16384 = 3
 SEED_BATCH_SIDES = 4
 SEED_BATCH_GRID0 = 4000
 SEED_TRAJ0 = 5000
+SEED_SURR_EVAL0 = 9000
 
 
 class SplitMix64:

@@ -11,9 +11,12 @@ pairs ``(U^t, U^{t+jump})`` for every ``t <= frames - 1 - jump``.
 """
 from __future__ import annotations
 
+import json
 import math
+import os
 import time
 
+import numpy as np
 import torch
 
 from . import ics, sw
@@ -90,17 +93,20 @@ def rel_l2_h(h, h_ref):
     return (d.norm(dim=1) / r.norm(dim=1)), (d.norm(dim=1) / (r - r.mean(dim=1, keepdim=True)).norm(dim=1))
 
 
-def rollout(net, u0: torch.Tensor, nsteps: int, gate: dict | None = None, timed: bool = True):
+def rollout(net, u0: torch.Tensor, nsteps: int, gate: dict | None = None, l2: torch.Tensor | None = None,
+            batch: "sw.Batch | None" = None):
     """Surrogate rollout of a dense [n][3][H][W] state: returns (final state,
-    fallbacks per grid, seconds)."""
+    fallbacks per grid, seconds).  gate: keyword arguments of
+    ``Surrogate.advance`` (judge mode writes ``l2``); ``batch`` reuses a batch
+    of the right shape."""
     n, _, H, W = u0.shape
-    b = sw.Batch([(W, H)] * n, dtype="f32")
+    b = batch if batch is not None else sw.Batch([(W, H)] * n, dtype="f32")
     b.load(u0)
     fb = torch.zeros(n, dtype=torch.int32, device="cuda")
     gate = gate or {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    net.advance(b, nsteps, fallbacks=fb, **gate)
+    net.advance(b, nsteps, fallbacks=fb, l2=l2, **gate)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     return b.export(), fb.cpu(), sec
@@ -121,3 +127,24 @@ def solver_run(u0: torch.Tensor, nsteps: int):
     sec = time.perf_counter() - t0
     b.sync_status()
     return b.export(), sec
+
+
+WEIGHTS_256 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "surrogate_256x256_j8.npz")
+
+
+def save_weights(path: str, net: "sw.Surrogate", in_offset, in_scale, out_scale, meta: dict):
+    """FP32 master parameters, normalisation and a JSON description in an
+    .npz of plain arrays (loadable without pickle)."""
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    np.savez(path, params=net.get_params().cpu().numpy(), in_offset=np.asarray(in_offset, np.float32),
+             in_scale=np.asarray(in_scale, np.float32), out_scale=np.asarray(out_scale, np.float32),
+             jump=np.int32(net.jump), H=np.int32(net.H), W=np.int32(net.W), meta=np.array(json.dumps(meta)))
+
+
+def load_weights(path: str, max_batch: int, seed: int = 0) -> tuple:
+    """(network with the stored weights and normalisation, meta dict)."""
+    with np.load(path, allow_pickle=False) as z:
+        net = sw.Surrogate(int(z["H"]), int(z["W"]), max_batch, jump=int(z["jump"]), seed=seed)
+        net.set_params(torch.from_numpy(z["params"]))
+        net.set_norm(tuple(z["in_offset"]), tuple(z["in_scale"]), tuple(z["out_scale"]))
+        return net, json.loads(str(z["meta"]))

@@ -71,7 +71,7 @@ class NetCfg(ctypes.Structure):
 
 class Gate(ctypes.Structure):
     _fields_ = [("mass_rel_tol", ctypes.c_double), ("hmin", ctypes.c_double), ("project_mass", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("judge", ctypes.c_int32), ("l2_tol", ctypes.c_double)]
 
 
 class State(ctypes.Structure):
@@ -133,7 +133,7 @@ SIGNATURES = {
     "sw_surrogate_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                                ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p]),
     "sw_surrogate_advance": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Gate),
-                                            ctypes.c_void_p, ctypes.c_void_p]),
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sw_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sw_last_error_detail": (ctypes.c_char_p, []),
 }
@@ -433,7 +433,8 @@ class Surrogate:
 
     def set_params(self, params):
         t = torch.as_tensor(params, dtype=torch.float32).to("cuda").contiguous()
-        assert t.numel() == self.nparams
+        if t.numel() != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters, got {t.numel()}")
         torch.cuda.synchronize()
         _hip_d2d(self._master_ptr, t.data_ptr(), self.nparams * 4)
         check(lib().sw_surrogate_sync_weights(self.handle, _stream_handle()), "sw_surrogate_sync_weights")
@@ -486,7 +487,14 @@ class Surrogate:
         return self.loss
 
     def advance(self, batch: "Batch", nsteps: int, mass_rel_tol=1e-4, hmin=0.0, project_mass=True,
-                fallbacks: torch.Tensor | None = None):
-        gate = Gate(mass_rel_tol, hmin, 1 if project_mass else 0, 0)
+                fallbacks: torch.Tensor | None = None, judge: bool = False, l2_tol: float = 1e-2,
+                l2: torch.Tensor | None = None):
+        """Gated rollout of `batch` by nsteps; fallbacks (int32, n) counts the
+        rejected jumps; in judge mode l2 (float64, n) receives each grid's
+        relative L2(h) against the plain solver."""
+        for t, dt, name in ((fallbacks, torch.int32, "fallbacks"), (l2, torch.float64, "l2")):
+            if t is not None and (t.dtype != dt or not t.is_cuda or not t.is_contiguous() or t.numel() < batch.n):
+                raise ValueError(f"{name}: contiguous {dt} device tensor of {batch.n} entries expected")
+        gate = Gate(mass_rel_tol, hmin, 1 if project_mass else 0, 1 if judge else 0, l2_tol)
         check(lib().sw_surrogate_advance(self.handle, batch.handle, nsteps, ctypes.byref(gate), _ptr(fallbacks),
-                                         _stream_handle()), "sw_surrogate_advance")
+                                         _ptr(l2), _stream_handle()), "sw_surrogate_advance")

@@ -75,3 +75,29 @@ def test_null_arguments():
     assert L.sw_get_tuning(None, None) == sw.EINVAL
     assert L.sw_destroy(None) == sw.OK
     assert L.sw_strerror(sw.EUNSTABLE).decode().startswith("unstable")
+
+
+STRUCTS = {"sw_grid": sw.Grid, "sw_halo": sw.Halo, "sw_opts": sw.Opts, "sw_layout": sw.Layout,
+           "sw_tuning": sw.Tuning, "sw_net_cfg": sw.NetCfg, "sw_gate": sw.Gate, "sw_state": sw.State}
+
+
+def test_binding_structs_match_header(tmp_path):
+    """Every struct the binding marshals has the header's size and field
+    offsets (compiled from include/sw.h with the host C compiler)."""
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sw.h"', "int main(void) {"]
+    for cname, cls in STRUCTS.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, cls in STRUCTS.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)

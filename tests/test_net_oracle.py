@@ -68,5 +68,28 @@ def test_gradient_matches_central_differences():
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) * max(1.0, loss), (i, fd, g[i])
 
 
+@pytest.mark.parametrize("c", [0.0, 0.375])
+def test_residual_blocks_add_relu_of_bias(c):
+    """With zero hidden weights and biases c >= 0 every residual block adds
+    relu(c) = c to its input, so A_l = A_1 + (l - 1) c in the interior and
+    the output layer sees A_5 = A_1 + 4c."""
+    p = no.init_params(9, out_gain=1.0)
+    layers = no.unpack(p)
+    for l in range(1, 5):
+        layers[l][0][:] = 0.0
+        layers[l][1][:] = c
+    flat = np.concatenate([np.concatenate([w.ravel(), b]) for w, b in layers])
+    h, hu, hv = (a.numpy() for a in ics.random_state(8, 6, seed=3))
+    u = np.stack([h, hu, hv])[None]
+    acts, delta = no.forward(flat, u, OFF, SCALE, bf16_mode=False)
+    a1 = acts[1][:, 1:-1, 1:-1]
+    for l in range(2, 6):
+        np.testing.assert_allclose(acts[l][:, 1:-1, 1:-1], a1 + (l - 1) * c, rtol=0, atol=1e-14)
+        assert not np.any(acts[l][:, 0]) and not np.any(acts[l][:, :, -1])      # zero padding stays zero
+    w6, b6 = layers[5]
+    want = no.conv3x3(no.pad(a1 + 4 * c), w6, b6)
+    np.testing.assert_allclose(delta, want, rtol=1e-13, atol=1e-13)
+
+
 def test_param_count():
     assert no.nparams() == 38755
