@@ -159,6 +159,10 @@ typedef struct {
 sw_status sw_set_tuning(sw_ctx *ctx, const sw_tuning *tuning);
 /* The tuning sw_step will use, with defaults resolved. */
 sw_status sw_get_tuning(const sw_ctx *ctx, sw_tuning *out);
+/* 1 (default): sw_step replays one hipGraph per (nsteps, current buffer,
+ * state planes, launch shape), captured on the first such call (kept up to 8
+ * per context); 0: eager launches.  Results are identical either way. */
+sw_status sw_set_graph(sw_ctx *ctx, int32_t enable);
 
 /* Pick the fastest launch shape for this context by timing candidates on the
  * stream with the caller's state (steps_per_trial >= 1 steps each), then set

@@ -6,8 +6,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/sw.h"
 #include "sw_internal.h"
@@ -20,6 +22,17 @@ struct sw_ctx {
     int device;
     sw_tuning tuning;   // as set by the caller (zero = default)
     SwScalars *sc;      // device
+    // sw_step as one graph launch: captured once per (nsteps, cur, planes,
+    // launch shape) on a private stream, replayed on the caller's
+    bool use_graph = true;
+    hipStream_t cap = nullptr;
+    struct Graph {
+        int nsteps, cur;
+        const void *planes[2][3];
+        SwTuning tun;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
 };
 
 namespace {
@@ -119,6 +132,25 @@ sw_status use_device(const sw_ctx *ctx) {
     return SW_OK;
 }
 
+// reset + prologue + nsteps step launches on stream s (no host sync)
+sw_status enqueue_steps(sw_ctx *ctx, const sw_state *state, int nsteps, const SwTuning &tun, hipStream_t s) {
+    SW_HIP(sw_launch_reset(ctx->sc, 0, s));
+    SW_HIP(sw_launch_prologue(launch_of(ctx, state, state->cur), s));
+    int cur = state->cur;
+    for (int n = 0; n < nsteps; ++n) {
+        SwLaunch b = launch_of(ctx, state, cur);
+        b.step = n;
+        SW_HIP(sw_launch_step(b, tun, s));
+        cur ^= 1;
+    }
+    return SW_OK;
+}
+
+void drop_graphs(sw_ctx *ctx) {
+    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+    ctx->graphs.clear();
+}
+
 }  // namespace
 
 sw_status sw_ctx_describe(const sw_ctx *ctx, sw_grid *grid, sw_opts *opts, sw_layout *layout, void **scalars,
@@ -215,8 +247,10 @@ sw_status sw_create(sw_grid grid, sw_halo halo, double g, double dx, const sw_op
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipMalloc((void **)&c->sc, sizeof(SwScalars));
     if (e == hipSuccess) e = hipMemset(c->sc, 0, sizeof(SwScalars));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
         if (c->sc) (void)hipFree(c->sc);
+        if (c->cap) (void)hipStreamDestroy(c->cap);
         delete c;
         return fail(e == hipErrorOutOfMemory ? SW_ENOMEM : SW_EHIP, "create: %s", hipGetErrorString(e));
     }
@@ -226,10 +260,10 @@ sw_status sw_create(sw_grid grid, sw_halo halo, double g, double dx, const sw_op
 
 sw_status sw_destroy(sw_ctx *ctx) {
     if (!ctx) return SW_OK;
-    if (ctx->sc) {
-        (void)use_device(ctx);
-        (void)hipFree(ctx->sc);
-    }
+    (void)use_device(ctx);
+    drop_graphs(ctx);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+    if (ctx->sc) (void)hipFree(ctx->sc);
     delete ctx;
     return SW_OK;
 }
@@ -313,17 +347,41 @@ sw_status sw_step(sw_ctx *ctx, sw_state *state, int32_t nsteps, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     SwTuning tun;
     if ((st = resolve_tuning(ctx, ctx->tuning, &tun)) != SW_OK) return st;
-    SW_HIP(sw_launch_reset(ctx->sc, 0, s));
-    SwLaunch a = launch_of(ctx, state, state->cur);
-    SW_HIP(sw_launch_prologue(a, s));
-    int cur = state->cur;
-    for (int n = 0; n < nsteps; ++n) {
-        SwLaunch b = launch_of(ctx, state, cur);
-        b.step = n;
-        SW_HIP(sw_launch_step(b, tun, s));
-        cur ^= 1;
+    if (!ctx->use_graph) {
+        if ((st = enqueue_steps(ctx, state, nsteps, tun, s)) != SW_OK) return st;
+    } else {
+        hipGraphExec_t exec = nullptr;
+        for (auto &gr : ctx->graphs)
+            if (gr.nsteps == nsteps && gr.cur == state->cur && std::memcmp(gr.planes, state->plane, sizeof gr.planes) == 0 &&
+                std::memcmp(&gr.tun, &tun, sizeof tun) == 0)
+                exec = gr.exec;
+        if (!exec) {
+            if (ctx->graphs.size() >= 8) drop_graphs(ctx);
+            SW_HIP(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+            st = enqueue_steps(ctx, state, nsteps, tun, ctx->cap);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(ctx->cap, &graph);
+            if (st != SW_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            if (e != hipSuccess) return fail(SW_EHIP, "step: capture: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return fail(SW_EHIP, "step: instantiate: %s", hipGetErrorString(e));
+            sw_ctx::Graph gr{nsteps, state->cur, {}, tun, exec};
+            std::memcpy(gr.planes, state->plane, sizeof gr.planes);
+            ctx->graphs.push_back(gr);
+        }
+        SW_HIP(hipGraphLaunch(exec, s));
     }
-    state->cur = cur;
+    state->cur ^= (nsteps & 1);
+    return SW_OK;
+}
+
+sw_status sw_set_graph(sw_ctx *ctx, int32_t enable) {
+    if (!ctx) return fail(SW_EINVAL, "set_graph: NULL context");
+    ctx->use_graph = enable != 0;
     return SW_OK;
 }
 
@@ -350,3 +408,5 @@ sw_status sw_reset_time(sw_ctx *ctx, void *stream) {
 }
 
 }  // extern "C"
+
+bool sw_ctx_use_graph(const sw_ctx *ctx) { return ctx && ctx->use_graph; }

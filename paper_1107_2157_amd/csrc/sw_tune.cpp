@@ -69,6 +69,8 @@ void cache_store(const char *path, const std::string &key, const sw_tuning &t, d
 sw_status sw_ctx_describe(const sw_ctx *ctx, sw_grid *grid, sw_opts *opts, sw_layout *layout, void **scalars,
                           size_t *scalars_bytes);
 
+bool sw_ctx_use_graph(const sw_ctx *ctx);
+
 extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per_trial, const char *cache_path,
                                  void *stream, sw_tuning *best_out) {
     sw_grid grid;
@@ -136,6 +138,9 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
 
     sw_tuning prev{};
     sw_get_tuning(ctx, &prev);
+    // trials launch eagerly: a first graph call of a shape would time its capture
+    const bool graph = sw_ctx_use_graph(ctx);
+    sw_set_graph(ctx, 0);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     double best_us = 1e300;
     hipError_t he = hipEventCreate(&e0);
@@ -169,6 +174,7 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
     if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(backup);
     (void)hipFree(scal_backup);
+    sw_set_graph(ctx, graph ? 1 : 0);
     if (he != hipSuccess) {
         sw_set_tuning(ctx, &prev);
         return SW_EHIP;

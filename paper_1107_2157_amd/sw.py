@@ -95,6 +95,7 @@ SIGNATURES = {
     "sw_reset_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "sw_set_variant": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "sw_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
+    "sw_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "sw_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "sw_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(State), ctypes.c_int32, ctypes.c_char_p,
                                    ctypes.c_void_p, ctypes.POINTER(Tuning)]),
@@ -262,6 +263,10 @@ class Solver:
         check(lib().sw_sync_status(self.ctx, _stream_handle(stream), ctypes.byref(t), ctypes.byref(dt),
                                    ctypes.byref(n)), "sw_sync_status")
         return t.value, dt.value, n.value
+
+    def set_graph(self, enable: bool):
+        """Replay sw_step calls as hipGraphs (default) or launch eagerly."""
+        check(lib().sw_set_graph(self.ctx, 1 if enable else 0), "sw_set_graph")
 
     def reset_time(self, stream=None):
         check(lib().sw_reset_time(self.ctx, _stream_handle(stream)), "sw_reset_time")

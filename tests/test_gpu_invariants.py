@@ -161,3 +161,30 @@ def test_restart_and_checkpoint_are_bitwise(variant, dtype):
     for x, y in zip(a.get_state(), c2.get_state()):
         assert torch.equal(x, y)
     assert abs((t1 + t2) - ta) <= 1e-12 * ta
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_graph_replays_equal_eager_launches(variant, dtype):
+    """sw_step replayed as hipGraphs equals eager launches bitwise, call after
+    call: odd call lengths alternate the current buffer, so two graphs are
+    each replayed several times, with eager torch work and host reads of the
+    state and time between the replays."""
+    announce(f"graph replays {dtype} v{variant}")
+    st = ics.random_state(192, 130, seed=12)
+    kw = dict(dtype=dtype, bc_x=sw.REFLECT, bc_y=sw.PERIODIC, variant=variant)
+    runs = []
+    for graph in (False, True):
+        s = sw.Solver(192, 130, **kw)
+        s.set_graph(graph)
+        s.set_state(*st)
+        out = []
+        for k in range(6):
+            s.step(7)
+            h, hu, hv = s.get_state(halo=True)
+            torch.randn(4096, device="cuda").cumsum(0).sum().item()   # unrelated eager work and a sync
+            out.append((h.numpy().tobytes(), hu.numpy().tobytes(), hv.numpy().tobytes(), s.sync_status()))
+        runs.append(out)
+    for k, (e, g) in enumerate(zip(*runs)):
+        assert e[:3] == g[:3], f"call {k}"
+        assert e[3] == g[3], f"call {k}: time / step counters"

@@ -91,5 +91,21 @@ def test_residual_blocks_add_relu_of_bias(c):
     np.testing.assert_allclose(delta, want, rtol=1e-13, atol=1e-13)
 
 
+def test_loss_of_the_zero_network_is_the_mean_squared_target():
+    """With every parameter zero the prediction is zero, so the loss is the
+    mean over pixels and the three channels of ((u8 - u) / out_scale)^2 and
+    its bias gradient of the output layer is -2 * mean target per channel."""
+    rng = np.random.default_rng(6)
+    h, hu, hv = (a.numpy() for a in ics.random_state(9, 5, seed=6))
+    u = np.stack([h, hu, hv])[None]
+    u8 = u + 0.02 * rng.standard_normal(u.shape)
+    out_scale = (0.01, 0.03, 0.05)
+    loss, g = no.loss_and_grad(np.zeros(no.nparams()), u, u8, OFF, SCALE, out_scale, bf16_mode=False)
+    t = [(u8[0, c].astype(np.float32) - u[0, c].astype(np.float32)) / np.float32(out_scale[c]) for c in range(3)]
+    want = sum(float(np.sum(np.square(tc, dtype=np.float64))) for tc in t) / (3 * 9 * 5)
+    assert abs(loss - want) <= 1e-12 * want
+    np.testing.assert_allclose(g[-3:], [-2.0 * float(np.mean(tc, dtype=np.float64)) / 3 for tc in t], rtol=1e-12)
+
+
 def test_param_count():
     assert no.nparams() == 38755
