@@ -306,8 +306,8 @@ sw_status sw_surrogate_train_step(sw_net *net, const float *u, const float *u8, 
  * per-grid time and step counters count only the solver steps taken (a
  * network jump has no time step).  Judge mode (gate->judge): l2 (device
  * double[n], may be NULL) receives each grid's relative L2(h) against the
- * plain solver; a grid above gate->l2_tol takes the solver's state, time and
- * step count, and its fallbacks entry is set to nsteps / jump.  The first
+ * plain solver; a grid above gate->l2_tol takes the solver's state, time,
+ * step count and unstable flag, and its fallbacks entry is set to nsteps / jump.  The first
  * judged call on a batch allocates the solver's copy (about the batch's arena
  * size), kept until the network is destroyed or judges another batch.
  * No host sync. */

@@ -100,7 +100,8 @@ hipError_t sw_sur_zero_stats(SwGateStats *st, int B, hipStream_t s);
 // Judge: per grid, relative L2(h) of the rollout (batch grids `a`) against
 // the plain solver's run (`ref`), both on their current buffer `cur`; grids
 // above l2_tol take the solver's state (halos included), their fallback count
-// becomes jumps, and their time / step counters become start + the solver's.
+// becomes jumps, their time / step counters become start + the solver's, and
+// their unstable flag the solver's.
 struct SwJudge {
     double d2, r2;     // sum (h - h_ref)^2, sum h_ref^2
     double t0;         // time at the start of the advance

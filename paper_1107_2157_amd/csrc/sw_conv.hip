@@ -17,6 +17,8 @@
 // m % 4.
 #include "sw_conv.h"
 
+#include <algorithm>
+
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -25,113 +27,188 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int CIN> constexpr int ksteps() { return CIN == 32 ? 9 : 3; }
 
-// One wave: NPB blocks of 16 pixels of one image row, all COUT channels.
-template <int CIN, int COUT, int MODE, int NPB>
-__global__ __launch_bounds__(256) void k_conv3x3(SwConvArgs a) {
+constexpr int kTileRows = 4;                // output rows per tile = waves per block
+constexpr int kTileCols = 64;               // output pixels per tile row (4 MFMA N blocks)
+constexpr int kStageCols = kTileCols + 2;   // staged pixels per row (halo)
+
+// Persistent, LDS-staged 3x3 convolution.  Each block owns a contiguous run
+// of 4-row x 64-pixel output tiles (contiguous, so neighbouring tiles share
+// halo rows in the same XCD's L2) and keeps the layer's weights (the MFMA A
+// operands of every K step) in registers for its whole life.  A tile's input
+// rows (6 x 66 pixels x CIN channels, halo included) are staged in LDS, double
+// buffered: the global loads of tile t + 1 are in flight while the MFMAs of
+// tile t read LDS.  Wave w computes output row w of the tile: per K step one
+// 16-byte LDS read per 16-pixel block gives the B operand (16 pixels x 64 B
+// contiguous per wave: conflict free).
+template <int CIN, int COUT, int MODE>
+__global__ __launch_bounds__(256) void k_conv3x3(SwConvArgs a, int tiles_y, int tiles_x, int ntiles) {
     constexpr int MB = (COUT + 15) / 16;
     constexpr int KS = ksteps<CIN>();
     constexpr int KP = KS * 32;
-    const int lane = threadIdx.x & 63;
-    const int wave = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
-    const int segs = a.W / (16 * NPB);
-    const int total = a.B * a.H * segs;
-    if (wave >= total) return;
-    const int b = wave / (a.H * segs);
-    const int rem = wave - b * a.H * segs;
-    const int y = rem / segs;
-    const int x0 = (rem - y * segs) * 16 * NPB;
-    const int Wp = a.W + 2;
-    const __bf16 *X = (const __bf16 *)a.x + ((int64_t)b * (a.H + 2) * Wp) * CIN;
-    const __bf16 *Wk = (const __bf16 *)a.w;
+    constexpr int NPB = kTileCols / 16;
+    constexpr int STAGE = (kTileRows + 2) * kStageCols * CIN;     // bf16 per buffer
+    constexpr int CHUNKS = STAGE / 8;                             // 16-byte chunks per tile
+    constexpr int PER = (CHUNKS + 255) / 256;                     // per thread
+    __shared__ __attribute__((aligned(16))) __bf16 tile[2][STAGE];
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane >> 4, n = lane & 15;
+    const int Wp = a.W + 2;
+    const int per_block = (ntiles + gridDim.x - 1) / gridDim.x;
+    const int t0 = blockIdx.x * per_block;
+    const int t1 = min(ntiles, t0 + per_block);
+    if (t0 >= t1) return;                                          // uniform per block: no barrier is skipped by part of it
 
-    f32x4 acc[MB][NPB];
+    // weights: A operand of K step ks, M block mb (row mb*16 + n, k = ks*32 + 8g .. + 7)
+    bf16x8 wa[KS][MB];
+    const __bf16 *Wk = (const __bf16 *)a.w;
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-        for (int pb = 0; pb < NPB; ++pb) acc[mb][pb] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        const int tap = CIN == 32 ? ks : 4 * ks + g;
-        const int ci0 = CIN == 32 ? 8 * g : 0;
-        const bool live = tap < 9;
-        const int dy = live ? tap / 3 : 1, dx = live ? tap % 3 : 1;   // offsets into the halo'd image
-        bf16x8 wa[MB];
+    for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
-            wa[mb] = *reinterpret_cast<const bf16x8 *>(Wk + (int64_t)(mb * 16 + n) * KP + ks * 32 + 8 * g);
-#pragma unroll
-        for (int pb = 0; pb < NPB; ++pb) {
-            const int px = x0 + pb * 16 + n;
-            bf16x8 xb = *reinterpret_cast<const bf16x8 *>(X + ((int64_t)(y + dy) * Wp + px + dx) * CIN + ci0);
-            if (!live) xb = bf16x8{};
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-                acc[mb][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[mb], xb, acc[mb][pb], 0, 0, 0);
-        }
-    }
+            wa[ks][mb] = *reinterpret_cast<const bf16x8 *>(Wk + (int64_t)(mb * 16 + n) * KP + ks * 32 + 8 * g);
 
-    // epilogue: lane holds channels co = mb*16 + 4g .. +3 of pixel x0 + pb*16 + n
+    const __bf16 *X = (const __bf16 *)a.x;
+    bf16x8 stg[PER];
+    auto load_tile = [&](int t) {
+        const int b = t / (tiles_y * tiles_x);
+        const int r = t - b * tiles_y * tiles_x;
+        const int ty = r / tiles_x, tx = r - ty * tiles_x;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int c = threadIdx.x + k * 256;
+            const int row = c / (kStageCols * CIN / 8), rem = c - row * (kStageCols * CIN / 8);
+            const int yy = ty * kTileRows + row;                   // halo row of the input
+            stg[k] = bf16x8{};
+            if (c < CHUNKS && yy < a.H + 2)
+                stg[k] = *reinterpret_cast<const bf16x8 *>(
+                    X + (((int64_t)b * (a.H + 2) + yy) * Wp + tx * kTileCols) * CIN + rem * 8);
+        }
+    };
+    auto store_tile = [&](int buf) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int c = threadIdx.x + k * 256;
+            if (c < CHUNKS) *reinterpret_cast<bf16x8 *>(&tile[buf][c * 8]) = stg[k];
+        }
+    };
+
+    load_tile(t0);
+    store_tile(0);
+    __syncthreads();
     const int Wq = sw_planar_pitch(a.W);
+    for (int t = t0; t < t1; ++t) {
+        const int buf = (t - t0) & 1;
+        if (t + 1 < t1) load_tile(t + 1);                         // in flight during the MFMAs below
+        const int b = t / (tiles_y * tiles_x);
+        const int r = t - b * tiles_y * tiles_x;
+        const int ty = r / tiles_x, tx = r - ty * tiles_x;
+        const int y = ty * kTileRows + w;                          // output row of this wave
+        const int x0 = tx * kTileCols;
+        const __bf16 *T = tile[buf];
+
+        f32x4 acc[MB][NPB];
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-        const int co0 = mb * 16 + 4 * g;
-        if (co0 >= COUT && MODE != SW_CONV_F32) continue;
+        for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int pb = 0; pb < NPB; ++pb) {
-            const int px = x0 + pb * 16 + n;
-            f32x4 v = acc[mb][pb];
-            if (MODE == SW_CONV_F32) {   // channels 0..3 (COUT <= 4) with bias, FP32, no halo
-                if (g != 0) continue;
-                float *Y = a.yf + (((int64_t)b * a.H + y) * a.W + px) * 4;
+            for (int pb = 0; pb < NPB; ++pb) acc[mb][pb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = r < COUT ? v[r] + a.bias[r] : 0.f;
-                *reinterpret_cast<f32x4 *>(Y) = v;
-                continue;
-            }
-            const int64_t at = (((int64_t)b * (a.H + 2) + y + 1) * Wp + px + 1) * COUT + co0;   // NHWC, halo'd
-            bf16x4 o, o2;
-            if (MODE == SW_CONV_RELU_BF16 || MODE == SW_CONV_RESID_BF16) {
+        for (int ks = 0; ks < KS; ++ks) {
+            const int tap = CIN == 32 ? ks : 4 * ks + g;
+            const int ci0 = CIN == 32 ? 8 * g : 0;
+            const bool live = tap < 9;
+            const int dy = live ? tap / 3 : 1, dx = live ? tap % 3 : 1;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r] + a.bias[co0 + r], 0.f);
-                if (MODE == SW_CONV_RESID_BF16) {   // CIN == COUT: the block's input at this pixel
-                    const bf16x4 xin = *reinterpret_cast<const bf16x4 *>((const __bf16 *)a.x + at);
-                    o2 = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+            for (int pb = 0; pb < NPB; ++pb) {
+                bf16x8 xb = *reinterpret_cast<const bf16x8 *>(T + ((w + dy) * kStageCols + pb * 16 + n + dx) * CIN + ci0);
+                if (!live) xb = bf16x8{};
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) v[r] += (float)xin[r];
-                    if (a.y2) *reinterpret_cast<bf16x4 *>((__bf16 *)a.y2 + at) = o2;
-                }
-                o = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
-                *reinterpret_cast<bf16x4 *>((__bf16 *)a.y + at) = o;
-            } else {   // SW_CONV_DGRAD
-                if (a.add) {
-                    const bf16x4 ad = *reinterpret_cast<const bf16x4 *>((const __bf16 *)a.add + at);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) v[r] += (float)ad[r];
-                }
-                o2 = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
-                if (a.y) *reinterpret_cast<bf16x4 *>((__bf16 *)a.y + at) = o2;
-                const bf16x4 mk = *reinterpret_cast<const bf16x4 *>((const __bf16 *)a.mask + at);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) o[r] = (float)mk[r] > 0.f ? o2[r] : (__bf16)0.f;
-                *reinterpret_cast<bf16x4 *>((__bf16 *)a.y2 + at) = o;
-            }
-            if (a.yp) {   // planar copy: 16 lanes of a channel write 16 consecutive pixels
-                __bf16 *P = (__bf16 *)a.yp + (((int64_t)b * (a.H + 2) + y + 1) * COUT + co0) * Wq + px + 8;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) P[(int64_t)r * Wq] = o[r];
+                for (int mb = 0; mb < MB; ++mb)
+                    acc[mb][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[ks][mb], xb, acc[mb][pb], 0, 0, 0);
             }
         }
+
+        // epilogue: lane holds channels co = mb*16 + 4g .. +3 of pixel x0 + pb*16 + n
+        if (y < a.H) {
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const int co0 = mb * 16 + 4 * g;
+                if (co0 >= COUT && MODE != SW_CONV_F32) continue;
+#pragma unroll
+                for (int pb = 0; pb < NPB; ++pb) {
+                    const int px = x0 + pb * 16 + n;
+                    f32x4 v = acc[mb][pb];
+                    if (MODE == SW_CONV_F32) {   // channels 0..3 (COUT <= 4) with bias, FP32, no halo
+                        if (g != 0) continue;
+                        float *Y = a.yf + (((int64_t)b * a.H + y) * a.W + px) * 4;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) v[q] = q < COUT ? v[q] + a.bias[q] : 0.f;
+                        *reinterpret_cast<f32x4 *>(Y) = v;
+                        continue;
+                    }
+                    const int64_t at = (((int64_t)b * (a.H + 2) + y + 1) * Wp + px + 1) * COUT + co0;   // NHWC, halo'd
+                    bf16x4 o, o2;
+                    if (MODE == SW_CONV_RELU_BF16 || MODE == SW_CONV_RESID_BF16) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) v[q] = fmaxf(v[q] + a.bias[co0 + q], 0.f);
+                        if (MODE == SW_CONV_RESID_BF16) {   // CIN == COUT: the block's input at this pixel, from LDS
+                            const bf16x4 xin = *reinterpret_cast<const bf16x4 *>(
+                                T + ((w + 1) * kStageCols + pb * 16 + n + 1) * CIN + co0);
+                            o2 = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) v[q] += (float)xin[q];
+                            if (a.y2) *reinterpret_cast<bf16x4 *>((__bf16 *)a.y2 + at) = o2;
+                        }
+                        o = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+                        *reinterpret_cast<bf16x4 *>((__bf16 *)a.y + at) = o;
+                    } else {   // SW_CONV_DGRAD
+                        if (a.add) {
+                            const bf16x4 ad = *reinterpret_cast<const bf16x4 *>((const __bf16 *)a.add + at);
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) v[q] += (float)ad[q];
+                        }
+                        o2 = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+                        if (a.y) *reinterpret_cast<bf16x4 *>((__bf16 *)a.y + at) = o2;
+                        const bf16x4 mk = *reinterpret_cast<const bf16x4 *>((const __bf16 *)a.mask + at);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) o[q] = (float)mk[q] > 0.f ? o2[q] : (__bf16)0.f;
+                        *reinterpret_cast<bf16x4 *>((__bf16 *)a.y2 + at) = o;
+                    }
+                    if (a.yp) {   // planar copy: 16 lanes of a channel write 16 consecutive pixels
+                        __bf16 *P = (__bf16 *)a.yp + (((int64_t)b * (a.H + 2) + y + 1) * COUT + co0) * Wq + px + 8;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) P[(int64_t)q * Wq] = o[q];
+                    }
+                }
+            }
+        }
+        if (t + 1 < t1) store_tile(buf ^ 1);                      // buffer buf ^ 1 was last read before the previous barrier
+        __syncthreads();
     }
+}
+
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipDeviceProp_t p;
+        cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) ? p.multiProcessorCount : 256;
+    }
+    return cus;
 }
 
 template <int CIN, int COUT, int MODE>
 hipError_t launch(const SwConvArgs &a, hipStream_t s) {
-    constexpr int NPB = 4;
-    if (a.W % (16 * NPB) != 0) return hipErrorInvalidValue;
-    const int64_t waves = (int64_t)a.B * a.H * (a.W / (16 * NPB));
-    k_conv3x3<CIN, COUT, MODE, NPB><<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(a);
+    if (a.W % kTileCols != 0) return hipErrorInvalidValue;
+    const int tiles_y = (a.H + kTileRows - 1) / kTileRows, tiles_x = a.W / kTileCols;
+    const int64_t ntiles = (int64_t)a.B * tiles_y * tiles_x;
+    if (ntiles > (int64_t)1 << 30) return hipErrorInvalidValue;
+    static int resident = 0;   // blocks of this instance that fit on one CU at once
+    if (!resident && (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_conv3x3<CIN, COUT, MODE>, 256, 0) !=
+                          hipSuccess || resident < 1))
+        resident = 1;
+    const int64_t blocks = std::min<int64_t>(ntiles, (int64_t)device_cus() * resident);
+    k_conv3x3<CIN, COUT, MODE><<<(unsigned)blocks, 256, 0, s>>>(a, tiles_y, tiles_x, (int)ntiles);
     return hipGetLastError();
 }
 

@@ -407,7 +407,7 @@ __global__ void k_judge_decide(SwJudge *j, int B, SwBatchScalars *sc, const SwBa
         sc[b].t = j[b].t0 + rsc[b].t;
         sc[b].last_dt = rsc[b].last_dt;
         sc[b].steps = j[b].steps0 + rsc[b].steps;
-        sc[b].unstable |= rsc[b].unstable;
+        sc[b].unstable = rsc[b].unstable;   // the rollout's history is discarded
     }
 }
 

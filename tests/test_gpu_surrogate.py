@@ -29,8 +29,9 @@ def make_net(H, W, B, params, out_scale):
     return net
 
 
-def test_forward_matches_oracle():
-    B, H, W = 2, 48, 64
+@pytest.mark.parametrize("B,H,W", [(2, 48, 64), (3, 22, 128)])
+def test_forward_matches_oracle(B, H, W):
+    """H = 22 leaves a partial tile of output rows."""
     p = no.init_params(11, out_gain=1.0)
     out_scale = (0.05, 0.05, 0.05)
     u = states(B, H, W, 21)
@@ -120,8 +121,10 @@ def test_forced_fallback_equals_solver(fault):
 
 def test_judge_rejects_to_the_solver():
     """Judge mode with a bound no rollout meets: every grid ends with the plain
-    solver's state (bitwise), step count and a full fallback count; the
-    reported L2 is the rollout's error before the replacement."""
+    solver's state (bitwise), step count, unstable flag (clear, although the
+    untrained network's states may have tripped a fallback step) and a full
+    fallback count; the reported L2 is the rollout's error before the
+    replacement."""
     n, H, W, nsteps = 3, 64, 64, 24
     u0 = states(n, H, W, 51)
     net = sw.Surrogate(H, W, n, jump=8, seed=4)
