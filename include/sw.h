@@ -273,8 +273,8 @@ typedef struct sw_net sw_net;
 
 /* Network for H x W grids (W a multiple of 64), up to max_batch grids per
  * call; allocates its weights and activation / gradient workspace (about
- * 21 * 32 * 2 * max_batch * (H + 2) * (W + 16) bytes, e.g. 12 GB for 256
- * grids of 256 x 256).
+ * 14 * 64 * max_batch * (H + 2) * (W + 2) bytes, e.g. 15 GB for 256 grids of
+ * 256 x 256).
  * Errors: SW_EINVAL, SW_ENOTSUP (other depth / width), SW_ENOMEM, SW_EHIP. */
 sw_status sw_surrogate_create(const sw_net_cfg *cfg, int32_t H, int32_t W, int32_t max_batch, sw_net **out);
 sw_status sw_surrogate_destroy(sw_net *net);

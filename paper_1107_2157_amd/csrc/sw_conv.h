@@ -7,28 +7,18 @@
 
 enum { SW_CONV_RELU_BF16 = 0, SW_CONV_RESID_BF16 = 1, SW_CONV_F32 = 2, SW_CONV_DGRAD = 3 };
 
-// Channel-planar copy of a BF16 tensor for the weight gradient:
-// P[b][yy][c][xx], yy in [0, H + 2) (halo rows), xx = x + 8 for x in [-1, W]
-// (one halo column each side, 16-byte aligned interior), row pitch W + 16.
-__host__ __device__ inline int sw_planar_pitch(int W) { return W + 16; }
-__host__ __device__ inline int64_t sw_planar_elems(int B, int H, int W, int C) {
-    return (int64_t)B * (H + 2) * C * sw_planar_pitch(W);
-}
-
 // One 3x3 convolution launch (see sw_conv.hip for layouts).  Modes:
 //   RELU:  y = relu(conv(x) + b)                                (first layer)
 //   RESID: y = x + relu(conv(x) + b), y2 = relu(conv(x) + b)     (residual blocks)
 //   F32:   yf = conv(x) + b in FP32                              (output layer)
 //   DGRAD: G = conv(x) + add, y = G, y2 = G where mask > 0       (input gradient)
-// Every BF16 output may be null except y in RELU / RESID and y2 in DGRAD;
-// yp receives the planar copy of y (RELU / RESID) or of y2 (DGRAD) if set.
+// Every BF16 output may be null except y in RELU / RESID and y2 in DGRAD.
 struct SwConvArgs {
     const void *x;       // BF16 NHWC input with halo, CIN channels
     const void *w;       // BF16 [COUT padded to 16][K padded to 32] implicit-GEMM weights
     const float *bias;   // FP32 [COUT] (RELU, RESID and F32 modes)
     void *y;             // BF16 NHWC output with halo, COUT channels
     void *y2;            // BF16 NHWC output with halo, COUT channels (RESID: relu part, DGRAD: masked)
-    void *yp;            // BF16 planar copy (see above), COUT channels
     float *yf;           // FP32 [B][H][W][4] output (F32 mode)
     const void *add;     // BF16 NHWC with halo, COUT channels, added before rounding (DGRAD)
     const void *mask;    // BF16 NHWC with halo, COUT channels: y2 kept where mask > 0 (DGRAD)
@@ -42,24 +32,24 @@ struct SwNorm {
 };
 
 // Dense FP32 frames [B][3][H][W] -> network input X0 (BF16 NHWC, 8 channels,
-// halo = reflective / periodic ghost values), its planar copy x0p if set, and,
-// if u8 != nullptr, the target (u8 - u) / out_scale as FP32 [B][H][W][4].
+// halo = reflective / periodic ghost values) and, if u8 != nullptr, the
+// target (u8 - u) / out_scale as FP32 [B][H][W][4].
 hipError_t sw_sur_prep_dense(const float *u, const float *u8, int B, int H, int W, int bc_x, int bc_y, SwNorm nrm,
-                             void *x0, void *x0p, float *target, hipStream_t s);
+                             void *x0, float *target, hipStream_t s);
 // Batch planes (current buffer, halo filled) of grids [0, B) -> X0.
 hipError_t sw_sur_prep_planes(const SwBatchGrid *grids, int cur, int B, int H, int W, SwNorm nrm, void *x0,
                               hipStream_t s);
 // MSE loss over the three channels: per-block partial sums into partial[nblocks],
-// and dZ = 2 (pred - target) / (3 B H W) as BF16 NHWC with halo, 8 channels,
-// plus its planar copy dzp.
+// and dZ = 2 (pred - target) / (3 B H W) as BF16 NHWC with halo, 8 channels.
 hipError_t sw_sur_loss(const float *pred, const float *target, int B, int H, int W, float *partial, int nblocks,
-                       void *dz, void *dzp, hipStream_t s);
+                       void *dz, hipStream_t s);
 hipError_t sw_sur_reduce_sum(const float *partial, int n, float *out, hipStream_t s);
-// Weight gradient of one layer from planar tensors (MFMA, K = pixels):
-// dW[co][tap][ci] = sum_p dZ[p][co] A[p + tap][ci], db[co] = sum_p dZ[p][co],
-// written into grad (logical layout, W then b).  dzp has coutp (8 or 32)
-// channels, ap cinp (8 or 32); partial holds nblocks * (cout * 9 * cin + cout) floats.
-hipError_t sw_sur_wgrad(const void *dzp, int coutp, int cout, const void *ap, int cinp, int cin, int B, int H, int W,
+// Weight gradient of one layer (MFMA, K = pixels) from the NHWC tensors with
+// halo: dW[co][tap][ci] = sum_p dZ[p][co] A[p + tap][ci], db[co] = sum_p dZ[p][co],
+// written into grad (logical layout, W then b).  dz has coutp (8 or 32)
+// channels, a cinp (8 or 32); W a multiple of 64; partial holds
+// nblocks * (cout * 9 * cin + cout) floats (at most nblocks blocks are used).
+hipError_t sw_sur_wgrad(const void *dz, int coutp, int cout, const void *a, int cinp, int cin, int B, int H, int W,
                         float *partial, int nblocks, float *grad_w, float *grad_b, hipStream_t s);
 // Adam on the FP32 master parameters and refresh of the BF16 forward /
 // input-gradient weight layouts.

@@ -96,7 +96,6 @@ __global__ __launch_bounds__(256) void k_conv3x3(SwConvArgs a, int tiles_y, int 
     load_tile(t0);
     store_tile(0);
     __syncthreads();
-    const int Wq = sw_planar_pitch(a.W);
     for (int t = t0; t < t1; ++t) {
         const int buf = (t - t0) & 1;
         if (t + 1 < t1) load_tile(t + 1);                         // in flight during the MFMAs below
@@ -173,11 +172,6 @@ __global__ __launch_bounds__(256) void k_conv3x3(SwConvArgs a, int tiles_y, int 
 #pragma unroll
                         for (int q = 0; q < 4; ++q) o[q] = (float)mk[q] > 0.f ? o2[q] : (__bf16)0.f;
                         *reinterpret_cast<bf16x4 *>((__bf16 *)a.y2 + at) = o;
-                    }
-                    if (a.yp) {   // planar copy: 16 lanes of a channel write 16 consecutive pixels
-                        __bf16 *P = (__bf16 *)a.yp + (((int64_t)b * (a.H + 2) + y + 1) * COUT + co0) * Wq + px + 8;
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) P[(int64_t)q * Wq] = o[q];
                     }
                 }
             }

@@ -39,10 +39,8 @@ struct sw_net {
     float *wpartial = nullptr;
     SwLayerDesc L[kLayers]{};
     SwLayerDesc *L_dev = nullptr;
-    // NHWC BF16 tensors with halo; *p are the channel-planar copies the weight
-    // gradient reads; relu[k] = relu(Z) of residual block k + 1 (its mask)
+    // NHWC BF16 tensors with halo; relu[k] = relu(Z) of residual block k + 1 (its mask)
     void *x0 = nullptr, *act[kLayers - 1] = {}, *relu[kLayers - 2] = {}, *g[2] = {}, *dz[2] = {}, *dz6 = nullptr;
-    void *x0p = nullptr, *actp[kLayers - 1] = {}, *dzp[2] = {}, *dz6p = nullptr;
     float *delta = nullptr, *target = nullptr;
     SwGateStats *stats = nullptr;
     int32_t *active = nullptr;
@@ -76,8 +74,6 @@ sw_status use_dev(const sw_net *n) {
     return SW_OK;
 }
 
-size_t planar_bytes(const sw_net *n, int B, int ch) { return (size_t)sw_planar_elems(B, n->H, n->W, ch) * 2; }
-
 bool residual(int l) { return l >= 1 && l <= kLayers - 2; }
 
 SwConvArgs conv_args(const sw_net *n, int B, const void *x) {
@@ -89,7 +85,7 @@ SwConvArgs conv_args(const sw_net *n, int B, const void *x) {
     return a;
 }
 
-// X0 -> act[0..4] -> delta; with train, also the ReLU parts and planar copies
+// X0 -> act[0..4] -> delta; with train, also the ReLU parts (backward masks)
 sw_status forward(const sw_net *n, int B, bool train, hipStream_t s) {
     for (int l = 0; l < kLayers; ++l) {
         const SwLayerDesc &L = n->L[l];
@@ -102,7 +98,6 @@ sw_status forward(const sw_net *n, int B, bool train, hipStream_t s) {
             mode = SW_CONV_F32;
         } else {
             a.y = n->act[l];
-            if (train) a.yp = n->actp[l];
             if (residual(l)) {
                 mode = SW_CONV_RESID_BF16;
                 if (train) a.y2 = n->relu[l - 1];
@@ -117,13 +112,13 @@ sw_status forward(const sw_net *n, int B, bool train, hipStream_t s) {
 // dZ of layer l gives dW_l, db_l, and G = dL/d(input of l) = conv^T(dZ) (+ G
 // of l's output where l is residual), then dZ_{l-1} = G * (Z_{l-1} > 0)
 sw_status backward(sw_net *n, int B, float *loss_out, hipStream_t s) {
-    SHIP(sw_sur_loss(n->delta, n->target, B, n->H, n->W, n->loss_partial, kLossBlocks, n->dz6, n->dz6p, s));
+    SHIP(sw_sur_loss(n->delta, n->target, B, n->H, n->W, n->loss_partial, kLossBlocks, n->dz6, s));
     if (loss_out) SHIP(sw_sur_reduce_sum(n->loss_partial, kLossBlocks, loss_out, s));
-    const void *dz = n->dz6, *dzp = n->dz6p, *gout = nullptr;
+    const void *dz = n->dz6, *gout = nullptr;
     int dzc = 8;
     for (int l = kLayers - 1; l >= 0; --l) {
         const SwLayerDesc &L = n->L[l];
-        SHIP(sw_sur_wgrad(dzp, dzc, L.cout, l == 0 ? n->x0p : n->actp[l - 1], L.cinp, L.cin, B, n->H, n->W,
+        SHIP(sw_sur_wgrad(dz, dzc, L.cout, l == 0 ? n->x0 : n->act[l - 1], L.cinp, L.cin, B, n->H, n->W,
                           n->wpartial, kWgradBlocks, n->grad + L.w_off, n->grad + L.b_off, s));
         if (l == 0) break;
         SwConvArgs a = conv_args(n, B, dz);
@@ -132,11 +127,9 @@ sw_status backward(sw_net *n, int B, float *loss_out, hipStream_t s) {
         a.mask = l == 1 ? n->act[0] : n->relu[l - 2];
         a.y = residual(l - 1) ? n->g[l & 1] : nullptr;
         a.y2 = n->dz[l & 1];
-        a.yp = n->dzp[l & 1];
         SHIP(sw_conv3x3(a, L.cdp, L.cin, SW_CONV_DGRAD, s));
         gout = a.y;
         dz = a.y2;
-        dzp = a.yp;
         dzc = 32;
     }
     return SW_OK;
@@ -214,19 +207,13 @@ sw_status sw_surrogate_create(const sw_net_cfg *cfg, int32_t H, int32_t W, int32
     if (st == SW_OK) st = dalloc(n, (void **)&n->wpartial, (size_t)kWgradBlocks * (32 * 9 * 32 + 32) * 4);
     if (st == SW_OK) st = dalloc(n, (void **)&n->L_dev, sizeof(n->L));
     if (st == SW_OK) st = dalloc(n, &n->x0, act_bytes(n, max_batch, 8));
-    if (st == SW_OK) st = dalloc(n, &n->x0p, planar_bytes(n, max_batch, 8));
-    for (int l = 0; l < kLayers - 1 && st == SW_OK; ++l) {
-        st = dalloc(n, &n->act[l], act_bytes(n, max_batch, 32));
-        if (st == SW_OK) st = dalloc(n, &n->actp[l], planar_bytes(n, max_batch, 32));
-    }
+    for (int l = 0; l < kLayers - 1 && st == SW_OK; ++l) st = dalloc(n, &n->act[l], act_bytes(n, max_batch, 32));
     for (int k = 0; k < kLayers - 2 && st == SW_OK; ++k) st = dalloc(n, &n->relu[k], act_bytes(n, max_batch, 32));
     for (int k = 0; k < 2 && st == SW_OK; ++k) {
         st = dalloc(n, &n->g[k], act_bytes(n, max_batch, 32));
         if (st == SW_OK) st = dalloc(n, &n->dz[k], act_bytes(n, max_batch, 32));
-        if (st == SW_OK) st = dalloc(n, &n->dzp[k], planar_bytes(n, max_batch, 32));
     }
     if (st == SW_OK) st = dalloc(n, &n->dz6, act_bytes(n, max_batch, 8));
-    if (st == SW_OK) st = dalloc(n, &n->dz6p, planar_bytes(n, max_batch, 8));
     if (st == SW_OK) st = dalloc(n, (void **)&n->delta, (size_t)max_batch * H * W * 16);
     if (st == SW_OK) st = dalloc(n, (void **)&n->target, (size_t)max_batch * H * W * 16);
     if (st == SW_OK) st = dalloc(n, (void **)&n->stats, (size_t)max_batch * sizeof(SwGateStats));
@@ -303,7 +290,7 @@ sw_status sw_surrogate_forward(sw_net *n, const float *u, int32_t B, float *delt
     if (st != SW_OK) return st;
     if (!u) return sw_fail(SW_EINVAL, "surrogate_forward: NULL input");
     hipStream_t s = (hipStream_t)stream;
-    SHIP(sw_sur_prep_dense(u, nullptr, B, n->H, n->W, n->cfg.bc_x, n->cfg.bc_y, n->nrm, n->x0, nullptr, nullptr, s));
+    SHIP(sw_sur_prep_dense(u, nullptr, B, n->H, n->W, n->cfg.bc_x, n->cfg.bc_y, n->nrm, n->x0, nullptr, s));
     if ((st = forward(n, B, false, s)) != SW_OK) return st;
     if (delta) SHIP(hipMemcpyAsync(delta, n->delta, (size_t)B * n->H * n->W * 16, hipMemcpyDeviceToDevice, s));
     return SW_OK;
@@ -327,7 +314,7 @@ sw_status sw_surrogate_grad(sw_net *n, const float *u, const float *u8, int32_t 
     if (st != SW_OK) return st;
     if (!u || !u8) return sw_fail(SW_EINVAL, "surrogate_grad: NULL input");
     hipStream_t s = (hipStream_t)stream;
-    SHIP(sw_sur_prep_dense(u, u8, B, n->H, n->W, n->cfg.bc_x, n->cfg.bc_y, n->nrm, n->x0, n->x0p, n->target, s));
+    SHIP(sw_sur_prep_dense(u, u8, B, n->H, n->W, n->cfg.bc_x, n->cfg.bc_y, n->nrm, n->x0, n->target, s));
     if ((st = forward(n, B, true, s)) != SW_OK) return st;
     if ((st = backward(n, B, loss, s)) != SW_OK) return st;
     if (grad) SHIP(hipMemcpyAsync(grad, n->grad, n->nparams * 4, hipMemcpyDeviceToDevice, s));

@@ -1,6 +1,8 @@
 // Learned-surrogate kernels other than the convolution: input preparation,
 // loss and its gradient seed, weight gradients, Adam with the BF16 weight
 // re-layout, and the gated rollout (apply, gate statistics, accept).
+#include <algorithm>
+
 #include "sw_common.h"
 #include "sw_conv.h"
 
@@ -46,7 +48,7 @@ __device__ __forceinline__ void store_x0(__bf16 *x0, float a, float b, float c) 
 }
 
 __global__ __launch_bounds__(256) void k_prep_dense(const float *u, const float *u8, int B, int H, int W, int bcx,
-                                                    int bcy, SwNorm nrm, __bf16 *x0, __bf16 *x0p, float *target) {
+                                                    int bcy, SwNorm nrm, __bf16 *x0, float *target) {
     const int Wp = W + 2, Hp = H + 2;
     const int64_t n = (int64_t)B * Hp * Wp;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
@@ -61,12 +63,6 @@ __global__ __launch_bounds__(256) void k_prep_dense(const float *u, const float 
         const float c0 = (h - nrm.in_off[0]) / nrm.in_scale[0], c1 = (hu - nrm.in_off[1]) / nrm.in_scale[1],
                     c2 = (hv - nrm.in_off[2]) / nrm.in_scale[2];
         store_x0(x0 + idx * 8, c0, c1, c2);
-        if (x0p) {   // planar: channel rows of pitch W + 16, halo column xx at xx + 7
-            __bf16 *P = x0p + ((int64_t)b * Hp + yy) * 8 * sw_planar_pitch(W) + xx + 7;
-            P[0] = (__bf16)c0;
-            P[sw_planar_pitch(W)] = (__bf16)c1;
-            P[2 * sw_planar_pitch(W)] = (__bf16)c2;
-        }
         if (target && xx >= 1 && xx <= W && yy >= 1 && yy <= H) {
             const float *vb = u8 + (int64_t)b * 3 * plane + (int64_t)y * W + x;
             float *tg = target + (((int64_t)b * H + y) * W + x) * 4;
@@ -97,7 +93,7 @@ __global__ __launch_bounds__(256) void k_prep_planes(const SwBatchGrid *grids, i
 }
 
 __global__ __launch_bounds__(256) void k_loss(const float *pred, const float *target, int B, int H, int W,
-                                              float *partial, __bf16 *dz, __bf16 *dzp) {
+                                              float *partial, __bf16 *dz) {
     const int64_t n = (int64_t)B * H * W;
     const float scale = 2.f / (3.f * (float)n);
     float acc = 0.f;
@@ -111,10 +107,6 @@ __global__ __launch_bounds__(256) void k_loss(const float *pred, const float *ta
         const int y = r / W, x = r - y * W;
         const float g0 = scale * d0, g1 = scale * d1, g2 = scale * d2;
         store_x0(dz + (((int64_t)b * (H + 2) + y + 1) * (W + 2) + x + 1) * 8, g0, g1, g2);
-        __bf16 *P = dzp + ((int64_t)b * (H + 2) + y + 1) * 8 * sw_planar_pitch(W) + x + 8;
-        P[0] = (__bf16)g0;
-        P[sw_planar_pitch(W)] = (__bf16)g1;
-        P[2 * sw_planar_pitch(W)] = (__bf16)g2;
     }
     __shared__ float red[4];
     acc = wave_sum_f(acc);
@@ -135,35 +127,49 @@ __global__ void k_reduce_sum(const float *partial, int n, float *out) {
 
 // Weight gradient partials on MFMA (v_mfma_f32_16x16x32_bf16), K = pixels:
 //     dW[co][(tap, ci)] = sum_p dZ[p][co] A[p + off(tap)][ci]
-// from the channel-planar tensors, where 8 consecutive pixels of one channel
-// are one aligned 16-byte load.  A K step is a 32-pixel chunk of one row:
-// lane (n, kg) = (lane % 16, lane / 16) takes pixels x + 8 kg .. + 7.  The
-// dZ operand (rows co) is loaded as is; the activation operand of tap (dy, dx)
-// is the row y + dy - 1 shifted by dx - 1 pixels, built from three aligned
-// loads with 16-bit funnel shifts.  Wave w owns input row dy = w / CH and,
-// for CINP = 32, channel half w % CH, i.e. the three taps (dy, 0..2) of 16
-// input channels (3 N tiles); for CINP = 8 a 16-wide N tile holds two taps of
-// 8 channels (2 N tiles).  Wave 0 also forms db with an all-ones operand.
-// Each block sums a contiguous range of chunks and writes its partial dW, db.
+// read from the NHWC tensors.  Persistent blocks walk contiguous runs of
+// 4-row x 64-pixel tiles and keep dW in registers.  A tile's dZ (4 x 64
+// pixels) and input rows (6 x 66 pixels, halo included) are staged in LDS
+// transposed, channel-major with the pixels contiguous, so 8 consecutive
+// pixels of one channel are one 16-byte LDS read (row strides padded so the
+// reads of 16 channels are conflict free); the next tile's global loads are
+// in flight during the MFMAs.  A K step is 32 pixels of one row: lane
+// (n, kg) = (lane % 16, lane / 16) takes pixels j0 = 8 kg .. + 7 of the step.
+// Wave w owns input row dy = w / CH and, for CINP = 32, channel half w % CH,
+// i.e. the taps (dy, 0..2) of 16 input channels: two aligned reads give all
+// three column shifts (dx = 1 by a 16-bit funnel shift, dx = 2 by a dword
+// shift).  For CINP = 8 a 16-wide N tile holds two taps of 8 channels.  Wave
+// 0 also forms db with an all-ones operand.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
+constexpr int kWgRows = 4, kWgCols = 64;
+
 template <int CINP, int COUTP>
-__global__ __launch_bounds__(384) void k_wgrad_mfma(const __bf16 *dzp, const __bf16 *ap, int cout, int cin, int B,
-                                                    int H, int W, float *partial, int nent) {
+__global__ __launch_bounds__(CINP == 32 ? 384 : 192) void k_wgrad(const __bf16 *dz, const __bf16 *a, int cout, int cin,
+                                                                  int H, int W, int tiles_y, int tiles_x, int ntiles,
+                                                                  float *partial, int nent) {
     constexpr int CH = CINP == 32 ? 2 : 1;
+    constexpr int NTH = 64 * 3 * CH;
     constexpr int MB = (COUTP + 15) / 16;
     constexpr int NT = CINP == 32 ? 3 : 2;
+    constexpr int DZS = kWgRows * kWgCols + 8;               // per output channel (padded)
+    constexpr int AROW = 72, AS = (kWgRows + 2) * AROW + 8;  // per input channel (padded)
+    constexpr int NKO = COUTP / 8, NKI = CINP / 8;
+    constexpr int DZ_CH = kWgRows * NKO * kWgCols, A_CH = (kWgRows + 2) * NKI * (kWgCols + 2);
+    constexpr int DZ_PER = (DZ_CH + NTH - 1) / NTH, A_PER = (A_CH + NTH - 1) / NTH;
+    __shared__ __attribute__((aligned(16))) __bf16 dzT[COUTP * DZS];
+    __shared__ __attribute__((aligned(16))) __bf16 aT[CINP * AS];
+
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int n = lane & 15, kg = lane >> 4;
     const int dy = w / CH, chalf = w % CH;
-    const int Wq = sw_planar_pitch(W);
-    const int cpr = W / 32;
-    const int64_t nchunks = (int64_t)B * H * cpr;
-    const int64_t c0 = nchunks * blockIdx.x / gridDim.x, c1 = nchunks * (blockIdx.x + 1) / gridDim.x;
     const int ci = CINP == 32 ? chalf * 16 + n : (n & 7);
+    const int Wp = W + 2;
+    const int per_block = (ntiles + gridDim.x - 1) / gridDim.x;
+    const int t0 = blockIdx.x * per_block, t1 = min(ntiles, t0 + per_block);
     const u32x4 ones = {0x3F803F80u, 0x3F803F80u, 0x3F803F80u, 0x3F803F80u};   // bf16 1.0 pairs
 
     f32x4 acc[MB][NT], accb[MB];
@@ -173,42 +179,94 @@ __global__ __launch_bounds__(384) void k_wgrad_mfma(const __bf16 *dzp, const __b
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[mb][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    for (int64_t c = c0; c < c1; ++c) {
-        const int b = (int)(c / ((int64_t)H * cpr));
-        const int rem = (int)(c - (int64_t)b * H * cpr);
-        const int y = rem / cpr;
-        const int x = (rem - y * cpr) * 32 + 8 * kg;
-        bf16x8 aop[MB];
+
+    bf16x8 sdz[DZ_PER], sa[A_PER];
+    auto load_tile = [&](int t) {
+        const int b = t / (tiles_y * tiles_x);
+        const int r = t - b * tiles_y * tiles_x;
+        const int ty = r / tiles_x, tx = r - ty * tiles_x;
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            const int co = mb * 16 + n;
-            aop[mb] = co < COUTP ? *reinterpret_cast<const bf16x8 *>(
-                                       dzp + (((int64_t)b * (H + 2) + y + 1) * COUTP + co) * Wq + x + 8)
-                                 : bf16x8{};
-        }
-        const __bf16 *row = ap + (((int64_t)b * (H + 2) + y + dy) * CINP + ci) * Wq + x;
-        const u32x4 pv = *reinterpret_cast<const u32x4 *>(row);
-        const u32x4 cv = *reinterpret_cast<const u32x4 *>(row + 8);
-        const u32x4 nv = *reinterpret_cast<const u32x4 *>(row + 16);
-        // pixel x - 1 + j (dx = 0), x + j (dx = 1), x + 1 + j (dx = 2), j = 0..7
-        const u32x4 s0 = {__builtin_amdgcn_alignbit(cv[0], pv[3], 16), __builtin_amdgcn_alignbit(cv[1], cv[0], 16),
-                          __builtin_amdgcn_alignbit(cv[2], cv[1], 16), __builtin_amdgcn_alignbit(cv[3], cv[2], 16)};
-        const u32x4 s2 = {__builtin_amdgcn_alignbit(cv[1], cv[0], 16), __builtin_amdgcn_alignbit(cv[2], cv[1], 16),
-                          __builtin_amdgcn_alignbit(cv[3], cv[2], 16), __builtin_amdgcn_alignbit(nv[0], cv[3], 16)};
-        bf16x8 bop[NT];
-        if (CINP == 32) {
-            bop[0] = as_bf16x8(s0);
-            bop[1] = as_bf16x8(cv);
-            bop[2] = as_bf16x8(s2);
-        } else {
-            bop[0] = as_bf16x8(n < 8 ? s0 : cv);
-            bop[1] = n < 8 ? as_bf16x8(s2) : bf16x8{};
+        for (int k = 0; k < DZ_PER; ++k) {   // chunk c = (row * NKO + part) * 64 + p
+            const int c = threadIdx.x + k * NTH;
+            const int p = c % kWgCols, rp = c / kWgCols;
+            const int row = rp / NKO, part = rp - row * NKO;
+            const int y = ty * kWgRows + row;
+            sdz[k] = bf16x8{};
+            if (c < DZ_CH && y < H)
+                sdz[k] = *reinterpret_cast<const bf16x8 *>(
+                    dz + (((int64_t)b * (H + 2) + y + 1) * Wp + tx * kWgCols + 1 + p) * COUTP + part * 8);
         }
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
+        for (int k = 0; k < A_PER; ++k) {    // chunk c = (row * NKI + part) * 66 + p, halo coordinates
+            const int c = threadIdx.x + k * NTH;
+            const int p = c % (kWgCols + 2), rp = c / (kWgCols + 2);
+            const int row = rp / NKI, part = rp - row * NKI;
+            const int yy = ty * kWgRows + row;
+            sa[k] = bf16x8{};
+            if (c < A_CH && yy < H + 2)
+                sa[k] = *reinterpret_cast<const bf16x8 *>(
+                    a + (((int64_t)b * (H + 2) + yy) * Wp + tx * kWgCols + p) * CINP + part * 8);
+        }
+    };
+    auto store_tile = [&]() {   // transposing writes: lanes of a wave take consecutive pixels
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[mb][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop[mb], bop[t], acc[mb][t], 0, 0, 0);
-            if (w == 0) accb[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop[mb], as_bf16x8(ones), accb[mb], 0, 0, 0);
+        for (int k = 0; k < DZ_PER; ++k) {
+            const int c = threadIdx.x + k * NTH;
+            if (c >= DZ_CH) continue;
+            const int p = c % kWgCols, rp = c / kWgCols;
+            const int row = rp / NKO, part = rp - row * NKO;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) dzT[(part * 8 + e) * DZS + row * kWgCols + p] = sdz[k][e];
+        }
+#pragma unroll
+        for (int k = 0; k < A_PER; ++k) {
+            const int c = threadIdx.x + k * NTH;
+            if (c >= A_CH) continue;
+            const int p = c % (kWgCols + 2), rp = c / (kWgCols + 2);
+            const int row = rp / NKI, part = rp - row * NKI;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) aT[(part * 8 + e) * AS + row * AROW + p] = sa[k][e];
+        }
+    };
+
+    if (t0 < t1) load_tile(t0);
+    for (int t = t0; t < t1; ++t) {
+        __syncthreads();                  // the previous tile's reads of LDS are done
+        store_tile();
+        __syncthreads();
+        if (t + 1 < t1) load_tile(t + 1); // in flight during the MFMAs below
+#pragma unroll
+        for (int kc = 0; kc < 2 * kWgRows; ++kc) {
+            const int r = kc >> 1, j0 = (kc & 1) * 32 + 8 * kg;
+            bf16x8 aop[MB];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const int co = mb * 16 + n;
+                aop[mb] = co < COUTP ? *reinterpret_cast<const bf16x8 *>(&dzT[co * DZS + r * kWgCols + j0]) : bf16x8{};
+            }
+            const __bf16 *row = &aT[ci * AS + (r + dy) * AROW + j0];
+            const u32x4 v0 = *reinterpret_cast<const u32x4 *>(row);
+            const u32x4 v1 = *reinterpret_cast<const u32x4 *>(row + 8);
+            // staged pixel j0 + dx + e is input pixel x0 + j0 + e + dx - 1: dx = 0, 1, 2
+            const u32x4 s1 = {__builtin_amdgcn_alignbit(v0[1], v0[0], 16), __builtin_amdgcn_alignbit(v0[2], v0[1], 16),
+                              __builtin_amdgcn_alignbit(v0[3], v0[2], 16), __builtin_amdgcn_alignbit(v1[0], v0[3], 16)};
+            const u32x4 s2 = {v0[1], v0[2], v0[3], v1[0]};
+            bf16x8 bop[NT];
+            if (CINP == 32) {
+                bop[0] = as_bf16x8(v0);
+                bop[1] = as_bf16x8(s1);
+                bop[2] = as_bf16x8(s2);
+            } else {
+                bop[0] = as_bf16x8(n < 8 ? v0 : s1);
+                bop[1] = n < 8 ? as_bf16x8(s2) : bf16x8{};
+            }
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+                for (int tt = 0; tt < NT; ++tt)
+                    acc[mb][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop[mb], bop[tt], acc[mb][tt], 0, 0, 0);
+                if (w == 0) accb[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop[mb], as_bf16x8(ones), accb[mb], 0, 0, 0);
+            }
         }
     }
     // D[m][n] in lane n + 16 (m / 4), element m % 4
@@ -216,33 +274,49 @@ __global__ __launch_bounds__(384) void k_wgrad_mfma(const __bf16 *dzp, const __b
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int co = mb * 16 + 4 * kg + r;
+        for (int q = 0; q < 4; ++q) {
+            const int co = mb * 16 + 4 * kg + q;
             if (co >= cout) continue;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
+            for (int tt = 0; tt < NT; ++tt) {
                 int tap, cc;
                 if (CINP == 32) {
-                    tap = 3 * dy + t;
+                    tap = 3 * dy + tt;
                     cc = ci;
                 } else {
-                    tap = 3 * dy + (t == 0 ? (n >> 3) : 2);
+                    tap = 3 * dy + (tt == 0 ? (n >> 3) : 2);
                     cc = n & 7;
-                    if (t == 1 && n >= 8) continue;
+                    if (tt == 1 && n >= 8) continue;
                 }
-                if (cc < cin) P[(co * 9 + tap) * cin + cc] = acc[mb][t][r];
+                if (cc < cin) P[(co * 9 + tap) * cin + cc] = acc[mb][tt][q];
             }
-            if (w == 0 && n == 0) P[cout * 9 * cin + co] = accb[mb][r];
+            if (w == 0 && n == 0) P[cout * 9 * cin + co] = accb[mb][q];
         }
 }
 
-__global__ void k_wgrad_reduce(const float *partial, int nblocks, int nent, int nw, float *grad_w, float *grad_b) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nent) return;
+// Sum of the block partials per entry: 64 entries per block, four partial
+// sums per entry over interleaved blocks, combined in LDS (FP64).
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float *partial, int nblocks, int nent, int nw, float *grad_w,
+                                                      float *grad_b) {
+    const int e = blockIdx.x * 64 + (threadIdx.x & 63), part = threadIdx.x >> 6;
     double acc = 0.0;
-    for (int k = 0; k < nblocks; ++k) acc += partial[(int64_t)k * nent + e];
-    if (e < nw) grad_w[e] = (float)acc;
-    else grad_b[e - nw] = (float)acc;
+    if (e < nent) {
+        int k = part;
+        for (; k + 12 < nblocks; k += 16) {
+            const float a0 = partial[(int64_t)k * nent + e], a1 = partial[(int64_t)(k + 4) * nent + e];
+            const float a2 = partial[(int64_t)(k + 8) * nent + e], a3 = partial[(int64_t)(k + 12) * nent + e];
+            acc += ((double)a0 + (double)a1) + ((double)a2 + (double)a3);
+        }
+        for (; k < nblocks; k += 4) acc += partial[(int64_t)k * nent + e];
+    }
+    __shared__ double red[4][64];
+    red[part][threadIdx.x & 63] = acc;
+    __syncthreads();
+    if (part == 0 && e < nent) {
+        const double sum = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+        if (e < nw) grad_w[e] = (float)sum;
+        else grad_b[e - nw] = (float)sum;
+    }
 }
 
 __global__ void k_adam(float *master, float *m, float *v, const float *grad, int64_t n, SwAdam ad) {
@@ -435,9 +509,9 @@ unsigned grid_for(int64_t n, int cap = 16384) {
 }  // namespace
 
 hipError_t sw_sur_prep_dense(const float *u, const float *u8, int B, int H, int W, int bc_x, int bc_y, SwNorm nrm,
-                             void *x0, void *x0p, float *target, hipStream_t s) {
-    k_prep_dense<<<grid_for((int64_t)B * (H + 2) * (W + 2)), 256, 0, s>>>(
-        u, u8, B, H, W, bc_x, bc_y, nrm, (__bf16 *)x0, (__bf16 *)x0p, u8 ? target : nullptr);
+                             void *x0, float *target, hipStream_t s) {
+    k_prep_dense<<<grid_for((int64_t)B * (H + 2) * (W + 2)), 256, 0, s>>>(u, u8, B, H, W, bc_x, bc_y, nrm,
+                                                                           (__bf16 *)x0, u8 ? target : nullptr);
     return hipGetLastError();
 }
 
@@ -448,8 +522,8 @@ hipError_t sw_sur_prep_planes(const SwBatchGrid *grids, int cur, int B, int H, i
 }
 
 hipError_t sw_sur_loss(const float *pred, const float *target, int B, int H, int W, float *partial, int nblocks,
-                       void *dz, void *dzp, hipStream_t s) {
-    k_loss<<<nblocks, 256, 0, s>>>(pred, target, B, H, W, partial, (__bf16 *)dz, (__bf16 *)dzp);
+                       void *dz, hipStream_t s) {
+    k_loss<<<nblocks, 256, 0, s>>>(pred, target, B, H, W, partial, (__bf16 *)dz);
     return hipGetLastError();
 }
 
@@ -458,24 +532,46 @@ hipError_t sw_sur_reduce_sum(const float *partial, int n, float *out, hipStream_
     return hipGetLastError();
 }
 
-hipError_t sw_sur_wgrad(const void *dzp, int coutp, int cout, const void *ap, int cinp, int cin, int B, int H, int W,
+template <int CINP, int COUTP>
+hipError_t launch_wgrad(const __bf16 *dz, const __bf16 *a, int cout, int cin, int B, int H, int W, float *partial,
+                        int maxblocks, int nent, int *used, hipStream_t s) {
+    constexpr int threads = CINP == 32 ? 384 : 192;
+    static int resident = 0;
+    if (!resident && (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_wgrad<CINP, COUTP>, threads, 0) !=
+                          hipSuccess || resident < 1))
+        resident = 1;
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipDeviceProp_t p;
+        cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) ? p.multiProcessorCount : 256;
+    }
+    const int tiles_y = (H + kWgRows - 1) / kWgRows, tiles_x = W / kWgCols;
+    const int64_t ntiles = (int64_t)B * tiles_y * tiles_x;
+    if (ntiles > (int64_t)1 << 30) return hipErrorInvalidValue;
+    const int nb = (int)std::min<int64_t>({ntiles, (int64_t)cus * resident, (int64_t)maxblocks});
+    k_wgrad<CINP, COUTP><<<nb, threads, 0, s>>>(dz, a, cout, cin, H, W, tiles_y, tiles_x, (int)ntiles, partial, nent);
+    *used = nb;
+    return hipGetLastError();
+}
+
+hipError_t sw_sur_wgrad(const void *dzv, int coutp, int cout, const void *av, int cinp, int cin, int B, int H, int W,
                         float *partial, int nblocks, float *grad_w, float *grad_b, hipStream_t s) {
-    if (W % 32 != 0 || nblocks < 1 || cout > coutp || cin > cinp) return hipErrorInvalidValue;
+    if (W % kWgCols != 0 || nblocks < 1 || cout > coutp || cin > cinp) return hipErrorInvalidValue;
     const int nent = cout * 9 * cin + cout;
-    const int64_t nchunks = (int64_t)B * H * (W / 32);
-    if (nchunks < nblocks) nblocks = (int)nchunks;
-    const __bf16 *dz = (const __bf16 *)dzp, *a = (const __bf16 *)ap;
+    const __bf16 *dz = (const __bf16 *)dzv, *a = (const __bf16 *)av;
+    int used = 0;
+    hipError_t e;
     if (cinp == 32 && coutp == 32)
-        k_wgrad_mfma<32, 32><<<nblocks, 384, 0, s>>>(dz, a, cout, cin, B, H, W, partial, nent);
+        e = launch_wgrad<32, 32>(dz, a, cout, cin, B, H, W, partial, nblocks, nent, &used, s);
     else if (cinp == 8 && coutp == 32)
-        k_wgrad_mfma<8, 32><<<nblocks, 192, 0, s>>>(dz, a, cout, cin, B, H, W, partial, nent);
+        e = launch_wgrad<8, 32>(dz, a, cout, cin, B, H, W, partial, nblocks, nent, &used, s);
     else if (cinp == 32 && coutp == 8)
-        k_wgrad_mfma<32, 8><<<nblocks, 384, 0, s>>>(dz, a, cout, cin, B, H, W, partial, nent);
+        e = launch_wgrad<32, 8>(dz, a, cout, cin, B, H, W, partial, nblocks, nent, &used, s);
     else
         return hipErrorInvalidValue;
-    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_wgrad_reduce<<<(nent + 255) / 256, 256, 0, s>>>(partial, nblocks, nent, cout * 9 * cin, grad_w, grad_b);
+    k_wgrad_reduce<<<(nent + 63) / 64, 256, 0, s>>>(partial, used, nent, cout * 9 * cin, grad_w, grad_b);
     return hipGetLastError();
 }
 
