@@ -77,6 +77,7 @@ def timed(torch, fn):
 def run_workload(name, steps, warmup, sw, ics, torch, tune_cache, fixed=None):
     n, dtype, bc, seed, _, desc = WORKLOADS[name]
     s = make_solver(name, sw, ics, torch)
+    ic = tuple(s.interior(k).clone() for k in range(3))
     if fixed:
         s.set_tuning(*fixed)
         tuning = s.get_tuning()
@@ -84,20 +85,25 @@ def run_workload(name, steps, warmup, sw, ics, torch, tune_cache, fixed=None):
         tuning = s.autotune(steps_per_trial=3 if n >= 8192 else 10, cache_path=tune_cache)
     if warmup > 0:
         s.step(warmup)
+
+    def restart():                                   # the initial state in buffer 0, time zero
+        s.state.cur = 0
+        s.set_state(*ic)
+        s.reset_time()
+
     # untimed calibration call: with the timed call it separates the per-call
-    # prologue (halo fill + first CFL reduction) from the per-step kernel time
+    # prologue (halo fill + first CFL reduction) from the per-step kernel time.
+    # Both calls start from the initial state; their graphs (keyed by steps
+    # and current buffer) are captured beforehand, outside the timed calls.
     k_cal = max(1, steps // 4)
-    # capture the graphs of both call shapes (keyed by steps and current
-    # buffer) outside the timed calls, then return to the same buffer parity
-    cur0 = s.state.cur
-    s.step(k_cal)
-    s.step(steps)
-    if s.state.cur != cur0:
-        s.step(1)
+    for k in (k_cal, steps):
+        restart()
+        s.step(k)
+    restart()
     t_cal = timed(torch, lambda: s.step(k_cal))
-    s.reset_time()
+    restart()
     torch.cuda.synchronize()
-    t = timed(torch, lambda: s.step(steps))          # the timed region: exactly `steps` steps
+    t = timed(torch, lambda: s.step(steps))          # the timed region: exactly `steps` steps from the initial state
     finite = True
     try:
         s.sync_status()
