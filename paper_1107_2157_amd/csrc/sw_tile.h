@@ -40,54 +40,67 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *base, unsigned bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kRsrcWord3);
 }
 
+// Cache policy bits of the step's row loads and stores (buffer instruction
+// aux field: 1 = sc0, 2 = nt, 16 = sc1).  Stores are non-temporal: the new
+// state is not read again before the whole grid has been written, and
+// streaming it past the caches was measured 5-16 % faster on every workload.
+// Loads keep the default policy, so the halo rows that neighbouring tiles
+// share stay in L2 (non-temporal loads were measured 15-20 % slower).
+#ifndef SW_LOAD_POLICY
+#define SW_LOAD_POLICY 0
+#endif
+#ifndef SW_STORE_POLICY
+#define SW_STORE_POLICY 2
+#endif
+
 template <typename T, int VEC> __device__ __forceinline__ void bload(rsrc_t r, unsigned vo, unsigned so, T o[VEC]);
 template <> __device__ __forceinline__ void bload<float, 1>(rsrc_t r, unsigned vo, unsigned so, float o[1]) {
-    o[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    o[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, SW_LOAD_POLICY));
 }
 template <> __device__ __forceinline__ void bload<float, 2>(rsrc_t r, unsigned vo, unsigned so, float o[2]) {
-    u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+    u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, SW_LOAD_POLICY);
     o[0] = __uint_as_float(v.x); o[1] = __uint_as_float(v.y);
 }
 template <> __device__ __forceinline__ void bload<float, 4>(rsrc_t r, unsigned vo, unsigned so, float o[4]) {
-    u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+    u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, SW_LOAD_POLICY);
     o[0] = __uint_as_float(v.x); o[1] = __uint_as_float(v.y); o[2] = __uint_as_float(v.z); o[3] = __uint_as_float(v.w);
 }
 template <> __device__ __forceinline__ void bload<double, 1>(rsrc_t r, unsigned vo, unsigned so, double o[1]) {
-    u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+    u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, SW_LOAD_POLICY);
     o[0] = __hiloint2double((int)v.y, (int)v.x);
 }
 template <> __device__ __forceinline__ void bload<double, 2>(rsrc_t r, unsigned vo, unsigned so, double o[2]) {
-    u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+    u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, SW_LOAD_POLICY);
     o[0] = __hiloint2double((int)v.y, (int)v.x); o[1] = __hiloint2double((int)v.w, (int)v.z);
 }
 __device__ __forceinline__ float bload1(rsrc_t r, unsigned vo, unsigned so, float) {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, SW_LOAD_POLICY));
 }
 __device__ __forceinline__ double bload1(rsrc_t r, unsigned vo, unsigned so, double) {
-    u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+    u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, SW_LOAD_POLICY);
     return __hiloint2double((int)v.y, (int)v.x);
 }
 
 template <typename T, int VEC> __device__ __forceinline__ void bstore(rsrc_t r, unsigned vo, unsigned so, const T o[VEC]);
 template <> __device__ __forceinline__ void bstore<float, 1>(rsrc_t r, unsigned vo, unsigned so, const float o[1]) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(o[0]), r, vo, so, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(o[0]), r, vo, so, SW_STORE_POLICY);
 }
 template <> __device__ __forceinline__ void bstore<float, 2>(rsrc_t r, unsigned vo, unsigned so, const float o[2]) {
     u32x2 v = {__float_as_uint(o[0]), __float_as_uint(o[1])};
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, so, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, so, SW_STORE_POLICY);
 }
 template <> __device__ __forceinline__ void bstore<float, 4>(rsrc_t r, unsigned vo, unsigned so, const float o[4]) {
     u32x4 v = {__float_as_uint(o[0]), __float_as_uint(o[1]), __float_as_uint(o[2]), __float_as_uint(o[3])};
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, vo, so, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, vo, so, SW_STORE_POLICY);
 }
 template <> __device__ __forceinline__ void bstore<double, 1>(rsrc_t r, unsigned vo, unsigned so, const double o[1]) {
     u32x2 v = {(unsigned)__double2loint(o[0]), (unsigned)__double2hiint(o[0])};
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, so, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, so, SW_STORE_POLICY);
 }
 template <> __device__ __forceinline__ void bstore<double, 2>(rsrc_t r, unsigned vo, unsigned so, const double o[2]) {
     u32x4 v = {(unsigned)__double2loint(o[0]), (unsigned)__double2hiint(o[0]), (unsigned)__double2loint(o[1]),
                (unsigned)__double2hiint(o[1])};
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, vo, so, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, vo, so, SW_STORE_POLICY);
 }
 
 // Cross-lane moves along the wave.  DPP wave_shr:1 / wave_shl:1 (GFX9
