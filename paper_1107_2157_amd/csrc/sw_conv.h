@@ -25,6 +25,8 @@ struct SwConvArgs {
     int B, H, W;
 };
 hipError_t sw_conv3x3(const SwConvArgs &a, int cin, int cout, int mode, hipStream_t s);
+// Compute units of the current device (for persistent grids).
+int sw_device_cus();
 
 // Per-channel affine normalisation of the state: x = (u - offset) / scale.
 struct SwNorm {

@@ -181,15 +181,20 @@ __global__ __launch_bounds__(256) void k_conv3x3(SwConvArgs a, int tiles_y, int 
     }
 }
 
-int device_cus() {
-    static int cus = 0;
-    if (!cus) {
+}  // namespace
+
+// Compute units of the current device (queried once; thread-safe initialisation).
+int sw_device_cus() {
+    static const int cus = [] {
         int dev = 0;
         hipDeviceProp_t p;
-        cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) ? p.multiProcessorCount : 256;
-    }
+        return (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) ? p.multiProcessorCount
+                                                                                                   : 256;
+    }();
     return cus;
 }
+
+namespace {
 
 template <int CIN, int COUT, int MODE>
 hipError_t launch(const SwConvArgs &a, hipStream_t s) {
@@ -197,11 +202,13 @@ hipError_t launch(const SwConvArgs &a, hipStream_t s) {
     const int tiles_y = (a.H + kTileRows - 1) / kTileRows, tiles_x = a.W / kTileCols;
     const int64_t ntiles = (int64_t)a.B * tiles_y * tiles_x;
     if (ntiles > (int64_t)1 << 30) return hipErrorInvalidValue;
-    static int resident = 0;   // blocks of this instance that fit on one CU at once
-    if (!resident && (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_conv3x3<CIN, COUT, MODE>, 256, 0) !=
-                          hipSuccess || resident < 1))
-        resident = 1;
-    const int64_t blocks = std::min<int64_t>(ntiles, (int64_t)device_cus() * resident);
+    static const int resident = [] {   // blocks of this instance that fit on one CU at once
+        int r = 0;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, k_conv3x3<CIN, COUT, MODE>, 256, 0) == hipSuccess && r > 0
+                   ? r
+                   : 1;
+    }();
+    const int64_t blocks = std::min<int64_t>(ntiles, (int64_t)sw_device_cus() * resident);
     k_conv3x3<CIN, COUT, MODE><<<(unsigned)blocks, 256, 0, s>>>(a, tiles_y, tiles_x, (int)ntiles);
     return hipGetLastError();
 }

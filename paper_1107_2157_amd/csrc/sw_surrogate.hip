@@ -536,16 +536,13 @@ template <int CINP, int COUTP>
 hipError_t launch_wgrad(const __bf16 *dz, const __bf16 *a, int cout, int cin, int B, int H, int W, float *partial,
                         int maxblocks, int nent, int *used, hipStream_t s) {
     constexpr int threads = CINP == 32 ? 384 : 192;
-    static int resident = 0;
-    if (!resident && (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_wgrad<CINP, COUTP>, threads, 0) !=
-                          hipSuccess || resident < 1))
-        resident = 1;
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        hipDeviceProp_t p;
-        cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) ? p.multiProcessorCount : 256;
-    }
+    static const int resident = [] {   // blocks of this instance that fit on one CU at once
+        int r = 0;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, k_wgrad<CINP, COUTP>, threads, 0) == hipSuccess && r > 0
+                   ? r
+                   : 1;
+    }();
+    const int cus = sw_device_cus();
     const int tiles_y = (H + kWgRows - 1) / kWgRows, tiles_x = W / kWgCols;
     const int64_t ntiles = (int64_t)B * tiles_y * tiles_x;
     if (ntiles > (int64_t)1 << 30) return hipErrorInvalidValue;

@@ -74,7 +74,54 @@ def test_null_arguments():
     assert L.sw_set_tuning(None, None) == sw.EINVAL
     assert L.sw_get_tuning(None, None) == sw.EINVAL
     assert L.sw_destroy(None) == sw.OK
+    assert L.sw_set_graph(None, 1) == sw.EINVAL
     assert L.sw_strerror(sw.EUNSTABLE).decode().startswith("unstable")
+    # batch and surrogate entry points
+    assert L.sw_batch_destroy(None) == sw.OK
+    assert L.sw_batch_step(None, 1, None) == sw.EINVAL
+    assert L.sw_batch_sync_status(None, None, None, None, None) == sw.EINVAL
+    assert L.sw_batch_export(None, None, None) == sw.EINVAL
+    assert L.sw_surrogate_destroy(None) == sw.OK
+    assert L.sw_surrogate_forward(None, None, 1, None, None) == sw.EINVAL
+    assert L.sw_surrogate_train_step(None, None, None, 1, 1e-3, None, None) == sw.EINVAL
+    gate = sw.Gate(1e-4, 0.0, 1, 0, 1e-2)
+    assert L.sw_surrogate_advance(None, None, 8, ctypes.byref(gate), None, None, None) == sw.EINVAL
+
+
+def batch_create(grids, **kw):
+    o = dict(dtype=sw.F32, bc_x=0, bc_y=0, scheme=0, dy=0.0, cfl=0.5, dt_fixed=0.0)
+    o.update(kw)
+    opts = sw.Opts(o["dtype"], o["bc_x"], o["bc_y"], o["scheme"], o["dy"], o["cfl"], o["dt_fixed"])
+    arr = (sw.Grid * max(len(grids), 1))(*[sw.Grid(nx, ny) for nx, ny in grids])
+    h = ctypes.c_void_p()
+    st = sw.lib().sw_batch_create(len(grids), arr, sw.Halo(1, 1, 1, 1), 9.8, 1.0, ctypes.byref(opts), ctypes.byref(h))
+    return st, sw.lib().sw_last_error_detail().decode()
+
+
+@pytest.mark.parametrize("grids,kw,status", [
+    ([], {}, sw.EINVAL), ([(8, 8), (0, 8)], {}, sw.EINVAL), ([(8, 8)], dict(cfl=0.0), sw.EINVAL),
+    ([(8, 8)], dict(scheme=1), sw.ENOTSUP), ([(8, 8)], dict(bc_y=7), sw.EINVAL),
+])
+def test_batch_create_validates_before_any_hip_call(grids, kw, status):
+    st, detail = batch_create(grids, **kw)
+    assert st == status, detail
+    assert detail
+
+
+@pytest.mark.parametrize("cfg,H,W,B,status", [
+    (dict(layers=5), 64, 64, 1, sw.ENOTSUP), (dict(hidden=16), 64, 64, 1, sw.ENOTSUP),
+    (dict(jump=7), 64, 64, 1, sw.EINVAL), (dict(jump=0), 64, 64, 1, sw.EINVAL),
+    (dict(bc_x=2), 64, 64, 1, sw.EINVAL), ({}, 64, 100, 1, sw.EINVAL), ({}, 0, 64, 1, sw.EINVAL),
+    ({}, 64, 64, 0, sw.EINVAL), ({}, 65536, 65536, 1, sw.EINVAL),
+])
+def test_surrogate_create_validates_before_any_hip_call(cfg, H, W, B, status):
+    c = dict(layers=6, hidden=32, jump=8, bc_x=0, bc_y=0, seed=1)
+    c.update(cfg)
+    net_cfg = sw.NetCfg(c["layers"], c["hidden"], c["jump"], c["bc_x"], c["bc_y"], 0, c["seed"])
+    h = ctypes.c_void_p()
+    st = sw.lib().sw_surrogate_create(ctypes.byref(net_cfg), H, W, B, ctypes.byref(h))
+    assert st == status, sw.lib().sw_last_error_detail().decode()
+    assert not h.value
 
 
 STRUCTS = {"sw_grid": sw.Grid, "sw_halo": sw.Halo, "sw_opts": sw.Opts, "sw_layout": sw.Layout,
