@@ -100,7 +100,8 @@ typedef struct {
 typedef struct sw_ctx sw_ctx;   /* opaque; owns device scalars (dt ring, time, flags) */
 
 /* Layout of a plane for a grid and dtype.  Pure host computation.
- * Errors: SW_EINVAL for nx, ny < 1, nx > 2^30, an unknown dtype or a NULL out. */
+ * Errors: SW_EINVAL for nx, ny < 1, nx > 2^21, ny > 2^30, an unknown dtype or a
+ * NULL out. */
 sw_status sw_layout_query(sw_grid grid, sw_dtype dtype, sw_layout *out);
 
 /* Create a solver context for one grid (problem statement: grid, halo, g, dx).

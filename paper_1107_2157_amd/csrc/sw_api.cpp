@@ -66,7 +66,10 @@ sw_status layout_for(sw_grid grid, sw_dtype dtype, sw_layout *out) {
     if (!out) return fail(SW_EINVAL, "layout: NULL output");
     if (dtype != SW_F32 && dtype != SW_F64) return fail(SW_EINVAL, "layout: unknown dtype %d", (int)dtype);
     if (grid.nx < 1 || grid.ny < 1) return fail(SW_EINVAL, "layout: grid %d x %d is empty", grid.nx, grid.ny);
-    if (grid.nx > (1 << 30) || grid.ny > (1 << 30)) return fail(SW_EINVAL, "layout: grid side above 2^30");
+    // A step kernel addresses one tile (at most 64 rows + 2 halo rows) through
+    // 32-bit buffer offsets: nx <= 2^21 keeps that span below 2 GiB in FP64.
+    if (grid.nx > (1 << 21)) return fail(SW_EINVAL, "layout: nx = %d above 2^21", grid.nx);
+    if (grid.ny > (1 << 30)) return fail(SW_EINVAL, "layout: ny = %d above 2^30", grid.ny);
     const int64_t eb = dtype == SW_F64 ? 8 : 4;
     const int64_t a = kAlignBytes / eb;                       // elements per 256 bytes
     const int64_t lead = a;                                   // interior starts 256 B into each row

@@ -38,7 +38,8 @@ def test_layout_rules():
             assert (L.pitch * eb) % 65536 != 0
 
 
-@pytest.mark.parametrize("nx,ny,dtype", [(0, 5, 0), (5, 0, 0), (-3, 4, 1), (5, 5, 7), (2 ** 30 + 1, 4, 0)])
+@pytest.mark.parametrize("nx,ny,dtype", [(0, 5, 0), (5, 0, 0), (-3, 4, 1), (5, 5, 7), (2 ** 21 + 1, 4, 1),
+                                        (4, 2 ** 30 + 1, 0)])
 def test_layout_rejects(nx, ny, dtype):
     out = sw.Layout()
     assert sw.lib().sw_layout_query(sw.Grid(nx, ny), dtype, ctypes.byref(out)) == sw.EINVAL
