@@ -50,6 +50,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(SwConvArgs a, int tiles_y, int 
     constexpr int CHUNKS = STAGE / 8;                             // 16-byte chunks per tile
     constexpr int PER = (CHUNKS + 255) / 256;                     // per thread
     __shared__ __attribute__((aligned(16))) __bf16 tile[2][STAGE];
+    __shared__ __attribute__((aligned(16))) __bf16 ostage[kTileRows][kTileCols * (COUT > 16 ? COUT : 16)];
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane >> 4, n = lane & 15;
@@ -129,50 +130,95 @@ __global__ __launch_bounds__(256) void k_conv3x3(SwConvArgs a, int tiles_y, int 
 
         // epilogue: lane holds channels co = mb*16 + 4g .. +3 of pixel x0 + pb*16 + n
         if (y < a.H) {
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                const int co0 = mb * 16 + 4 * g;
-                if (co0 >= COUT && MODE != SW_CONV_F32) continue;
+            if (MODE == SW_CONV_F32) {   // channels 0..3 (COUT <= 4) with bias, FP32, no halo
 #pragma unroll
                 for (int pb = 0; pb < NPB; ++pb) {
-                    const int px = x0 + pb * 16 + n;
+                    if (g != 0) continue;
+                    f32x4 v = acc[0][pb];
+                    float *Y = a.yf + (((int64_t)b * a.H + y) * a.W + x0 + pb * 16 + n) * 4;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) v[q] = q < COUT ? v[q] + a.bias[q] : 0.f;
+                    *reinterpret_cast<f32x4 *>(Y) = v;
+                }
+            } else {
+                // The wave's 64 output pixels x COUT channels are one contiguous run of the
+                // NHWC row: values go to the wave's LDS area, then out as 16 contiguous bytes
+                // per lane.  Two outputs (RESID's ReLU part, DGRAD's dZ) reuse the area in turn.
+                const int64_t row0 = (((int64_t)b * (a.H + 2) + y + 1) * Wp + x0 + 1) * COUT;
+                auto slot = [&](int mb, int pb) -> bf16x4 & {
+                    return *reinterpret_cast<bf16x4 *>(&ostage[w][(pb * 16 + n) * COUT + mb * 16 + 4 * g]);
+                };
+                auto wave_sync = [] {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                };
+                auto flush = [&](__bf16 *dst) {
+                    wave_sync();
+#pragma unroll
+                    for (int k = 0; k < kTileCols * COUT / 512; ++k)
+                        *reinterpret_cast<bf16x8 *>(dst + row0 + k * 512 + lane * 8) =
+                            *reinterpret_cast<const bf16x8 *>(&ostage[w][k * 512 + lane * 8]);
+                    wave_sync();   // the copy's reads are done before the area is written again
+                };
+                auto relu_part = [&](int mb, int pb) {
                     f32x4 v = acc[mb][pb];
-                    if (MODE == SW_CONV_F32) {   // channels 0..3 (COUT <= 4) with bias, FP32, no halo
-                        if (g != 0) continue;
-                        float *Y = a.yf + (((int64_t)b * a.H + y) * a.W + px) * 4;
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) v[q] = q < COUT ? v[q] + a.bias[q] : 0.f;
-                        *reinterpret_cast<f32x4 *>(Y) = v;
-                        continue;
-                    }
-                    const int64_t at = (((int64_t)b * (a.H + 2) + y + 1) * Wp + px + 1) * COUT + co0;   // NHWC, halo'd
-                    bf16x4 o, o2;
-                    if (MODE == SW_CONV_RELU_BF16 || MODE == SW_CONV_RESID_BF16) {
+                    for (int q = 0; q < 4; ++q) v[q] = fmaxf(v[q] + a.bias[mb * 16 + 4 * g + q], 0.f);
+                    return v;
+                };
+                if (MODE == SW_CONV_RELU_BF16 || MODE == SW_CONV_RESID_BF16) {
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) v[q] = fmaxf(v[q] + a.bias[co0 + q], 0.f);
-                        if (MODE == SW_CONV_RESID_BF16) {   // CIN == COUT: the block's input at this pixel, from LDS
-                            const bf16x4 xin = *reinterpret_cast<const bf16x4 *>(
-                                T + ((w + 1) * kStageCols + pb * 16 + n + 1) * CIN + co0);
-                            o2 = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+                    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                            for (int q = 0; q < 4; ++q) v[q] += (float)xin[q];
-                            if (a.y2) *reinterpret_cast<bf16x4 *>((__bf16 *)a.y2 + at) = o2;
+                        for (int pb = 0; pb < NPB; ++pb) {
+                            f32x4 v = relu_part(mb, pb);
+                            if (MODE == SW_CONV_RESID_BF16) {   // CIN == COUT: the block's input at this pixel, from LDS
+                                const bf16x4 xin = *reinterpret_cast<const bf16x4 *>(
+                                    T + ((w + 1) * kStageCols + pb * 16 + n + 1) * CIN + mb * 16 + 4 * g);
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) v[q] += (float)xin[q];
+                            }
+                            slot(mb, pb) = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
                         }
-                        o = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
-                        *reinterpret_cast<bf16x4 *>((__bf16 *)a.y + at) = o;
-                    } else {   // SW_CONV_DGRAD
-                        if (a.add) {
-                            const bf16x4 ad = *reinterpret_cast<const bf16x4 *>((const __bf16 *)a.add + at);
+                    flush((__bf16 *)a.y);
+                    if (MODE == SW_CONV_RESID_BF16 && a.y2) {
 #pragma unroll
-                            for (int q = 0; q < 4; ++q) v[q] += (float)ad[q];
-                        }
-                        o2 = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
-                        if (a.y) *reinterpret_cast<bf16x4 *>((__bf16 *)a.y + at) = o2;
-                        const bf16x4 mk = *reinterpret_cast<const bf16x4 *>((const __bf16 *)a.mask + at);
+                        for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) o[q] = (float)mk[q] > 0.f ? o2[q] : (__bf16)0.f;
-                        *reinterpret_cast<bf16x4 *>((__bf16 *)a.y2 + at) = o;
+                            for (int pb = 0; pb < NPB; ++pb) {
+                                const f32x4 v = relu_part(mb, pb);
+                                slot(mb, pb) = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+                            }
+                        flush((__bf16 *)a.y2);
                     }
+                } else {   // SW_CONV_DGRAD: G = conv + add into y (if set), dZ = G where mask > 0 into y2
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                        for (int pb = 0; pb < NPB; ++pb) {
+                            f32x4 v = acc[mb][pb];
+                            if (a.add) {
+                                const bf16x4 ad = *reinterpret_cast<const bf16x4 *>(
+                                    (const __bf16 *)a.add + row0 + (pb * 16 + n) * COUT + mb * 16 + 4 * g);
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) v[q] += (float)ad[q];
+                            }
+                            slot(mb, pb) = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+                        }
+                    if (a.y) flush((__bf16 *)a.y);
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                        for (int pb = 0; pb < NPB; ++pb) {   // each lane rewrites only its own values
+                            const bf16x4 mk = *reinterpret_cast<const bf16x4 *>(
+                                (const __bf16 *)a.mask + row0 + (pb * 16 + n) * COUT + mb * 16 + 4 * g);
+                            bf16x4 gv = slot(mb, pb);
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) gv[q] = (float)mk[q] > 0.f ? gv[q] : (__bf16)0.f;
+                            slot(mb, pb) = gv;
+                        }
+                    flush((__bf16 *)a.y2);
                 }
             }
         }
