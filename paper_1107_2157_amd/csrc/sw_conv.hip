@@ -156,9 +156,9 @@ __global__ __launch_bounds__(256) void k_conv3x3(SwConvArgs a, int tiles_y, int 
                 auto flush = [&](__bf16 *dst) {
                     wave_sync();
 #pragma unroll
-                    for (int k = 0; k < kTileCols * COUT / 512; ++k)
-                        *reinterpret_cast<bf16x8 *>(dst + row0 + k * 512 + lane * 8) =
-                            *reinterpret_cast<const bf16x8 *>(&ostage[w][k * 512 + lane * 8]);
+                    for (int k = 0; k < kTileCols * COUT / 512; ++k)   // non-temporal: GB-sized tensors
+                        __builtin_nontemporal_store(*reinterpret_cast<const bf16x8 *>(&ostage[w][k * 512 + lane * 8]),
+                                                    reinterpret_cast<bf16x8 *>(dst + row0 + k * 512 + lane * 8));
                     wave_sync();   // the copy's reads are done before the area is written again
                 };
                 auto relu_part = [&](int mb, int pb) {
