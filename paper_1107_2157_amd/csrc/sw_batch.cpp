@@ -208,6 +208,12 @@ int sw_batch_internal_step_masked(sw_batch *b, int nsteps, const int32_t *active
     return enqueue(b, r, nsteps, b->cur, s, active);
 }
 
+int sw_batch_internal_set_cur(sw_batch *b, int cur) {
+    if (!b || (cur != 0 && cur != 1)) return sw_fail(SW_EINVAL, "batch: set_cur %d", cur);
+    b->cur = cur;
+    return SW_OK;
+}
+
 bool sw_batch_internal_compatible(const sw_batch *a, const sw_batch *b) {
     if (!a || !b || a->n != b->n || a->region != b->region || a->g != b->g || a->dx != b->dx) return false;
     if (std::memcmp(&a->opts, &b->opts, sizeof a->opts) != 0) return false;

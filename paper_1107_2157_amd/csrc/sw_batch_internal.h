@@ -72,3 +72,6 @@ bool sw_batch_internal_compatible(const sw_batch *a, const sw_batch *b);
 // dst := src's current buffer (whole region, halos included) and current-buffer
 // index, with dst's time and step counters cleared.  Compatible batches only.
 int sw_batch_internal_copy_state(sw_batch *dst, const sw_batch *src, hipStream_t s);
+// Make buffer cur (0 or 1) the batch's current buffer (its contents must
+// already hold the state, halos included).
+int sw_batch_internal_set_cur(sw_batch *b, int cur);

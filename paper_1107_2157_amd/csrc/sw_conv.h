@@ -85,12 +85,13 @@ hipError_t sw_sur_apply(const float *delta, const SwBatchGrid *grids, int cur, i
                         int project, int bcx, int bcy, SwGateStats *st, hipStream_t s);
 hipError_t sw_sur_gate(SwGateStats *st, int B, double mass_tol, double hmin, int *active, int *fallbacks,
                        hipStream_t s);
-// Accepted grids: copy the prediction (buffer cur ^ 1) into buffer cur.
-hipError_t sw_sur_accept(const SwBatchGrid *grids, int cur, int B, int H, int W, const int *active, hipStream_t s);
+// Rejected grids (active != 0): copy U^n (buffer cur, halos included) over
+// the prediction in buffer cur ^ 1, where the solver then takes the jump.
+hipError_t sw_sur_restore(const SwBatchGrid *grids, int cur, int B, int H, int W, const int *active, hipStream_t s);
 hipError_t sw_sur_zero_stats(SwGateStats *st, int B, hipStream_t s);
 
-// Judge: per grid, relative L2(h) of the rollout (batch grids `a`) against
-// the plain solver's run (`ref`), both on their current buffer `cur`; grids
+// Judge: per grid, relative L2(h) of the rollout (batch grids `a`, current
+// buffer cur_a) against the plain solver's run (`ref`, buffer cur_ref); grids
 // above l2_tol take the solver's state (halos included), their fallback count
 // becomes jumps, their time / step counters become start + the solver's, and
 // their unstable flag the solver's.
@@ -100,6 +101,6 @@ struct SwJudge {
     long long steps0;  // step count at the start of the advance
 };
 hipError_t sw_sur_judge_begin(const SwBatchScalars *sc, int B, SwJudge *j, hipStream_t s);
-hipError_t sw_sur_judge(const SwBatchGrid *a, const SwBatchGrid *ref, int cur, int B, int H, int W, SwJudge *j,
-                        SwBatchScalars *sc, const SwBatchScalars *ref_sc, double l2_tol, int jumps, int *reject,
-                        int *fallbacks, double *l2, hipStream_t s);
+hipError_t sw_sur_judge(const SwBatchGrid *a, int cur_a, const SwBatchGrid *ref, int cur_ref, int B, int H, int W,
+                        SwJudge *j, SwBatchScalars *sc, const SwBatchScalars *ref_sc, double l2_tol, int jumps,
+                        int *reject, int *fallbacks, double *l2, hipStream_t s);

@@ -352,7 +352,8 @@ sw_status sw_surrogate_advance(sw_net *n, sw_batch *solver, int32_t nsteps, cons
         return sw_fail(SW_EINVAL, "surrogate_advance: boundary conditions differ from the network's");
     if (gate->judge && !(gate->l2_tol >= 0)) return sw_fail(SW_EINVAL, "surrogate_advance: l2_tol %g", gate->l2_tol);
     hipStream_t s = (hipStream_t)stream;
-    const int B = bi.n, cur = bi.cur;
+    const int B = bi.n;
+    int cur = bi.cur;
     if (gate->judge) {   // the plain solver's copy of U^n, and the books at the start
         if (n->shadow && !sw_batch_internal_compatible(n->shadow, solver)) drop_shadow(n);
         if (!n->shadow && (st = (sw_status)sw_batch_internal_clone(solver, &n->shadow, &n->shadow_arena)) != SW_OK)
@@ -362,6 +363,7 @@ sw_status sw_surrogate_advance(sw_net *n, sw_batch *solver, int32_t nsteps, cons
     }
     if ((st = sw_batch_fill_halo(solver, stream)) != SW_OK) return st;
     for (int j = 0; j < nsteps / n->cfg.jump; ++j) {
+        // U^n in buffer cur; every grid's U^{n+jump} ends in buffer cur ^ 1
         SHIP(sw_sur_prep_planes(bi.d_grids, cur, B, n->H, n->W, n->nrm, n->x0, s));
         if ((st = forward(n, B, false, s)) != SW_OK) return st;
         SHIP(sw_sur_zero_stats(n->stats, B, s));
@@ -369,18 +371,19 @@ sw_status sw_surrogate_advance(sw_net *n, sw_batch *solver, int32_t nsteps, cons
         SHIP(sw_sur_apply(n->delta, bi.d_grids, cur, B, n->H, n->W, n->nrm, gate->project_mass, bi.bc_x, bi.bc_y,
                           n->stats, s));
         SHIP(sw_sur_gate(n->stats, B, gate->mass_rel_tol, gate->hmin, n->active, fallbacks, s));
-        // rejected grids: the plain solver takes the jump from U^n
+        // rejected grids: U^n over the prediction, then the plain solver takes the jump (an even
+        // number of steps, so it ends where it started); accepted grids keep the prediction
+        SHIP(sw_sur_restore(bi.d_grids, cur, B, n->H, n->W, n->active, s));
+        cur ^= 1;
+        if ((st = (sw_status)sw_batch_internal_set_cur(solver, cur)) != SW_OK) return st;
         if ((st = (sw_status)sw_batch_internal_step_masked(solver, n->cfg.jump, n->active, s)) != SW_OK) return st;
-        // accepted grids: the prediction becomes U^{n+jump}
-        SHIP(sw_sur_accept(bi.d_grids, cur, B, n->H, n->W, n->active, s));
     }
     if (gate->judge) {   // the plain solver over the same span, then the verdict per grid
         if ((st = sw_batch_step(n->shadow, nsteps, stream)) != SW_OK) return st;
         SwBatchInfo si;
         if ((st = (sw_status)sw_batch_internal_info(n->shadow, &si)) != SW_OK) return st;
-        if (si.cur != cur) return sw_fail(SW_EINVAL, "surrogate_advance: judge buffers out of step");
-        SHIP(sw_sur_judge(bi.d_grids, si.d_grids, cur, B, n->H, n->W, n->judge, bi.d_sc, si.d_sc, gate->l2_tol,
-                          nsteps / n->cfg.jump, n->reject, fallbacks, l2, s));
+        SHIP(sw_sur_judge(bi.d_grids, cur, si.d_grids, si.cur, B, n->H, n->W, n->judge, bi.d_sc, si.d_sc,
+                          gate->l2_tol, nsteps / n->cfg.jump, n->reject, fallbacks, l2, s));
     }
     return SW_OK;
 }

@@ -421,17 +421,17 @@ __global__ void k_gate(SwGateStats *st, int B, double mass_tol, double hmin, int
     if (fallbacks) fallbacks[b] += reject;
 }
 
-// Accepted grids: copy the whole halo'd rectangle of buffer cur ^ 1 into cur.
-__global__ __launch_bounds__(256) void k_accept(const SwBatchGrid *grids, int cur, int H, int W, const int *active) {
+// Rejected grids: copy the whole halo'd rectangle of buffer cur into cur ^ 1.
+__global__ __launch_bounds__(256) void k_restore(const SwBatchGrid *grids, int cur, int H, int W, const int *active) {
     const int b = blockIdx.y;
-    if (active[b]) return;
+    if (!active[b]) return;
     const SwBatchGrid &g = grids[b];
     const int64_t n = (int64_t)(H + 2) * (W + 2);
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         const int yy = (int)(p / (W + 2)), xx = (int)(p - (int64_t)yy * (W + 2));
         const int64_t off = (int64_t)(yy - 1) * g.pitch + (xx - 1);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) ((float *)g.plane[cur][k])[off] = ((const float *)g.plane[cur ^ 1][k])[off];
+        for (int k = 0; k < 3; ++k) ((float *)g.plane[cur ^ 1][k])[off] = ((const float *)g.plane[cur][k])[off];
     }
 }
 
@@ -447,11 +447,11 @@ __global__ void k_judge_begin(const SwBatchScalars *sc, int B, SwJudge *j) {
 }
 
 // Per grid (blockIdx.y): sums of (h - h_ref)^2 and h_ref^2 over the interior.
-__global__ __launch_bounds__(256) void k_judge_sums(const SwBatchGrid *ga, const SwBatchGrid *gr, int cur, int H,
-                                                    int W, SwJudge *j) {
+__global__ __launch_bounds__(256) void k_judge_sums(const SwBatchGrid *ga, int cur_a, const SwBatchGrid *gr,
+                                                    int cur_r, int H, int W, SwJudge *j) {
     const int b = blockIdx.y;
-    const float *A = (const float *)ga[b].plane[cur][0];
-    const float *R = (const float *)gr[b].plane[cur][0];
+    const float *A = (const float *)ga[b].plane[cur_a][0];
+    const float *R = (const float *)gr[b].plane[cur_r][0];
     const int64_t pa = ga[b].pitch, pr = gr[b].pitch, n = (int64_t)H * W;
     double d2 = 0.0, r2 = 0.0;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
@@ -486,8 +486,8 @@ __global__ void k_judge_decide(SwJudge *j, int B, SwBatchScalars *sc, const SwBa
 }
 
 // Rejected grids: copy the solver's halo'd rectangle (buffer cur) over the rollout's.
-__global__ __launch_bounds__(256) void k_judge_copy(const SwBatchGrid *ga, const SwBatchGrid *gr, int cur, int H,
-                                                    int W, const int *reject) {
+__global__ __launch_bounds__(256) void k_judge_copy(const SwBatchGrid *ga, int cur_a, const SwBatchGrid *gr,
+                                                    int cur_r, int H, int W, const int *reject) {
     const int b = blockIdx.y;
     if (!reject[b]) return;
     const int64_t n = (int64_t)(H + 2) * (W + 2);
@@ -495,7 +495,7 @@ __global__ __launch_bounds__(256) void k_judge_copy(const SwBatchGrid *ga, const
         const int yy = (int)(p / (W + 2)), xx = (int)(p - (int64_t)yy * (W + 2));
         const int64_t oa = (int64_t)(yy - 1) * ga[b].pitch + (xx - 1), orr = (int64_t)(yy - 1) * gr[b].pitch + (xx - 1);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) ((float *)ga[b].plane[cur][k])[oa] = ((const float *)gr[b].plane[cur][k])[orr];
+        for (int k = 0; k < 3; ++k) ((float *)ga[b].plane[cur_a][k])[oa] = ((const float *)gr[b].plane[cur_r][k])[orr];
     }
 }
 
@@ -607,9 +607,9 @@ hipError_t sw_sur_gate(SwGateStats *st, int B, double mass_tol, double hmin, int
     return hipGetLastError();
 }
 
-hipError_t sw_sur_accept(const SwBatchGrid *grids, int cur, int B, int H, int W, const int *active, hipStream_t s) {
+hipError_t sw_sur_restore(const SwBatchGrid *grids, int cur, int B, int H, int W, const int *active, hipStream_t s) {
     dim3 grid(grid_for((int64_t)(H + 2) * (W + 2), 64), B);
-    k_accept<<<grid, 256, 0, s>>>(grids, cur, H, W, active);
+    k_restore<<<grid, 256, 0, s>>>(grids, cur, H, W, active);
     return hipGetLastError();
 }
 
@@ -618,14 +618,14 @@ hipError_t sw_sur_judge_begin(const SwBatchScalars *sc, int B, SwJudge *j, hipSt
     return hipGetLastError();
 }
 
-hipError_t sw_sur_judge(const SwBatchGrid *a, const SwBatchGrid *ref, int cur, int B, int H, int W, SwJudge *j,
-                        SwBatchScalars *sc, const SwBatchScalars *ref_sc, double l2_tol, int jumps, int *reject,
-                        int *fallbacks, double *l2, hipStream_t s) {
-    k_judge_sums<<<dim3(grid_for((int64_t)H * W, 64), B), 256, 0, s>>>(a, ref, cur, H, W, j);
+hipError_t sw_sur_judge(const SwBatchGrid *a, int cur_a, const SwBatchGrid *ref, int cur_ref, int B, int H, int W,
+                        SwJudge *j, SwBatchScalars *sc, const SwBatchScalars *ref_sc, double l2_tol, int jumps,
+                        int *reject, int *fallbacks, double *l2, hipStream_t s) {
+    k_judge_sums<<<dim3(grid_for((int64_t)H * W, 64), B), 256, 0, s>>>(a, cur_a, ref, cur_ref, H, W, j);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_judge_decide<<<(B + 255) / 256, 256, 0, s>>>(j, B, sc, ref_sc, l2_tol, jumps, reject, fallbacks, l2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_judge_copy<<<dim3(grid_for((int64_t)(H + 2) * (W + 2), 64), B), 256, 0, s>>>(a, ref, cur, H, W, reject);
+    k_judge_copy<<<dim3(grid_for((int64_t)(H + 2) * (W + 2), 64), B), 256, 0, s>>>(a, cur_a, ref, cur_ref, H, W, reject);
     return hipGetLastError();
 }
