@@ -374,12 +374,16 @@ class Batch:
         nx, ny = self.shapes[0]
         if out is None:
             out = torch.empty((self.n, 3, ny, nx), dtype=self.torch_dtype, device="cuda")
+        elif (not isinstance(out, torch.Tensor) or tuple(out.shape) != (self.n, 3, ny, nx) or not out.is_cuda
+              or out.dtype != self.torch_dtype or not out.is_contiguous()):
+            raise ValueError(f"out: expected a contiguous {self.torch_dtype} device tensor of shape {(self.n, 3, ny, nx)}")
         check(lib().sw_batch_export(self.handle, ctypes.c_void_p(out.data_ptr()), _stream_handle()), "sw_batch_export")
         return out
 
     def load(self, dense: torch.Tensor):
         """Set every grid's current state from a dense [n][3][ny][nx] device tensor."""
-        d = dense.to(self.torch_dtype).contiguous()
+        nx, ny = self.shapes[0]
+        d = _device_tensor(dense, (self.n, 3, ny, nx), self.torch_dtype, "dense")
         check(lib().sw_batch_import(self.handle, ctypes.c_void_p(d.data_ptr()), _stream_handle()), "sw_batch_import")
         torch.cuda.synchronize()
 
@@ -405,6 +409,21 @@ def _hip_d2d(dst: int, src: int, nbytes: int):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _device_tensor(t, shape, dtype, name: str, convert: bool = True) -> torch.Tensor:
+    """A contiguous device tensor of exactly this shape and dtype (converted
+    if allowed), so the library never reads or writes past its end."""
+    if not isinstance(t, torch.Tensor) or tuple(t.shape) != tuple(shape):
+        got = tuple(t.shape) if isinstance(t, torch.Tensor) else type(t).__name__
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {got}")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: expected a device tensor")
+    if t.dtype != dtype:
+        if not convert:
+            raise ValueError(f"{name}: expected {dtype}, got {t.dtype}")
+        t = t.to(dtype)
+    return t.contiguous()
 
 
 class Surrogate:
@@ -452,14 +471,16 @@ class Surrogate:
 
     def forward(self, u: torch.Tensor) -> torch.Tensor:
         """u: [B][3][H][W] FP32 on the GPU -> normalised delta [B][H][W][4]."""
-        u = u.contiguous()
-        B = u.shape[0]
+        B = u.shape[0] if isinstance(u, torch.Tensor) and u.dim() == 4 else -1
+        u = _device_tensor(u, (B, 3, self.H, self.W), torch.float32, "u")
         out = torch.empty((B, self.H, self.W, 4), dtype=torch.float32, device="cuda")
         check(lib().sw_surrogate_forward(self.handle, _ptr(u), B, _ptr(out), _stream_handle()),
               "sw_surrogate_forward")
         return out
 
     def activation(self, layer: int, B: int) -> torch.Tensor:
+        if not 1 <= B <= self.max_batch:
+            raise ValueError(f"B = {B} outside [1, {self.max_batch}]")
         p, nb = ctypes.c_void_p(), ctypes.c_int64()
         check(lib().sw_surrogate_activation(self.handle, layer, ctypes.byref(p), ctypes.byref(nb)),
               "sw_surrogate_activation")
@@ -478,15 +499,20 @@ class Surrogate:
         _hip_d2d(buf.data_ptr(), p.value, nbytes)
         return buf.view(shape)
 
+    def _pair(self, u, u8):
+        B = u.shape[0] if isinstance(u, torch.Tensor) and u.dim() == 4 else -1
+        shape = (B, 3, self.H, self.W)
+        return B, _device_tensor(u, shape, torch.float32, "u"), _device_tensor(u8, shape, torch.float32, "u8")
+
     def grad(self, u, u8):
-        B = u.shape[0]
+        B, u, u8 = self._pair(u, u8)
         g = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
-        check(lib().sw_surrogate_grad(self.handle, _ptr(u.contiguous()), _ptr(u8.contiguous()), B, _ptr(g),
-                                      _ptr(self.loss), _stream_handle()), "sw_surrogate_grad")
+        check(lib().sw_surrogate_grad(self.handle, _ptr(u), _ptr(u8), B, _ptr(g), _ptr(self.loss), _stream_handle()),
+              "sw_surrogate_grad")
         return g, self.loss
 
     def train_step(self, u, u8, lr: float):
-        B = u.shape[0]
+        B, u, u8 = self._pair(u, u8)
         check(lib().sw_surrogate_train_step(self.handle, _ptr(u), _ptr(u8), B, lr, _ptr(self.loss),
                                             _stream_handle()), "sw_surrogate_train_step")
         return self.loss

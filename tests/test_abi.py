@@ -149,3 +149,15 @@ def test_binding_structs_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for fname, _ in cls._fields_:
             assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_binding_checks_tensors_before_the_abi():
+    """Tensors reach the C ABI only as contiguous device tensors of the exact
+    shape the call implies (the library cannot check plain pointers)."""
+    import torch
+    with pytest.raises(ValueError, match="shape"):
+        sw._device_tensor(torch.zeros(2, 3, 4, 5), (2, 3, 4, 4), torch.float32, "u")
+    with pytest.raises(ValueError, match="device"):
+        sw._device_tensor(torch.zeros(2, 3, 4, 4), (2, 3, 4, 4), torch.float32, "u")
+    with pytest.raises(ValueError, match="shape"):
+        sw._device_tensor([1.0, 2.0], (2,), torch.float32, "u")

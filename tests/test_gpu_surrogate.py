@@ -214,3 +214,24 @@ def test_committed_weights_gain_at_256():
     ej, _ = surrogate.rel_l2_h(judged[:, 0], ref[:, 0])
     assert bool((ej <= 1e-2).all())
     torch.testing.assert_close(l2.cpu(), e.cpu(), rtol=1e-6, atol=1e-12)
+
+
+def test_binding_rejects_mismatched_tensors():
+    """Wrong shapes, host tensors and oversize batches are refused before any
+    kernel runs (a kernel would read or write past the tensor's end)."""
+    net = sw.Surrogate(64, 64, 2, jump=8, seed=1)
+    with pytest.raises(ValueError):
+        net.forward(torch.zeros(2, 3, 64, 48, device="cuda"))
+    with pytest.raises(ValueError):
+        net.forward(torch.zeros(3, 3, 64, 64))
+    with pytest.raises(ValueError):
+        net.train_step(torch.zeros(2, 3, 64, 64, device="cuda"), torch.zeros(2, 3, 32, 64, device="cuda"), 1e-3)
+    with pytest.raises(ValueError):
+        net.activation(1, 3)
+    b = sw.Batch([(64, 40)] * 2, dtype="f32")
+    with pytest.raises(ValueError):
+        b.export(torch.zeros(2, 3, 40, 63, device="cuda"))
+    with pytest.raises(ValueError):
+        b.load(torch.zeros(2, 3, 40, 64))
+    with pytest.raises(ValueError):
+        b.load(torch.zeros(1, 3, 40, 64, device="cuda"))
