@@ -123,6 +123,50 @@ def run_workload(name, steps, warmup, sw, ics, torch, tune_cache, fixed=None):
     return out
 
 
+def run_fixed_dt(steps, fused_tuning, sw, ics, torch, tune_cache):
+    """Fixed-dt mode (dt = 0.5 dx / the initial state's max signal speed) on
+    the headline grid: the fused single-step kernel in the headline's tuned
+    shape against the autotuner's fixed-dt choice, which may be temporal
+    blocking (K steps of a tile per launch, staged in LDS).  `steps` is a
+    multiple of every K, so no single-step remainder runs.  Both runs start
+    from the same state; their final states must be bitwise equal."""
+    n, dtype, _, seed, _, _ = WORKLOADS["swe16384-f32-periodic"]
+    st = ics.bumps_state(n, n, seed=seed, periodic=True, count=8, device="cuda")
+    h, hu, hv = st
+    dt = 0.5 / float((torch.maximum(hu.abs(), hv.abs()) / h + torch.sqrt(9.8 * h)).max())
+    s = sw.Solver(n, n, dtype=dtype, bc_x=sw.PERIODIC, bc_y=sw.PERIODIC, cfl=0.0, dt_fixed=dt)
+
+    def restart():
+        s.state.cur = 0
+        s.set_state(*st)
+        s.reset_time()
+
+    out = {"workload": "swe16384-f32-periodic-fixed-dt", "dtype": dtype, "steps": steps, "dt": dt}
+    finals = []
+    for label in ("fused", "tuned"):
+        restart()
+        if label == "fused":
+            s.set_tuning(**fused_tuning)
+            tuning = s.get_tuning()
+        else:
+            tuning = s.autotune(steps_per_trial=3, cache_path=tune_cache)
+        restart()
+        s.step(steps)                                # graph capture + warm-up
+        restart()
+        t = timed(torch, lambda: s.step(steps))
+        s.sync_status()
+        finals.append([s.interior(k).clone() for k in range(3)])
+        g = n * n * steps / t / 1e9
+        out[label] = {"tuning": tuning, "gcells_per_s": g, "ms_per_step": 1e3 * t / steps,
+                      # bandwidth a single-step kernel would need for this rate (24 B per cell-update)
+                      "single_step_equiv_hbm_frac": g * 24 / HBM_PEAK_GBS}
+    out["speedup"] = out["tuned"]["gcells_per_s"] / out["fused"]["gcells_per_s"]
+    out["bitwise_equal"] = all(torch.equal(a, b) for a, b in zip(*finals))
+    del s, st, finals
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_batch(steps, sw, ics, torch, tune_cache, per_grid_steps):
     """Batched workload: 512 grids, sides 64*(1 + floor(16u)) (seed 4), each
     with its own 1-8 Gaussian bumps (seed 4000 + k), FP32, reflective walls.
@@ -272,6 +316,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 512-grid run")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate run")
+    ap.add_argument("--fixed-dt-only", action="store_true",
+                    help="run only the fixed-dt comparison (fused single step against temporal blocking)")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="run only the learned-surrogate workload and print its record")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1107_2157_amd", "tune_cache_gfx950.txt"),
@@ -303,6 +349,14 @@ def main():
         print(json.dumps(run_surrogate(sw, ics, torch)), flush=True)
         return
 
+    if args.fixed_dt_only:
+        probe = make_solver("swe16384-f32-periodic", sw, ics, torch)
+        fused = probe.autotune(steps_per_trial=3, cache_path=args.tune_cache)   # the headline's shape
+        del probe
+        torch.cuda.empty_cache()
+        print(json.dumps(run_fixed_dt(210, fused, sw, ics, torch, args.tune_cache)), flush=True)
+        return
+
     steps = args.steps or WORKLOADS[args.workload][4]
     fixed = tuple(int(x) for x in args.tuning.split(",")) if args.tuning else None
     main_run = run_workload(args.workload, steps, args.warmup, sw, ics, torch, args.tune_cache, fixed)
@@ -324,6 +378,9 @@ def main():
             also.append({k: r[k] for k in ("workload", "dtype", "steps", "gcells_per_s", "ms_per_step",
                                             "kernel_us", "finite", "tuning")} |
                         {"hbm_frac": r["alg_bytes_per_launch"] / (r["kernel_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS})
+
+    if not args.no_also and args.workload == "swe16384-f32-periodic":
+        also.append(run_fixed_dt(210, main_run["tuning"], sw, ics, torch, args.tune_cache))
 
     if not args.no_also and not args.no_batch and args.workload == "swe16384-f32-periodic":
         also.append(run_batch(500, sw, ics, torch, args.tune_cache, per_grid_steps=50))

@@ -139,18 +139,24 @@ sw_status sw_reset_time(sw_ctx *ctx, void *stream);
 
 /* Kernel variant used by sw_step: 0 = auto (fastest known), 1 = one thread
  * per cell reading neighbours from global memory (baseline), 2 = fused
- * row-marching kernel (paper scheme only).  Results agree up to rounding
- * order.  Errors: SW_EINVAL for an unknown variant. */
+ * row-marching kernel (paper scheme only), 3 = temporal blocking: K steps of
+ * a tile and its K-cell halo per launch in LDS (paper scheme with a fixed dt
+ * only; a CFL dt depends on every cell after each step; nsteps % K remaining
+ * steps use the fused kernel).  Variants 2 and 3 give bitwise identical
+ * states; the baseline agrees with them up to rounding order.
+ * Errors: SW_EINVAL for an unknown variant; sw_step reports SW_ENOTSUP for a
+ * variant the options exclude. */
 sw_status sw_set_variant(sw_ctx *ctx, int32_t variant);
 
 /* Launch shape of the step kernel (what the autotuner searches).  Zero
- * fields mean "library default".  All fused shapes compute every cell with
- * the same arithmetic, so their results are bitwise identical; the per-cell
- * baseline agrees with them to rounding. */
+ * fields mean "library default".  All fused and blocked shapes compute
+ * every cell with the same arithmetic, so their results are bitwise
+ * identical; the per-cell baseline agrees with them to rounding.  Blocked
+ * defaults: K = 5 and 16 waves in SW_F32, K = 3 and 8 waves in SW_F64. */
 typedef struct {
-    int32_t variant;    /* 0 auto, 1 per-cell baseline, 2 fused */
-    int32_t rows;       /* fused: rows per tile (>= 1) */
-    int32_t vec;        /* fused: cells per lane; SW_F32: 1, 2 or 4, SW_F64: 1 or 2 */
+    int32_t variant;    /* 0 auto, 1 per-cell baseline, 2 fused, 3 temporal blocking */
+    int32_t rows;       /* fused: rows per tile (>= 1); blocked: steps per launch K (3, 5; 7 in SW_F32) */
+    int32_t vec;        /* fused: cells per lane; SW_F32: 1, 2 or 4, SW_F64: 1 or 2; blocked: waves per tile (4, 8, 16) */
     int32_t occupancy;  /* fused: register budget in waves per SIMD: 0 (compiler's choice), 3 or 4 */
     int32_t prefetch;   /* fused: rows loaded ahead of the row being updated: 1, 2 or 3 */
     int32_t order;      /* fused: tile order: 0 row-block-major per XCD, 1 vertically grouped per XCD, 2 plain */
@@ -169,9 +175,10 @@ sw_status sw_set_graph(sw_ctx *ctx, int32_t enable);
  * stream with the caller's state (steps_per_trial >= 1 steps each), then set
  * it.  buf[cur], its halo and the context's time/flags are saved first and
  * restored afterwards, so the simulation is left where it was.  Allocates
- * (and frees) a temporary copy of one buffer of device memory.  If
- * cache_path is non-NULL, a cached choice for the same (GPU, dtype, scheme,
- * grid) is used without timing, and new choices are appended there.
+ * (and frees) a temporary copy of one buffer of device memory.  With a
+ * fixed dt the blocked kernel is among the candidates.  If cache_path is
+ * non-NULL, a cached choice for the same (GPU, dtype, scheme, grid, fixed or
+ * CFL dt) is used without timing, and new choices are appended there.
  * best may be NULL.  Synchronises the stream.
  * Errors: SW_EINVAL, SW_ENOMEM, SW_EHIP, SW_ENOTSUP (no candidate ran). */
 sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per_trial, const char *cache_path, void *stream,

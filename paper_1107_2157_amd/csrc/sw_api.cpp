@@ -139,11 +139,28 @@ sw_status use_device(const sw_ctx *ctx) {
 sw_status enqueue_steps(sw_ctx *ctx, const sw_state *state, int nsteps, const SwTuning &tun, hipStream_t s) {
     SW_HIP(sw_launch_reset(ctx->sc, 0, s));
     SW_HIP(sw_launch_prologue(launch_of(ctx, state, state->cur), s));
-    int cur = state->cur;
-    for (int n = 0; n < nsteps; ++n) {
+    int cur = state->cur, n = 0;
+    if (tun.variant == 3) {   // K steps per launch (K odd: one buffer flip per launch, as K single steps)
+        for (; n + tun.rows <= nsteps; n += tun.rows) {
+            SwLaunch b = launch_of(ctx, state, cur);
+            b.step = n;
+            SW_HIP(sw_launch_tb(b, tun.rows, tun.vec, s));
+            cur ^= 1;
+        }
+    }
+    SwTuning single = tun;    // the remaining steps: the fused kernel in its default shape
+    if (tun.variant == 3) {
+        single.variant = 2;
+        single.vec = sw_fused_default_vec((int)ctx->opts.dtype);
+        single.rows = sw_fused_default_rows(ctx->grid.nx, ctx->grid.ny, single.vec);
+        single.minw = 0;
+        single.pd = 2;
+        single.order = 0;
+    }
+    for (; n < nsteps; ++n) {
         SwLaunch b = launch_of(ctx, state, cur);
         b.step = n;
-        SW_HIP(sw_launch_step(b, tun, s));
+        SW_HIP(sw_launch_step(b, single, s));
         cur ^= 1;
     }
     return SW_OK;
@@ -281,10 +298,22 @@ namespace {
 // Resolve defaults; returns SW_OK or an error for unsupported settings.
 sw_status resolve_tuning(const sw_ctx *ctx, const sw_tuning &in, SwTuning *out) {
     int variant = in.variant;
-    if (variant < 0 || variant > 2) return fail(SW_EINVAL, "tuning: unknown variant %d", variant);
+    if (variant < 0 || variant > 3) return fail(SW_EINVAL, "tuning: unknown variant %d", variant);
     if (variant == 0) variant = ctx->opts.scheme == SW_SCHEME_PAPER ? 2 : 1;
-    if (variant == 2 && ctx->opts.scheme != SW_SCHEME_PAPER)
-        return fail(SW_ENOTSUP, "tuning: the fused kernel implements the paper scheme only");
+    if ((variant == 2 || variant == 3) && ctx->opts.scheme != SW_SCHEME_PAPER)
+        return fail(SW_ENOTSUP, "tuning: the fused and blocked kernels implement the paper scheme only");
+    if (variant == 3) {
+        if (!(ctx->opts.dt_fixed > 0))
+            return fail(SW_ENOTSUP, "tuning: temporal blocking needs a fixed dt (a CFL dt depends on every cell)");
+        const int k = in.rows ? in.rows : (ctx->opts.dtype == SW_F64 ? 3 : 5);
+        if (!sw_tb_supported((int)ctx->opts.dtype, k))
+            return fail(SW_EINVAL, "tuning: %d steps per blocked launch not available for this dtype", k);
+        const int waves = in.vec ? in.vec : (ctx->opts.dtype == SW_F64 ? 8 : 16);
+        if (waves != 4 && waves != 8 && waves != 16)
+            return fail(SW_EINVAL, "tuning: %d waves per blocked tile (4, 8 or 16)", waves);
+        *out = SwTuning{3, k, waves, 0, 0, 0};
+        return SW_OK;
+    }
     out->variant = variant;
     out->vec = in.vec ? in.vec : sw_fused_default_vec((int)ctx->opts.dtype);
     out->rows = in.rows ? in.rows : sw_fused_default_rows(ctx->grid.nx, ctx->grid.ny, out->vec);
@@ -302,7 +331,7 @@ sw_status resolve_tuning(const sw_ctx *ctx, const sw_tuning &in, SwTuning *out) 
 
 sw_status sw_set_variant(sw_ctx *ctx, int32_t variant) {
     if (!ctx) return fail(SW_EINVAL, "set_variant: NULL context");
-    if (variant < 0 || variant > 2) return fail(SW_EINVAL, "set_variant: unknown variant %d", variant);
+    if (variant < 0 || variant > 3) return fail(SW_EINVAL, "set_variant: unknown variant %d", variant);
     sw_tuning t = ctx->tuning;
     t.variant = variant;
     SwTuning r;

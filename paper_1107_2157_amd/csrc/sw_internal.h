@@ -43,7 +43,7 @@ hipError_t sw_launch_prologue(const SwLaunch &a, hipStream_t s);
 hipError_t sw_launch_fill_halo(const SwLaunch &a, hipStream_t s);
 // Tuning of a step launch.
 struct SwTuning {
-    int variant;     // 1 per-cell baseline, 2 fused
+    int variant;     // 1 per-cell baseline, 2 fused, 3 temporal blocking (fixed dt; rows = steps per launch)
     int rows;        // fused: rows per tile
     int vec;         // fused: cells per lane
     int minw;        // fused: register budget as waves per SIMD (0 = compiler's choice)
@@ -54,6 +54,10 @@ hipError_t sw_launch_step(const SwLaunch &a, const SwTuning &t, hipStream_t s);
 hipError_t sw_launch_fused_cfg(const SwLaunch &a, int rows, int vec, int minw, int pd, int order,
                                hipStream_t s);
 int sw_fused_default_rows(int nx, int ny, int vec);
+// Temporal blocking (fixed dt, paper scheme): k steps of every cell per launch.
+bool sw_tb_supported(int dtype, int k);
+// waves per block: 4, 8 or 16 (the tile is the same; more waves hide LDS latency).
+hipError_t sw_launch_tb(const SwLaunch &a, int k, int waves, hipStream_t s);
 int sw_fused_default_vec(int dtype);
 bool sw_fused_supported(int dtype, int vec, int minw, int pd);
 

@@ -1,0 +1,233 @@
+// Temporal blocking of the fixed-dt step: K time steps per launch.
+//
+// With a fixed dt (the paper's mode) a cell after K steps depends only on the
+// state within K cells of it, so a block can stage a tile plus a K-cell halo
+// in LDS, advance it K steps there and write only the tile's own cells: the
+// state crosses HBM once per K steps instead of once per step.  Each step
+// shrinks the region that can still be advanced by one cell on every side;
+// on periodic axes the halo is loaded wrapped and simply advanced with the
+// rest, on reflective axes the ghost layer is re-derived from the new state
+// after every step (mirror image, wall-normal momentum negated), exactly as
+// the boundary rule does between single steps.  Within a step each wave
+// marches a chunk of rows the way the fused single-step kernel marches a
+// strip (same fluxes, same rounding, reciprocal included), so K blocked steps
+// give bitwise the state of K fused steps.
+//
+// Tile: RX = 64 staged columns (one lane per column, one wave width), so
+// TX = 64 - 2K output columns; TY output rows (32 in FP32, 16 in FP64) and
+// RY = TY + 2K staged rows, double buffered: 2 * 3 * 64 * RY values.  K is
+// odd, so a K-step launch flips the buffers once, as K single steps would.
+#include "sw_tile.h"
+
+using namespace sw;
+using namespace sw::tile;
+
+namespace {
+
+template <typename T> constexpr int tb_rows() { return sizeof(T) == 4 ? 32 : 16; }
+constexpr int kTbCols = 64;
+
+// One wave advances staged rows r0 .. r1 - 1 of one substep from P to Q
+// (lane = staged column), marching upward: each row's state is read once,
+// the G flux of the face below a row is carried to the next row and the F
+// flux of the face right of a lane reaches the lane to its right by DPP.
+// The arithmetic is the fused single-step kernel's, operation for
+// operation.  Rows r0 - 1 and r1 are read, not written; a row is stored
+// where `store_col` and the row lies in the domain (or the y axis is
+// periodic).  Wave-uniform: all 64 lanes call it together.
+template <typename T, int RX>
+__device__ __forceinline__ void tb_march(const T *const P[3], T *const Q[3], int r0, int r1, bool store_col, int y0,
+                                         int ny, bool pery, T k, T lx, T ly, T mx, T my) {
+    const int lane = threadIdx.x & 63;
+    T S[3], Bp[3], Gd[3];
+    auto load = [&](int r, T u[3]) {
+        const int o = r * RX + lane;
+        u[0] = P[0][o];
+        u[1] = P[1][o];
+        u[2] = P[2][o];
+    };
+    auto row = [&](auto face_c, auto emit_c, const T U[3], bool want_x, int rout) {
+        constexpr bool FACE = decltype(face_c)::value, EMIT = decltype(emit_c)::value;
+        const T h = U[0], p = U[1], q = U[2];
+        const T rc = fast_rcp(h);
+        const T u = p * rc, v = q * rc;
+        const T kh = k * h;
+        const T fp = fma(kh, h, p * u), fq = q * u, gq = fma(kh, h, q * v);
+        const T hh = T(0.5) * h, hp = T(0.5) * p, hq = T(0.5) * q;
+        if (FACE) {
+            T f[3];
+            yface_flux<T>(Bp[0] + fma(-ly, q, hh), Bp[1] + fma(-ly, fq, hp), Bp[2] + fma(-ly, gq, hq), k, f);
+            if (EMIT) {
+                const int y = y0 + rout;
+                if (store_col && (pery || (y >= 0 && y < ny))) {
+                    const int o = rout * RX + lane;
+#pragma unroll
+                    for (int kk = 0; kk < 3; ++kk) Q[kk][o] = fma(-my, f[kk] - Gd[kk], S[kk]);
+                }
+            }
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk) Gd[kk] = f[kk];
+        }
+        Bp[0] = fma(ly, q, hh);
+        Bp[1] = fma(ly, fq, hp);
+        Bp[2] = fma(ly, gq, hq);
+        if (!want_x) return;
+        T L[3], R[3], Rn[3], fr[3];
+        L[0] = fma(lx, p, hh);
+        L[1] = fma(lx, fp, hp);
+        L[2] = fma(lx, fq, hq);
+        R[0] = fma(-lx, p, hh);
+        R[1] = fma(-lx, fp, hp);
+        R[2] = fma(-lx, fq, hq);
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) Rn[kk] = from_next_lane(R[kk], R[kk]);
+        xface_flux<T>(L[0] + Rn[0], L[1] + Rn[1], L[2] + Rn[2], k, fr);
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) S[kk] = fma(-mx, fr[kk] - from_prev_lane(fr[kk], fr[kk]), U[kk]);
+    };
+    T A[3], B[3];
+    load(r0 - 1, A);
+    load(r0, B);
+    row(bconst<false>{}, bconst<false>{}, A, false, 0);
+    load(r0 + 1, A);
+    row(bconst<true>{}, bconst<false>{}, B, true, 0);
+    for (int r = r0 + 1; r < r1; ++r) {
+        const T U[3] = {A[0], A[1], A[2]};       // row r
+        load(r + 1, A);
+        row(bconst<true>{}, bconst<true>{}, U, true, r - 1);
+    }
+    row(bconst<true>{}, bconst<true>{}, A, false, r1 - 1);   // row r1 closes the chunk
+}
+
+template <typename T, int K, int NW>
+__global__ __launch_bounds__(64 * NW) void k_step_tb(SwLaunch a) {
+    constexpr int RX = kTbCols, TX = RX - 2 * K;
+    constexpr int TY = tb_rows<T>(), RY = TY + 2 * K, RN = RX * RY;
+    __shared__ T buf[2][3][RN];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: row loops run on scalars
+    const int nx = a.nx, ny = a.ny;
+    const bool perx = a.bc_x == 1, pery = a.bc_y == 1;
+    const int gx0 = blockIdx.x * TX - K, gy0 = blockIdx.y * TY - K;   // global cell of staged (0, 0)
+    const int64_t pitch = a.pitch;
+    const T *I[3] = {(const T *)a.in[0], (const T *)a.in[1], (const T *)a.in[2]};
+    T *O[3] = {(T *)a.out[0], (T *)a.out[1], (T *)a.out[2]};
+    const double dt = a.dt_fixed;
+    const T k = (T)(0.5 * a.g), g = (T)a.g;
+    const T lx = (T)(0.5 * dt / a.dx), ly = (T)(0.5 * dt / a.dy);
+    const T mx = (T)(dt / a.dx), my = (T)(dt / a.dy);
+
+    // staged column / row -> global index: wrapped on periodic axes, clamped to
+    // the ghost layer [-1, n] on reflective ones (cells beyond it feed no cell
+    // of the domain)
+    const int x = gx0 + lane;
+    int gx = x;
+    if (perx) {
+        gx %= nx;
+        if (gx < 0) gx += nx;
+    } else {
+        gx = min(max(gx, -1), nx);
+    }
+    const bool col_in = perx || (x >= 0 && x < nx);
+    const bool col_lo_wall = !perx && x == -1, col_hi_wall = !perx && x == nx;
+    for (int r = wave; r < RY; r += NW) {
+        int gy = gy0 + r;
+        if (pery) {
+            gy %= ny;
+            if (gy < 0) gy += ny;
+        } else {
+            gy = min(max(gy, -1), ny);
+        }
+        const int64_t off = (int64_t)gy * pitch + gx;
+        const int o = r * RX + lane;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) buf[0][f][o] = I[f][off];
+    }
+    __syncthreads();
+
+    int cur = 0;
+#pragma unroll 1
+    for (int s = 0; s < K; ++s) {
+        // cells that can still be advanced: staged rows / columns [s + 1, R - 2 - s],
+        // split into one chunk of consecutive rows per wave
+        const int lo = s + 1, hx = RX - 2 - s, hy = RY - 2 - s;
+        const bool col_live = lane >= lo && lane <= hx;
+        const int chunk = (hy - lo + NW) / NW;
+        const int r0 = lo + wave * chunk, r1 = min(r0 + chunk, hy + 1);
+        const T *P[3] = {buf[cur][0], buf[cur][1], buf[cur][2]};
+        T *Q[3] = {buf[cur ^ 1][0], buf[cur ^ 1][1], buf[cur ^ 1][2]};
+        if (r0 < r1) tb_march<T, RX>(P, Q, r0, r1, col_live && col_in, gy0, ny, pery, k, lx, ly, mx, my);
+        __syncthreads();
+        if (s + 1 < K && !(perx && pery)) {
+            // reflective ghost layer of the new state, where the next step reads it
+            for (int r = lo + wave; r <= hy; r += NW) {
+                const int y = gy0 + r;
+                const bool row_in = pery || (y >= 0 && y < ny);
+                const int o = r * RX + lane;
+                if (col_live && row_in && (col_lo_wall || col_hi_wall)) {
+                    const int src = o + (col_lo_wall ? 1 : -1);
+                    Q[0][o] = Q[0][src];
+                    Q[1][o] = -Q[1][src];
+                    Q[2][o] = Q[2][src];
+                }
+                if (col_live && col_in && !pery && (y == -1 || y == ny)) {
+                    const int src = o + (y == -1 ? RX : -RX);
+                    Q[0][o] = Q[0][src];
+                    Q[1][o] = Q[1][src];
+                    Q[2][o] = -Q[2][src];
+                }
+            }
+            __syncthreads();
+        }
+        cur ^= 1;
+    }
+
+    // the tile's own cells: U^{n+K}, their ghost images, the sticky flag
+    bool bad = false;
+    const bool col_out = lane >= K && lane < K + TX && x < nx;
+    for (int r = K + wave; r < K + TY; r += NW) {
+        const int y = gy0 + r;
+        if (!col_out || y >= ny) continue;
+        const int o = r * RX + lane;
+        const U3<T> v = {buf[cur][0][o], buf[cur][1][o], buf[cur][2][o]};
+        const int64_t off = (int64_t)y * pitch + x;
+        O[0][off] = v.h;
+        O[1][off] = v.p;
+        O[2][off] = v.q;
+        if (x == 0 || x == nx - 1 || y == 0 || y == ny - 1) write_ghosts(O, pitch, nx, ny, a.bc_x, a.bc_y, x, y, v);
+        bad |= !(signal_speed(v, g) <= finite_max<T>());
+    }
+    if (__ballot(bad) && lane == 0) atomicOr(&a.sc->unstable, 1u);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+#pragma unroll 1
+        for (int s = 0; s < K; ++s) a.sc->t += dt;   // as K single steps accumulate it
+        a.sc->last_dt = dt;
+        a.sc->steps += K;
+    }
+}
+
+template <typename T, int K> hipError_t launch_tb(const SwLaunch &a, int waves, hipStream_t s) {
+    constexpr int TX = kTbCols - 2 * K, TY = tb_rows<T>();
+    dim3 grid((a.nx + TX - 1) / TX, (a.ny + TY - 1) / TY);
+    if (waves == 16) k_step_tb<T, K, 16><<<grid, 1024, 0, s>>>(a);
+    else if (waves == 8) k_step_tb<T, K, 8><<<grid, 512, 0, s>>>(a);
+    else k_step_tb<T, K, 4><<<grid, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool sw_tb_supported(int dtype, int k) { return k == 3 || k == 5 || (dtype == 0 && k == 7); }
+
+hipError_t sw_launch_tb(const SwLaunch &a, int k, int waves, hipStream_t s) {
+    if (a.dt_fixed <= 0 || a.scheme != 0) return hipErrorInvalidValue;
+    if (a.dtype == 0) {
+        if (k == 3) return launch_tb<float, 3>(a, waves, s);
+        if (k == 5) return launch_tb<float, 5>(a, waves, s);
+        if (k == 7) return launch_tb<float, 7>(a, waves, s);
+    } else {
+        if (k == 3) return launch_tb<double, 3>(a, waves, s);
+        if (k == 5) return launch_tb<double, 5>(a, waves, s);
+    }
+    return hipErrorInvalidValue;
+}

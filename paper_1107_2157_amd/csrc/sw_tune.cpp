@@ -6,8 +6,12 @@
 // and the context's time scalars are saved first and restored before every
 // trial and at the end, so tuning leaves the simulation where it was.  Every
 // fused shape produces bitwise identical cells, so the choice affects speed
-// only.  Results are cached in a text file, one line per key
-//   <arch>:<CUs>:<dtype>:<scheme>:<nx>x<ny> variant rows vec occupancy prefetch order us_per_step
+// only.  With a fixed dt the temporally blocked kernel (K steps per launch,
+// 4, 8 or 16 waves per tile) joins the candidates; it too reproduces the
+// fused kernel's bits.  Results are cached in a text file, one line per key
+//   <arch>:<CUs>:<dtype>:<scheme>:<nx>x<ny>[:fixeddt] variant rows vec occupancy prefetch order us_per_step
+// (the suffix marks contexts with a fixed dt, whose choice may be a blocked
+// launch that a CFL-dt context cannot use).
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -22,7 +26,7 @@
 
 namespace {
 
-std::string tune_key(sw_dtype dtype, sw_scheme scheme, int nx, int ny, int device) {
+std::string tune_key(sw_dtype dtype, sw_scheme scheme, int nx, int ny, bool fixed_dt, int device) {
     hipDeviceProp_t prop;
     std::string arch = "unknown";
     int cus = 0;
@@ -35,6 +39,7 @@ std::string tune_key(sw_dtype dtype, sw_scheme scheme, int nx, int ny, int devic
     std::ostringstream k;
     k << arch << ":" << cus << ":" << (dtype == SW_F64 ? "f64" : "f32") << ":" << (int)scheme << ":" << nx << "x"
       << ny;
+    if (fixed_dt) k << ":fixeddt";
     return k.str();
 }
 
@@ -84,7 +89,7 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
     hipStream_t s = (hipStream_t)stream;
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) return SW_EHIP;
-    const std::string key = tune_key(opts.dtype, opts.scheme, grid.nx, grid.ny, device);
+    const std::string key = tune_key(opts.dtype, opts.scheme, grid.nx, grid.ny, opts.dt_fixed > 0, device);
 
     sw_tuning best{};
     if (cache_lookup(cache_path, key, &best) && sw_set_tuning(ctx, &best) == SW_OK) {
@@ -107,6 +112,10 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
                         for (int rows : rows_list)
                             for (int order = 0; order <= 1; ++order)
                                 cands.push_back(sw_tuning{2, rows, vecs[vi], occ, pd, order});
+        if (opts.dt_fixed > 0)   // temporal blocking: K steps per launch
+            for (int k : {3, 5, 7})
+                for (int waves : {4, 8, 16})
+                    if (sw_tb_supported((int)opts.dtype, k)) cands.push_back(sw_tuning{3, k, waves, 0, 0, 0});
     }
 
     // save buf[cur] (whole planes, halo included) and the time scalars
@@ -157,12 +166,14 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
         if ((he = hipEventRecord(e1, s)) != hipSuccess) break;
         if ((he = hipEventSynchronize(e1)) != hipSuccess) break;
         if ((he = hipEventElapsedTime(&ms1, e0, e1)) != hipSuccess) break;
+        // blocked candidates: a whole number of K-step launches in the difference
+        const int kt = cands[i].variant == 3 ? cands[i].rows * steps_per_trial : steps_per_trial;
         if ((he = hipEventRecord(e0, s)) != hipSuccess) break;
-        if (sw_step(ctx, state, 1 + steps_per_trial, stream) != SW_OK) continue;
+        if (sw_step(ctx, state, 1 + kt, stream) != SW_OK) continue;
         if ((he = hipEventRecord(e1, s)) != hipSuccess) break;
         if ((he = hipEventSynchronize(e1)) != hipSuccess) break;
         if ((he = hipEventElapsedTime(&msk, e0, e1)) != hipSuccess) break;
-        double us = 1000.0 * (msk - ms1) / steps_per_trial;
+        double us = 1000.0 * (msk - ms1) / kt;
         if (us < best_us) {
             best_us = us;
             best = cands[i];
