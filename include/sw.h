@@ -152,11 +152,11 @@ sw_status sw_set_variant(sw_ctx *ctx, int32_t variant);
  * fields mean "library default".  All fused and blocked shapes compute
  * every cell with the same arithmetic, so their results are bitwise
  * identical; the per-cell baseline agrees with them to rounding.  Blocked
- * defaults: K = 5 and 16 waves in SW_F32, K = 3 and 8 waves in SW_F64. */
+ * defaults: K = 5 with 16 waves in SW_F32, with 8 waves in SW_F64. */
 typedef struct {
     int32_t variant;    /* 0 auto, 1 per-cell baseline, 2 fused, 3 temporal blocking */
     int32_t rows;       /* fused: rows per tile (>= 1); blocked: steps per launch K (3, 5; 7 in SW_F32) */
-    int32_t vec;        /* fused: cells per lane; SW_F32: 1, 2 or 4, SW_F64: 1 or 2; blocked: waves per tile (4, 8, 16) */
+    int32_t vec;        /* fused: cells per lane; SW_F32: 1, 2 or 4, SW_F64: 1 or 2; blocked: waves per tile (4, 8, 12, 16) */
     int32_t occupancy;  /* fused: register budget in waves per SIMD: 0 (compiler's choice), 3 or 4 */
     int32_t prefetch;   /* fused: rows loaded ahead of the row being updated: 1, 2 or 3 */
     int32_t order;      /* fused: tile order: 0 row-block-major per XCD, 1 vertically grouped per XCD, 2 plain */

@@ -305,12 +305,12 @@ sw_status resolve_tuning(const sw_ctx *ctx, const sw_tuning &in, SwTuning *out) 
     if (variant == 3) {
         if (!(ctx->opts.dt_fixed > 0))
             return fail(SW_ENOTSUP, "tuning: temporal blocking needs a fixed dt (a CFL dt depends on every cell)");
-        const int k = in.rows ? in.rows : (ctx->opts.dtype == SW_F64 ? 3 : 5);
+        const int k = in.rows ? in.rows : 5;
         if (!sw_tb_supported((int)ctx->opts.dtype, k))
             return fail(SW_EINVAL, "tuning: %d steps per blocked launch not available for this dtype", k);
         const int waves = in.vec ? in.vec : (ctx->opts.dtype == SW_F64 ? 8 : 16);
-        if (waves != 4 && waves != 8 && waves != 16)
-            return fail(SW_EINVAL, "tuning: %d waves per blocked tile (4, 8 or 16)", waves);
+        if (waves != 4 && waves != 8 && waves != 12 && waves != 16)
+            return fail(SW_EINVAL, "tuning: %d waves per blocked tile (4, 8, 12 or 16)", waves);
         *out = SwTuning{3, k, waves, 0, 0, 0};
         return SW_OK;
     }

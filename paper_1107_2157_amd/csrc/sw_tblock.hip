@@ -14,9 +14,10 @@
 // give bitwise the state of K fused steps.
 //
 // Tile: RX = 64 staged columns (one lane per column, one wave width), so
-// TX = 64 - 2K output columns; TY output rows (32 in FP32, 16 in FP64) and
-// RY = TY + 2K staged rows, double buffered: 2 * 3 * 64 * RY values.  K is
-// odd, so a K-step launch flips the buffers once, as K single steps would.
+// TX = 64 - 2K output columns; RY staged rows (98 in FP32, 50 in FP64), so
+// TY = RY - 2K output rows; one buffer of 3 * 64 * RY values, updated in
+// place.  K is odd, so a K-step launch flips the global buffers once, as K
+// single steps would.
 #include "sw_tile.h"
 
 using namespace sw;
@@ -24,27 +25,41 @@ using namespace sw::tile;
 
 namespace {
 
-template <typename T> constexpr int tb_rows() { return sizeof(T) == 4 ? 32 : 16; }
+// Staged rows per tile (the tile's own rows TY = RY - 2K): three planes of
+// 64 x RY values in LDS, two tiles per CU (75 KB in FP32, 77 KB in FP64).
+// With 16 (FP32) or 12 / 8 (FP64) waves, RY - 2 - 2s rows split into equal
+// chunks at every step s, so no wave waits for a longer one at the barrier.
+template <typename T> constexpr int tb_staged_rows() { return sizeof(T) == 4 ? 98 : 50; }
 constexpr int kTbCols = 64;
 
-// One wave advances staged rows r0 .. r1 - 1 of one substep from P to Q
-// (lane = staged column), marching upward: each row's state is read once,
-// the G flux of the face below a row is carried to the next row and the F
-// flux of the face right of a lane reaches the lane to its right by DPP.
-// The arithmetic is the fused single-step kernel's, operation for
-// operation.  Rows r0 - 1 and r1 are read, not written; a row is stored
-// where `store_col` and the row lies in the domain (or the y axis is
-// periodic).  Wave-uniform: all 64 lanes call it together.
+// Lanes of one staged column, for the whole launch.
+struct TbCols {
+    bool store;    // a cell of the domain that this step advances
+    bool ghost_lo; // the reflective ghost left of x = 0, refreshed this step
+    bool ghost_hi; // the reflective ghost right of x = nx - 1
+};
+
+// One wave advances staged rows r0 .. r1 - 1 of one step in place (lane =
+// staged column), marching upward: each row's state is read once, the G
+// flux of the face below a row is carried to the next row and the F flux of
+// the face right of a lane reaches the lane to its right by DPP.  The
+// arithmetic is the fused single-step kernel's, operation for operation.
+// Rows r0 - 1 and r1 belong to the neighbouring waves' chunks; they were
+// read into E0 / E1 before the step's first barrier.  A new row is stored
+// where its column and row lie in the domain; at reflective walls the wave
+// also stores the mirror image into the ghost cell beside it (wall-normal
+// momentum negated), as the boundary rule does between single steps.
+// Wave-uniform: all 64 lanes call it together; `xwall` is uniform.
 template <typename T, int RX>
-__device__ __forceinline__ void tb_march(const T *const P[3], T *const Q[3], int r0, int r1, bool store_col, int y0,
-                                         int ny, bool pery, T k, T lx, T ly, T mx, T my) {
+__device__ __forceinline__ void tb_march(T *const B[3], const T E0[3], const T E1[3], int r0, int r1, TbCols c,
+                                         bool xwall, int y0, int ny, bool pery, T k, T lx, T ly, T mx, T my) {
     const int lane = threadIdx.x & 63;
     T S[3], Bp[3], Gd[3];
     auto load = [&](int r, T u[3]) {
         const int o = r * RX + lane;
-        u[0] = P[0][o];
-        u[1] = P[1][o];
-        u[2] = P[2][o];
+        u[0] = B[0][o];
+        u[1] = B[1][o];
+        u[2] = B[2][o];
     };
     auto row = [&](auto face_c, auto emit_c, const T U[3], bool want_x, int rout) {
         constexpr bool FACE = decltype(face_c)::value, EMIT = decltype(emit_c)::value;
@@ -59,10 +74,46 @@ __device__ __forceinline__ void tb_march(const T *const P[3], T *const Q[3], int
             yface_flux<T>(Bp[0] + fma(-ly, q, hh), Bp[1] + fma(-ly, fq, hp), Bp[2] + fma(-ly, gq, hq), k, f);
             if (EMIT) {
                 const int y = y0 + rout;
-                if (store_col && (pery || (y >= 0 && y < ny))) {
-                    const int o = rout * RX + lane;
+                if (pery || (y >= 0 && y < ny)) {
+                    T out[3];
 #pragma unroll
-                    for (int kk = 0; kk < 3; ++kk) Q[kk][o] = fma(-my, f[kk] - Gd[kk], S[kk]);
+                    for (int kk = 0; kk < 3; ++kk) out[kk] = fma(-my, f[kk] - Gd[kk], S[kk]);
+                    const int o = rout * RX + lane;
+                    if (c.store) {
+#pragma unroll
+                        for (int kk = 0; kk < 3; ++kk) B[kk][o] = out[kk];
+                    }
+                    if (xwall) {
+                        // both shifts by every lane (DPP reads the neighbour's register), then select
+                        T mn[3], mp[3];
+#pragma unroll
+                        for (int kk = 0; kk < 3; ++kk) {
+                            mn[kk] = from_next_lane(out[kk], out[kk]);
+                            mp[kk] = from_prev_lane(out[kk], out[kk]);
+                        }
+                        if (c.ghost_lo) {
+                            B[0][o] = mn[0];
+                            B[1][o] = -mn[1];
+                            B[2][o] = mn[2];
+                        }
+                        if (c.ghost_hi) {
+                            B[0][o] = mp[0];
+                            B[1][o] = -mp[1];
+                            B[2][o] = mp[2];
+                        }
+                    }
+                    if (!pery && c.store) {
+                        if (y == 0) {
+                            B[0][o - RX] = out[0];
+                            B[1][o - RX] = out[1];
+                            B[2][o - RX] = -out[2];
+                        }
+                        if (y == ny - 1) {
+                            B[0][o + RX] = out[0];
+                            B[1][o + RX] = out[1];
+                            B[2][o + RX] = -out[2];
+                        }
+                    }
                 }
             }
 #pragma unroll
@@ -85,25 +136,27 @@ __device__ __forceinline__ void tb_march(const T *const P[3], T *const Q[3], int
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk) S[kk] = fma(-mx, fr[kk] - from_prev_lane(fr[kk], fr[kk]), U[kk]);
     };
-    T A[3], B[3];
-    load(r0 - 1, A);
-    load(r0, B);
-    row(bconst<false>{}, bconst<false>{}, A, false, 0);
-    load(r0 + 1, A);
-    row(bconst<true>{}, bconst<false>{}, B, true, 0);
+    T U[3], N[3];
+    load(r0, U);
+    row(bconst<false>{}, bconst<false>{}, E0, false, 0);
+    if (r0 + 1 < r1) load(r0 + 1, N);
+    else N[0] = E1[0], N[1] = E1[1], N[2] = E1[2];
+    row(bconst<true>{}, bconst<false>{}, U, true, 0);
     for (int r = r0 + 1; r < r1; ++r) {
-        const T U[3] = {A[0], A[1], A[2]};       // row r
-        load(r + 1, A);
+        U[0] = N[0], U[1] = N[1], U[2] = N[2];            // row r
+        if (r + 1 < r1) load(r + 1, N);
+        else N[0] = E1[0], N[1] = E1[1], N[2] = E1[2];
         row(bconst<true>{}, bconst<true>{}, U, true, r - 1);
     }
-    row(bconst<true>{}, bconst<true>{}, A, false, r1 - 1);   // row r1 closes the chunk
+    row(bconst<true>{}, bconst<true>{}, N, false, r1 - 1);   // row r1 closes the chunk
 }
 
 template <typename T, int K, int NW>
 __global__ __launch_bounds__(64 * NW) void k_step_tb(SwLaunch a) {
     constexpr int RX = kTbCols, TX = RX - 2 * K;
-    constexpr int TY = tb_rows<T>(), RY = TY + 2 * K, RN = RX * RY;
-    __shared__ T buf[2][3][RN];
+    constexpr int RY = tb_staged_rows<T>(), TY = RY - 2 * K, RN = RX * RY;
+    __shared__ T buf[3][RN];
+    T *const Bf[3] = {buf[0], buf[1], buf[2]};
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: row loops run on scalars
     const int nx = a.nx, ny = a.ny;
@@ -130,6 +183,7 @@ __global__ __launch_bounds__(64 * NW) void k_step_tb(SwLaunch a) {
     }
     const bool col_in = perx || (x >= 0 && x < nx);
     const bool col_lo_wall = !perx && x == -1, col_hi_wall = !perx && x == nx;
+    const bool xwall = !perx && (gx0 < 0 || gx0 + RX > nx);            // uniform
     for (int r = wave; r < RY; r += NW) {
         int gy = gy0 + r;
         if (pery) {
@@ -141,11 +195,10 @@ __global__ __launch_bounds__(64 * NW) void k_step_tb(SwLaunch a) {
         const int64_t off = (int64_t)gy * pitch + gx;
         const int o = r * RX + lane;
 #pragma unroll
-        for (int f = 0; f < 3; ++f) buf[0][f][o] = I[f][off];
+        for (int f = 0; f < 3; ++f) buf[f][o] = I[f][off];
     }
     __syncthreads();
 
-    int cur = 0;
 #pragma unroll 1
     for (int s = 0; s < K; ++s) {
         // cells that can still be advanced: staged rows / columns [s + 1, R - 2 - s],
@@ -154,32 +207,21 @@ __global__ __launch_bounds__(64 * NW) void k_step_tb(SwLaunch a) {
         const bool col_live = lane >= lo && lane <= hx;
         const int chunk = (hy - lo + NW) / NW;
         const int r0 = lo + wave * chunk, r1 = min(r0 + chunk, hy + 1);
-        const T *P[3] = {buf[cur][0], buf[cur][1], buf[cur][2]};
-        T *Q[3] = {buf[cur ^ 1][0], buf[cur ^ 1][1], buf[cur ^ 1][2]};
-        if (r0 < r1) tb_march<T, RX>(P, Q, r0, r1, col_live && col_in, gy0, ny, pery, k, lx, ly, mx, my);
-        __syncthreads();
-        if (s + 1 < K && !(perx && pery)) {
-            // reflective ghost layer of the new state, where the next step reads it
-            for (int r = lo + wave; r <= hy; r += NW) {
-                const int y = gy0 + r;
-                const bool row_in = pery || (y >= 0 && y < ny);
-                const int o = r * RX + lane;
-                if (col_live && row_in && (col_lo_wall || col_hi_wall)) {
-                    const int src = o + (col_lo_wall ? 1 : -1);
-                    Q[0][o] = Q[0][src];
-                    Q[1][o] = -Q[1][src];
-                    Q[2][o] = Q[2][src];
-                }
-                if (col_live && col_in && !pery && (y == -1 || y == ny)) {
-                    const int src = o + (y == -1 ? RX : -RX);
-                    Q[0][o] = Q[0][src];
-                    Q[1][o] = Q[1][src];
-                    Q[2][o] = -Q[2][src];
-                }
+        const bool active = r0 < r1;
+        T E0[3], E1[3];
+        if (active) {
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk) {
+                E0[kk] = buf[kk][(r0 - 1) * RX + lane];
+                E1[kk] = buf[kk][r1 * RX + lane];
             }
-            __syncthreads();
         }
-        cur ^= 1;
+        __syncthreads();        // the neighbours' edge rows are read before anyone writes
+        if (active)
+            tb_march<T, RX>(Bf, E0, E1, r0, r1, TbCols{col_live && col_in, col_live && col_lo_wall,
+                                                       col_live && col_hi_wall},
+                            xwall, gy0, ny, pery, k, lx, ly, mx, my);
+        __syncthreads();
     }
 
     // the tile's own cells: U^{n+K}, their ghost images, the sticky flag
@@ -189,7 +231,7 @@ __global__ __launch_bounds__(64 * NW) void k_step_tb(SwLaunch a) {
         const int y = gy0 + r;
         if (!col_out || y >= ny) continue;
         const int o = r * RX + lane;
-        const U3<T> v = {buf[cur][0][o], buf[cur][1][o], buf[cur][2][o]};
+        const U3<T> v = {buf[0][o], buf[1][o], buf[2][o]};
         const int64_t off = (int64_t)y * pitch + x;
         O[0][off] = v.h;
         O[1][off] = v.p;
@@ -207,9 +249,10 @@ __global__ __launch_bounds__(64 * NW) void k_step_tb(SwLaunch a) {
 }
 
 template <typename T, int K> hipError_t launch_tb(const SwLaunch &a, int waves, hipStream_t s) {
-    constexpr int TX = kTbCols - 2 * K, TY = tb_rows<T>();
+    constexpr int TX = kTbCols - 2 * K, TY = tb_staged_rows<T>() - 2 * K;
     dim3 grid((a.nx + TX - 1) / TX, (a.ny + TY - 1) / TY);
     if (waves == 16) k_step_tb<T, K, 16><<<grid, 1024, 0, s>>>(a);
+    else if (waves == 12) k_step_tb<T, K, 12><<<grid, 768, 0, s>>>(a);
     else if (waves == 8) k_step_tb<T, K, 8><<<grid, 512, 0, s>>>(a);
     else k_step_tb<T, K, 4><<<grid, 256, 0, s>>>(a);
     return hipGetLastError();

@@ -7,7 +7,7 @@
 // trial and at the end, so tuning leaves the simulation where it was.  Every
 // fused shape produces bitwise identical cells, so the choice affects speed
 // only.  With a fixed dt the temporally blocked kernel (K steps per launch,
-// 4, 8 or 16 waves per tile) joins the candidates; it too reproduces the
+// 8, 12 or 16 waves per tile) joins the candidates; it too reproduces the
 // fused kernel's bits.  Results are cached in a text file, one line per key
 //   <arch>:<CUs>:<dtype>:<scheme>:<nx>x<ny>[:fixeddt] variant rows vec occupancy prefetch order us_per_step
 // (the suffix marks contexts with a fixed dt, whose choice may be a blocked
@@ -114,7 +114,7 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
                                 cands.push_back(sw_tuning{2, rows, vecs[vi], occ, pd, order});
         if (opts.dt_fixed > 0)   // temporal blocking: K steps per launch
             for (int k : {3, 5, 7})
-                for (int waves : {4, 8, 16})
+                for (int waves : {8, 12, 16})
                     if (sw_tb_supported((int)opts.dtype, k)) cands.push_back(sw_tuning{3, k, waves, 0, 0, 0});
     }
 

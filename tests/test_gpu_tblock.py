@@ -75,10 +75,10 @@ def test_blocked_matches_oracle(dtype, bc):
         assert_bitwise_fused(got, start, nsteps, dtype, bc[0], bc[1], dt)
 
 
-@pytest.mark.parametrize("waves", [4, 8, 16])
+@pytest.mark.parametrize("waves", [4, 8, 12, 16])
 @pytest.mark.parametrize("dtype,k", [("f32", 5), ("f32", 7), ("f64", 3)])
 def test_blocked_waves_per_tile(waves, dtype, k):
-    """Every split of a tile's rows over 4, 8 or 16 waves gives the same bits."""
+    """Every split of a tile's rows over 4, 8, 12 or 16 waves gives the same bits."""
     nx, ny = 333, 170
     h, _, _ = ics.bumps_state(nx, ny, seed=11, periodic=True, count=5)
     _, hu, hv = ics.random_state(nx, ny, seed=12, amp_h=0.0, amp_m=0.02)
@@ -86,6 +86,25 @@ def test_blocked_waves_per_tile(waves, dtype, k):
     for bc in ((sw.PERIODIC, sw.REFLECT), (sw.REFLECT, sw.PERIODIC)):
         got, start, _ = run_tb((h, hu, hv), 2 * k + 1, dtype, k, bc[0], bc[1], dt, waves=waves)
         assert_bitwise_fused(got, start, 2 * k + 1, dtype, bc[0], bc[1], dt)
+
+
+@pytest.mark.parametrize("dtype,k,waves", [("f32", 5, 16), ("f32", 3, 12), ("f64", 3, 8), ("f64", 5, 12)])
+def test_blocked_walls_at_tile_and_chunk_edges(dtype, k, waves):
+    """Grid sides one below, at and one above multiples of the tile's own
+    width (64 - 2K) and height (staged rows - 2K), so reflective walls and
+    their ghost cells fall on the first and last live lanes and on the rows
+    where one wave's chunk meets the next."""
+    tx = 64 - 2 * k
+    ty = (98 if dtype == "f32" else 50) - 2 * k
+    for nx, ny in ((2 * tx - 1, 2 * ty + 1), (2 * tx, 2 * ty), (2 * tx + 1, 2 * ty - 1), (tx + 3, ty - 3)):
+        h, _, _ = ics.bumps_state(nx, ny, seed=nx + ny, periodic=False, count=3)
+        _, hu, hv = ics.random_state(nx, ny, seed=nx * ny, amp_h=0.0, amp_m=0.02)
+        dt = fixed_dt(h)
+        for bc in ((sw.REFLECT, sw.REFLECT), (sw.PERIODIC, sw.REFLECT), (sw.REFLECT, sw.PERIODIC)):
+            got, start, _ = run_tb((h, hu, hv), 2 * k + 1, dtype, k, bc[0], bc[1], dt, waves=waves)
+            assert_bitwise_fused(got, start, 2 * k + 1, dtype, bc[0], bc[1], dt)
+        ref, _ = oracle_run(start, 2 * k + 1, dt, sw.REFLECT, sw.PERIODIC)
+        assert rel_maxnorm(got, ref) <= TOL[dtype], (nx, ny)
 
 
 @pytest.mark.parametrize("shape", [(1, 1), (1, 37), (37, 1), (2, 3), (5, 9), (64, 64), (65, 130), (257, 9)])
