@@ -167,6 +167,51 @@ def run_fixed_dt(steps, fused_tuning, sw, ics, torch, tune_cache):
     return out
 
 
+def run_comparison(steps, fused_tuning, sw, ics, torch):
+    """The paper's comparison designs (section "Performance Measurements") on
+    the headline workload: the fused kernel in the headline's tuned shape,
+    the unfused step (face states of the first half-step written to HBM and
+    read back by a second kernel) and the AoS step (one (h, hu, hv, 0)
+    vector per cell; each call converts the state in and out).  Per-step
+    times come from two calls of different length, so the per-call work
+    (prologue, AoS conversions) cancels.  All three final states must be
+    bitwise equal."""
+    name = "swe16384-f32-periodic"
+    n = WORKLOADS[name][0]
+    s = make_solver(name, sw, ics, torch)
+    ic = tuple(s.interior(k).clone() for k in range(3))
+
+    def restart():
+        s.state.cur = 0
+        s.set_state(*ic)
+        s.reset_time()
+
+    out = {"workload": name + "-paper-comparison", "dtype": "f32", "steps": steps}
+    finals = []
+    k_cal = steps // 5
+    for label, tuning in (("fused", fused_tuning), ("unfused", {"variant": 4}), ("aos", {"variant": 5})):
+        s.set_tuning(**tuning)
+        for k in (k_cal, steps):                   # graph capture (and workspace) outside the timed calls
+            restart()
+            s.step(k)
+        restart()
+        t_cal = timed(torch, lambda: s.step(k_cal))
+        restart()
+        t = timed(torch, lambda: s.step(steps))
+        s.sync_status()
+        finals.append([s.interior(k).clone() for k in range(3)])
+        per_step = (t - t_cal) / (steps - k_cal)
+        out[label] = {"tuning": s.get_tuning(), "gcells_per_s": n * n / per_step / 1e9,
+                      "ms_per_step": 1e3 * per_step, "ms_per_call": 1e3 * t}
+    for label in ("unfused", "aos"):
+        out[label]["ratio_to_fused"] = out[label]["gcells_per_s"] / out["fused"]["gcells_per_s"]
+    out["unfused_to_aos"] = out["unfused"]["gcells_per_s"] / out["aos"]["gcells_per_s"]
+    out["bitwise_equal"] = all(torch.equal(a, b) and torch.equal(a, c) for a, b, c in zip(*finals))
+    del s, ic, finals
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_batch(steps, sw, ics, torch, tune_cache, per_grid_steps):
     """Batched workload: 512 grids, sides 64*(1 + floor(16u)) (seed 4), each
     with its own 1-8 Gaussian bumps (seed 4000 + k), FP32, reflective walls.
@@ -316,6 +361,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 512-grid run")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate run")
+    ap.add_argument("--comparison-only", action="store_true",
+                    help="run only the paper-comparison record (fused against unfused and AoS steps)")
     ap.add_argument("--fixed-dt-only", action="store_true",
                     help="run only the fixed-dt comparison (fused single step against temporal blocking)")
     ap.add_argument("--surrogate-only", action="store_true",
@@ -349,6 +396,14 @@ def main():
         print(json.dumps(run_surrogate(sw, ics, torch)), flush=True)
         return
 
+    if args.comparison_only:
+        probe = make_solver("swe16384-f32-periodic", sw, ics, torch)
+        fused = probe.autotune(steps_per_trial=3, cache_path=args.tune_cache)   # the headline's shape
+        del probe
+        torch.cuda.empty_cache()
+        print(json.dumps(run_comparison(50, fused, sw, ics, torch)), flush=True)
+        return
+
     if args.fixed_dt_only:
         probe = make_solver("swe16384-f32-periodic", sw, ics, torch)
         fused = probe.autotune(steps_per_trial=3, cache_path=args.tune_cache)   # the headline's shape
@@ -378,6 +433,9 @@ def main():
             also.append({k: r[k] for k in ("workload", "dtype", "steps", "gcells_per_s", "ms_per_step",
                                             "kernel_us", "finite", "tuning")} |
                         {"hbm_frac": r["alg_bytes_per_launch"] / (r["kernel_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS})
+
+    if not args.no_also and args.workload == "swe16384-f32-periodic":
+        also.append(run_comparison(50, main_run["tuning"], sw, ics, torch))
 
     if not args.no_also and args.workload == "swe16384-f32-periodic":
         also.append(run_fixed_dt(210, main_run["tuning"], sw, ics, torch, args.tune_cache))

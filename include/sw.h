@@ -126,7 +126,8 @@ sw_status sw_fill_halo(sw_ctx *ctx, const sw_state *state, void *stream);
  * entry is ignored (it is refilled first).  A step that produces h <= 0 or a
  * non-finite value sets the context's sticky unstable flag (reported by
  * sw_sync_status); the run continues on garbage.
- * Errors (synchronous): SW_EINVAL, SW_EHIP. */
+ * Errors (synchronous): SW_EINVAL, SW_EHIP, SW_ENOMEM (workspace of
+ * variant 4 or 5), SW_ENOTSUP (a variant the options exclude). */
 sw_status sw_step(sw_ctx *ctx, sw_state *state, int32_t nsteps, void *stream);
 
 /* Synchronise the stream, then report the simulated time, the last dt and the
@@ -142,8 +143,17 @@ sw_status sw_reset_time(sw_ctx *ctx, void *stream);
  * row-marching kernel (paper scheme only), 3 = temporal blocking: K steps of
  * a tile and its K-cell halo per launch in LDS (paper scheme with a fixed dt
  * only; a CFL dt depends on every cell after each step; nsteps % K remaining
- * steps use the fused kernel).  Variants 2 and 3 give bitwise identical
- * states; the baseline agrees with them up to rounding order.
+ * steps use the fused kernel), 4 = unfused: the first half-step writes the
+ * face states to HBM and a second kernel reads them back (the array
+ * temporaries of the paper's generated code), 5 = AoS: the state packed as
+ * one (h, hu, hv, 0) vector per cell (the paper's hand-optimised kernel;
+ * each sw_step converts the current buffer in and the result back out).
+ * Variants 4 and 5 are comparison points for section "Performance
+ * Measurements" of the paper (paper scheme, either dt mode); the first
+ * sw_step that uses one allocates its workspace (six face planes of
+ * (ny + 1) * pitch elements, or two AoS copies of a buffer), kept until
+ * sw_destroy.  Variants 2-5 give bitwise identical states; the baseline
+ * agrees with them up to rounding order.
  * Errors: SW_EINVAL for an unknown variant; sw_step reports SW_ENOTSUP for a
  * variant the options exclude. */
 sw_status sw_set_variant(sw_ctx *ctx, int32_t variant);
@@ -154,8 +164,8 @@ sw_status sw_set_variant(sw_ctx *ctx, int32_t variant);
  * identical; the per-cell baseline agrees with them to rounding.  Blocked
  * defaults: K = 5 with 16 waves in SW_F32, with 8 waves in SW_F64. */
 typedef struct {
-    int32_t variant;    /* 0 auto, 1 per-cell baseline, 2 fused, 3 temporal blocking */
-    int32_t rows;       /* fused: rows per tile (>= 1); blocked: steps per launch K (3, 5; 7 in SW_F32) */
+    int32_t variant;    /* 0 auto, 1 per-cell baseline, 2 fused, 3 temporal blocking, 4 unfused, 5 AoS */
+    int32_t rows;       /* fused, AoS: rows per tile (>= 1); blocked: steps per launch K (3, 5; 7 in SW_F32) */
     int32_t vec;        /* fused: cells per lane; SW_F32: 1, 2 or 4, SW_F64: 1 or 2; blocked: waves per tile (4, 8, 12, 16) */
     int32_t occupancy;  /* fused: register budget in waves per SIMD: 0 (compiler's choice), 3 or 4 */
     int32_t prefetch;   /* fused: rows loaded ahead of the row being updated: 1, 2 or 3 */

@@ -33,6 +33,10 @@ struct sw_ctx {
         hipGraphExec_t exec;
     };
     std::vector<Graph> graphs;
+    // workspace of the comparison variants (face planes or AoS buffers),
+    // allocated by the first sw_step that needs it, freed by sw_destroy
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
 };
 
 namespace {
@@ -135,11 +139,52 @@ sw_status use_device(const sw_ctx *ctx) {
     return SW_OK;
 }
 
+// Workspace bytes of a step variant: six face planes (unfused) or two AoS
+// buffers of 4-vectors (AoS); none for the others.
+size_t workspace_bytes(const sw_ctx *ctx, int variant) {
+    const size_t eb = (size_t)ctx->layout.elem_bytes;
+    if (variant == 4) return 6 * (size_t)ctx->layout.pitch * ((size_t)ctx->grid.ny + 1) * eb;
+    if (variant == 5) return 2 * (size_t)ctx->layout.plane_elems * 4 * eb;
+    return 0;
+}
+
 // reset + prologue + nsteps step launches on stream s (no host sync)
 sw_status enqueue_steps(sw_ctx *ctx, const sw_state *state, int nsteps, const SwTuning &tun, hipStream_t s) {
     SW_HIP(sw_launch_reset(ctx->sc, 0, s));
     SW_HIP(sw_launch_prologue(launch_of(ctx, state, state->cur), s));
     int cur = state->cur, n = 0;
+    const size_t eb = (size_t)ctx->layout.elem_bytes;
+    if (tun.variant == 4) {
+        const size_t plane = (size_t)ctx->layout.pitch * ((size_t)ctx->grid.ny + 1) * eb;
+        SwFaces f;
+        for (int k = 0; k < 3; ++k) {
+            f.x[k] = (char *)ctx->ws + k * plane;
+            f.y[k] = (char *)ctx->ws + (3 + k) * plane;
+        }
+        f.pitch = ctx->layout.pitch;
+        for (; n < nsteps; ++n) {
+            SwLaunch b = launch_of(ctx, state, cur);
+            b.step = n;
+            SW_HIP(sw_launch_unfused(b, f, s));
+            cur ^= 1;
+        }
+        return SW_OK;
+    }
+    if (tun.variant == 5) {
+        const size_t vb = 4 * eb, buf = (size_t)ctx->layout.plane_elems * vb;
+        char *aos[2] = {(char *)ctx->ws, (char *)ctx->ws + buf};
+        const int64_t np = ctx->layout.plane_elems;
+        SW_HIP(sw_launch_aos_convert((int)ctx->opts.dtype, state->plane[cur], aos[0], np, true, s));
+        for (; n < nsteps; ++n) {
+            SwLaunch b = launch_of(ctx, state, cur);
+            b.step = n;
+            SW_HIP(sw_launch_aos_step(b, aos[n & 1] + ctx->layout.origin * vb, aos[(n + 1) & 1] + ctx->layout.origin * vb,
+                                      tun.rows, s));
+        }
+        SW_HIP(sw_launch_aos_convert((int)ctx->opts.dtype, state->plane[cur ^ (nsteps & 1)], aos[nsteps & 1], np,
+                                     false, s));
+        return SW_OK;
+    }
     if (tun.variant == 3) {   // K steps per launch (K odd: one buffer flip per launch, as K single steps)
         for (; n + tun.rows <= nsteps; n += tun.rows) {
             SwLaunch b = launch_of(ctx, state, cur);
@@ -282,6 +327,7 @@ sw_status sw_destroy(sw_ctx *ctx) {
     if (!ctx) return SW_OK;
     (void)use_device(ctx);
     drop_graphs(ctx);
+    if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     if (ctx->sc) (void)hipFree(ctx->sc);
     delete ctx;
@@ -298,10 +344,19 @@ namespace {
 // Resolve defaults; returns SW_OK or an error for unsupported settings.
 sw_status resolve_tuning(const sw_ctx *ctx, const sw_tuning &in, SwTuning *out) {
     int variant = in.variant;
-    if (variant < 0 || variant > 3) return fail(SW_EINVAL, "tuning: unknown variant %d", variant);
+    if (variant < 0 || variant > 5) return fail(SW_EINVAL, "tuning: unknown variant %d", variant);
     if (variant == 0) variant = ctx->opts.scheme == SW_SCHEME_PAPER ? 2 : 1;
-    if ((variant == 2 || variant == 3) && ctx->opts.scheme != SW_SCHEME_PAPER)
-        return fail(SW_ENOTSUP, "tuning: the fused and blocked kernels implement the paper scheme only");
+    if (variant >= 2 && ctx->opts.scheme != SW_SCHEME_PAPER)
+        return fail(SW_ENOTSUP, "tuning: the fused, blocked, unfused and AoS kernels implement the paper scheme only");
+    if (variant == 4) {
+        *out = SwTuning{4, 0, 0, 0, 0, 0};
+        return SW_OK;
+    }
+    if (variant == 5) {
+        if (in.rows < 0) return fail(SW_EINVAL, "tuning: rows = %d", in.rows);
+        *out = SwTuning{5, in.rows ? in.rows : 8, 1, 0, 0, 0};
+        return SW_OK;
+    }
     if (variant == 3) {
         if (!(ctx->opts.dt_fixed > 0))
             return fail(SW_ENOTSUP, "tuning: temporal blocking needs a fixed dt (a CFL dt depends on every cell)");
@@ -331,7 +386,7 @@ sw_status resolve_tuning(const sw_ctx *ctx, const sw_tuning &in, SwTuning *out) 
 
 sw_status sw_set_variant(sw_ctx *ctx, int32_t variant) {
     if (!ctx) return fail(SW_EINVAL, "set_variant: NULL context");
-    if (variant < 0 || variant > 3) return fail(SW_EINVAL, "set_variant: unknown variant %d", variant);
+    if (variant < 0 || variant > 5) return fail(SW_EINVAL, "set_variant: unknown variant %d", variant);
     sw_tuning t = ctx->tuning;
     t.variant = variant;
     SwTuning r;
@@ -379,6 +434,21 @@ sw_status sw_step(sw_ctx *ctx, sw_state *state, int32_t nsteps, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     SwTuning tun;
     if ((st = resolve_tuning(ctx, ctx->tuning, &tun)) != SW_OK) return st;
+    const size_t need = workspace_bytes(ctx, tun.variant);
+    if (need > ctx->ws_bytes) {            // before any capture: graphs hold the old address
+        drop_graphs(ctx);
+        SW_HIP(hipStreamSynchronize(s));
+        if (ctx->ws) SW_HIP(hipFree(ctx->ws));
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+        hipError_t e = hipMalloc(&ctx->ws, need);
+        if (e != hipSuccess) {
+            ctx->ws = nullptr;
+            return fail(e == hipErrorOutOfMemory ? SW_ENOMEM : SW_EHIP, "step: workspace of %zu bytes: %s", need,
+                        hipGetErrorString(e));
+        }
+        ctx->ws_bytes = need;
+    }
     if (!ctx->use_graph) {
         if ((st = enqueue_steps(ctx, state, nsteps, tun, s)) != SW_OK) return st;
     } else {

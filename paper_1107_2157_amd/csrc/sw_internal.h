@@ -43,7 +43,8 @@ hipError_t sw_launch_prologue(const SwLaunch &a, hipStream_t s);
 hipError_t sw_launch_fill_halo(const SwLaunch &a, hipStream_t s);
 // Tuning of a step launch.
 struct SwTuning {
-    int variant;     // 1 per-cell baseline, 2 fused, 3 temporal blocking (fixed dt; rows = steps per launch)
+    int variant;     // 1 per-cell baseline, 2 fused, 3 temporal blocking (fixed dt; rows = steps per launch),
+                     // 4 unfused (face states in HBM), 5 AoS (rows per tile)
     int rows;        // fused: rows per tile
     int vec;         // fused: cells per lane
     int minw;        // fused: register budget as waves per SIMD (0 = compiler's choice)
@@ -60,6 +61,24 @@ bool sw_tb_supported(int dtype, int k);
 hipError_t sw_launch_tb(const SwLaunch &a, int k, int waves, hipStream_t s);
 int sw_fused_default_vec(int dtype);
 bool sw_fused_supported(int dtype, int vec, int minw, int pd);
+
+// The paper's comparison designs (paper scheme only).  Unfused: face states
+// of the first half-step in HBM planes, x face i of row j at x[k][j * pitch
+// + i] (i = 0..nx), y face j of column i at y[k][j * pitch + i] (j = 0..ny);
+// each plane holds (ny + 1) * pitch elements.
+struct SwFaces {
+    void *x[3];
+    void *y[3];
+    int64_t pitch;
+};
+hipError_t sw_launch_unfused(const SwLaunch &a, const SwFaces &f, hipStream_t s);
+// AoS: whole planes (halo and padding included, n elements) converted
+// between the three SoA planes and one array of (h, hu, hv, 0) vectors; the
+// step reads and writes such arrays (`in`, `out` point at interior cell
+// (0, 0), same pitch as the planes).
+hipError_t sw_launch_aos_convert(int dtype, const void *const soa[3], void *aos, int64_t n, bool to_aos,
+                                 hipStream_t s);
+hipError_t sw_launch_aos_step(const SwLaunch &a, const void *in, void *out, int rows, hipStream_t s);
 
 // The instantiated launch shapes: (dtype, cells per lane, register budget,
 // prefetch depth).
