@@ -43,6 +43,11 @@ def _compile(src: str) -> str:
 
 
 def build(verbose: bool = False) -> str:
+    # the kernel generated from region expressions (wave_advance.rgn) first
+    sys.path.insert(0, ROOT)
+    from paper_1107_2157_amd import regions
+    if regions.write_generated() and verbose:
+        print(f"generated {regions.GENERATED}")
     os.makedirs(BUILD_DIR, exist_ok=True)
     srcs = sources()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:

@@ -170,6 +170,16 @@ sw_status enqueue_steps(sw_ctx *ctx, const sw_state *state, int nsteps, const Sw
         }
         return SW_OK;
     }
+    if (tun.variant == 6) {   // generated kernel; boundary values applied outside it, as in the paper
+        for (; n < nsteps; ++n) {
+            SwLaunch b = launch_of(ctx, state, cur);
+            b.step = n;
+            SW_HIP(sw_launch_rgn(b, s));
+            SW_HIP(sw_launch_fill_halo(launch_of(ctx, state, cur ^ 1), s));
+            cur ^= 1;
+        }
+        return SW_OK;
+    }
     if (tun.variant == 5) {
         const size_t vb = 4 * eb, buf = (size_t)ctx->layout.plane_elems * vb;
         char *aos[2] = {(char *)ctx->ws, (char *)ctx->ws + buf};
@@ -344,12 +354,12 @@ namespace {
 // Resolve defaults; returns SW_OK or an error for unsupported settings.
 sw_status resolve_tuning(const sw_ctx *ctx, const sw_tuning &in, SwTuning *out) {
     int variant = in.variant;
-    if (variant < 0 || variant > 5) return fail(SW_EINVAL, "tuning: unknown variant %d", variant);
+    if (variant < 0 || variant > 6) return fail(SW_EINVAL, "tuning: unknown variant %d", variant);
     if (variant == 0) variant = ctx->opts.scheme == SW_SCHEME_PAPER ? 2 : 1;
     if (variant >= 2 && ctx->opts.scheme != SW_SCHEME_PAPER)
-        return fail(SW_ENOTSUP, "tuning: the fused, blocked, unfused and AoS kernels implement the paper scheme only");
-    if (variant == 4) {
-        *out = SwTuning{4, 0, 0, 0, 0, 0};
+        return fail(SW_ENOTSUP, "tuning: the fused, blocked, unfused, AoS and generated kernels implement the paper scheme only");
+    if (variant == 4 || variant == 6) {
+        *out = SwTuning{variant, 0, 0, 0, 0, 0};
         return SW_OK;
     }
     if (variant == 5) {
@@ -386,7 +396,7 @@ sw_status resolve_tuning(const sw_ctx *ctx, const sw_tuning &in, SwTuning *out) 
 
 sw_status sw_set_variant(sw_ctx *ctx, int32_t variant) {
     if (!ctx) return fail(SW_EINVAL, "set_variant: NULL context");
-    if (variant < 0 || variant > 5) return fail(SW_EINVAL, "set_variant: unknown variant %d", variant);
+    if (variant < 0 || variant > 6) return fail(SW_EINVAL, "set_variant: unknown variant %d", variant);
     sw_tuning t = ctx->tuning;
     t.variant = variant;
     SwTuning r;

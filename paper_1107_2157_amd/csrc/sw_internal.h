@@ -44,7 +44,8 @@ hipError_t sw_launch_fill_halo(const SwLaunch &a, hipStream_t s);
 // Tuning of a step launch.
 struct SwTuning {
     int variant;     // 1 per-cell baseline, 2 fused, 3 temporal blocking (fixed dt; rows = steps per launch),
-                     // 4 unfused (face states in HBM), 5 AoS (rows per tile)
+                     // 4 unfused (face states in HBM), 5 AoS (rows per tile), 6 generated from
+                     // region expressions
     int rows;        // fused: rows per tile
     int vec;         // fused: cells per lane
     int minw;        // fused: register budget as waves per SIMD (0 = compiler's choice)
@@ -79,6 +80,9 @@ hipError_t sw_launch_unfused(const SwLaunch &a, const SwFaces &f, hipStream_t s)
 hipError_t sw_launch_aos_convert(int dtype, const void *const soa[3], void *aos, int64_t n, bool to_aos,
                                  hipStream_t s);
 hipError_t sw_launch_aos_step(const SwLaunch &a, const void *in, void *out, int rows, hipStream_t s);
+// The step generated from region expressions (wave_advance.rgn): new
+// interior of `out` and the CFL epilogue; the halo is filled separately.
+hipError_t sw_launch_rgn(const SwLaunch &a, hipStream_t s);
 
 // The instantiated launch shapes: (dtype, cells per lane, register budget,
 // prefetch depth).

@@ -1,0 +1,682 @@
+"""Region expressions: a small front end for the paper's data-parallel
+kernels, and a generator of one HIP tile kernel from them.
+
+The paper (sections "Region functions" and "Source-To-Source
+Transformations") writes a stencil kernel as whole-array statements over
+*regions*: ``region_cpy(A, halo)`` is the part of array ``A`` left after
+trimming ``halo = [left, right, down, up]`` elements from its four sides,
+``region_ptr(A, halo)`` the same part of an output array as a writable view.
+Elemental functions act element by element.  Arrays carry their halo in
+memory; global boundary values are applied outside the kernel.
+
+This module reads such a program (the ``.rgn`` language below), checks it,
+and emits a HIP kernel in the paper's generated design mapped onto gfx950:
+one thread per output element; every input array is copied with the halo
+its regions need into LDS by the thread block; array temporaries (face
+quantities) are evaluated over the part of their extent the block needs and
+kept in LDS; block barriers separate the phases; output views become one
+store per thread.  It also interprets the program with numpy (the
+whole-array semantics of the source), which gives the language its meaning
+independently of the generated code.
+
+The language, one statement per line (``#`` starts a comment)::
+
+    kernel NAME
+    scalar dt, dx, dy, g           # values the runtime passes in
+    in H, U, V                     # state arrays with a one-element halo
+    out oH, oU, oV                 # output arrays, same shape
+    elemental f(a, b) = EXPR       # inline function of scalars
+    west = [0, 1, 1, 1]            # a halo vector (may be reassigned)
+    Hx = EXPR                      # an array temporary; its extent is the expression's
+    pH = region_ptr(oH, interior)  # a writable view of an output array
+    pH = EXPR                      # stores into the view
+
+EXPR is built from numbers, scalars, ``region_cpy(ARRAY, HALO)``, calls of
+elemental functions, ``+ - * /``, unary minus, ``**2`` and parentheses.
+Every binary operation between arrays requires equal extents, so an
+off-by-one region is reported before any code exists.  Extents are kept
+symbolically as ``(nx + a, ny + b)``: the output views define ``nx x ny``.
+
+    python -m paper_1107_2157_amd.regions [--check]
+
+regenerates (or, with ``--check``, verifies) ``csrc/sw_rgn_wave_advance.hip``
+from ``wave_advance.rgn``.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import re
+import sys
+from dataclasses import dataclass, field
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PROGRAM = os.path.join(HERE, "wave_advance.rgn")
+GENERATED = os.path.join(HERE, "csrc", "sw_rgn_wave_advance.hip")
+
+
+class RegionError(ValueError):
+    """A program the front end rejects (syntax, unknown name, extent mismatch)."""
+
+
+# ---------------------------------------------------------------------------
+# Expressions
+
+@dataclass(frozen=True)
+class Num:
+    value: float
+
+
+@dataclass(frozen=True)
+class Sym:
+    name: str                      # a scalar or an elemental function's parameter
+
+
+@dataclass(frozen=True)
+class Region:
+    array: str
+    halo: tuple                    # (left, right, down, up), resolved when parsed
+
+
+@dataclass(frozen=True)
+class Neg:
+    a: object
+
+
+@dataclass(frozen=True)
+class Bin:
+    op: str
+    a: object
+    b: object
+
+
+@dataclass(frozen=True)
+class Square:
+    a: object
+
+
+@dataclass(frozen=True)
+class Call:
+    fn: str
+    args: tuple
+
+
+_TOKEN = re.compile(r"\s*(?:(\d+\.\d*(?:[eE][-+]?\d+)?|\.\d+(?:[eE][-+]?\d+)?|\d+(?:[eE][-+]?\d+)?)"
+                    r"|([A-Za-z_][A-Za-z_0-9]*)|(\*\*|[-+*/(),\[\]=]))")
+
+
+def tokenize(text: str, line: int):
+    pos, out = 0, []
+    text = text.rstrip()
+    while pos < len(text):
+        m = _TOKEN.match(text, pos)
+        if not m or m.end() == pos:
+            raise RegionError(f"line {line}: cannot read {text[pos:]!r}")
+        num, name, op = m.groups()
+        out.append(("num", num) if num else ("name", name) if name else ("op", op))
+        pos = m.end()
+    return out
+
+
+class _Parser:
+    def __init__(self, toks, line, prog):
+        self.toks, self.i, self.line, self.prog = toks, 0, line, prog
+
+    def peek(self):
+        return self.toks[self.i] if self.i < len(self.toks) else (None, None)
+
+    def take(self, kind=None, value=None):
+        k, v = self.peek()
+        if k is None or (kind and k != kind) or (value and v != value):
+            raise RegionError(f"line {self.line}: expected {value or kind}, found {v!r}")
+        self.i += 1
+        return v
+
+    def done(self):
+        if self.i != len(self.toks):
+            raise RegionError(f"line {self.line}: unexpected {self.toks[self.i][1]!r}")
+
+    def expr(self, params=()):
+        e = self.term(params)
+        while self.peek() in (("op", "+"), ("op", "-")):
+            op = self.take()
+            e = Bin(op, e, self.term(params))
+        return e
+
+    def term(self, params):
+        e = self.unary(params)
+        while self.peek() in (("op", "*"), ("op", "/")):
+            op = self.take()
+            e = Bin(op, e, self.unary(params))
+        return e
+
+    def unary(self, params):
+        if self.peek() == ("op", "-"):
+            self.take()
+            return Neg(self.unary(params))
+        e = self.atom(params)
+        if self.peek() == ("op", "**"):
+            self.take()
+            if self.take("num") != "2":
+                raise RegionError(f"line {self.line}: only **2 is supported")
+            e = Square(e)
+        return e
+
+    def atom(self, params):
+        k, v = self.peek()
+        if k == "num":
+            self.take()
+            return Num(float(v))
+        if (k, v) == ("op", "("):
+            self.take()
+            e = self.expr(params)
+            self.take("op", ")")
+            return e
+        name = self.take("name")
+        if name == "region_cpy":
+            arr, halo = self.region_args()
+            if arr not in self.prog.arrays:
+                raise RegionError(f"line {self.line}: region_cpy of unknown array {arr!r}")
+            if arr in self.prog.outputs:
+                raise RegionError(f"line {self.line}: region_cpy of output array {arr!r}")
+            if halo not in self.prog.halos:
+                raise RegionError(f"line {self.line}: unknown halo {halo!r}")
+            return Region(arr, self.prog.halos[halo])
+        if name == "region_ptr":
+            raise RegionError(f"line {self.line}: region_ptr may only start a view assignment")
+        if self.peek() == ("op", "("):
+            self.take()
+            args = [self.expr(params)]
+            while self.peek() == ("op", ","):
+                self.take()
+                args.append(self.expr(params))
+            self.take("op", ")")
+            if name not in self.prog.elementals:
+                raise RegionError(f"line {self.line}: unknown function {name!r}")
+            if len(args) != len(self.prog.elementals[name].params):
+                raise RegionError(f"line {self.line}: {name} takes {len(self.prog.elementals[name].params)} arguments")
+            return Call(name, tuple(args))
+        if name in params or name in self.prog.scalars:
+            return Sym(name)
+        if name in self.prog.arrays:
+            raise RegionError(f"line {self.line}: array {name!r} used without region_cpy")
+        raise RegionError(f"line {self.line}: unknown name {name!r}")
+
+    def region_args(self):
+        """(ARRAY, HALO) of region_cpy / region_ptr: both plain names."""
+        self.take("op", "(")
+        arr = self.take("name")
+        self.take("op", ",")
+        halo = self.take("name")
+        self.take("op", ")")
+        return arr, halo
+
+
+@dataclass
+class Elemental:
+    params: tuple
+    body: object
+
+
+@dataclass
+class Program:
+    name: str = ""
+    scalars: list = field(default_factory=list)
+    inputs: list = field(default_factory=list)
+    outputs: list = field(default_factory=list)
+    elementals: dict = field(default_factory=dict)
+    arrays: dict = field(default_factory=dict)      # name -> extent (a, b): (nx + a, ny + b)
+    temps: list = field(default_factory=list)       # [(name, expr)] in order
+    views: dict = field(default_factory=dict)       # view -> (output array, halo)
+    stores: list = field(default_factory=list)      # [(view, expr)]
+    halos: dict = field(default_factory=dict)
+
+
+def extent_of(prog: Program, e, line: int):
+    """Extent (a, b) of an array-valued expression (nx + a, ny + b), or None for a scalar."""
+    if isinstance(e, (Num, Sym)):
+        return None
+    if isinstance(e, Region):
+        a, b = prog.arrays[e.array]
+        l, r, d, u = e.halo
+        return (a - l - r, b - d - u)
+    if isinstance(e, (Neg, Square)):
+        return extent_of(prog, e.a, line)
+    if isinstance(e, Bin):
+        ea, eb = extent_of(prog, e.a, line), extent_of(prog, e.b, line)
+        if ea is not None and eb is not None and ea != eb:
+            raise RegionError(f"line {line}: extents differ: {fmt_extent(ea)} {e.op} {fmt_extent(eb)}")
+        return ea if ea is not None else eb
+    if isinstance(e, Call):
+        ext = None
+        for x in e.args:
+            ex = extent_of(prog, x, line)
+            if ex is not None and ext is not None and ex != ext:
+                raise RegionError(f"line {line}: arguments of {e.fn} differ in extent: "
+                                  f"{fmt_extent(ext)} and {fmt_extent(ex)}")
+            ext = ext if ext is not None else ex
+        return ext
+    raise TypeError(e)
+
+
+def fmt_extent(ext):
+    def one(n, a):
+        return n if a == 0 else f"{n}{a:+d}"
+    return f"({one('nx', ext[0])}, {one('ny', ext[1])})"
+
+
+def parse(text: str) -> Program:
+    prog = Program()
+    for ln, raw in enumerate(text.splitlines(), 1):
+        line = raw.split("#", 1)[0].strip()
+        if not line:
+            continue
+        head = line.split(None, 1)
+        if head[0] == "kernel":
+            prog.name = head[1].strip()
+            continue
+        if head[0] in ("scalar", "in", "out"):
+            names = [x.strip() for x in head[1].split(",")]
+            for n in names:
+                if not re.fullmatch(r"[A-Za-z_]\w*", n):
+                    raise RegionError(f"line {ln}: bad name {n!r}")
+                if n in prog.arrays or n in prog.scalars:
+                    raise RegionError(f"line {ln}: {n!r} declared twice")
+            if head[0] == "scalar":
+                prog.scalars += names
+            else:
+                (prog.inputs if head[0] == "in" else prog.outputs).extend(names)
+                for n in names:
+                    prog.arrays[n] = (2, 2)          # a one-element halo on every side
+            continue
+        if head[0] == "elemental":
+            m = re.fullmatch(r"elemental\s+([A-Za-z_]\w*)\s*\(([^)]*)\)\s*=\s*(.+)", line)
+            if not m:
+                raise RegionError(f"line {ln}: bad elemental definition")
+            fn, params = m.group(1), tuple(x.strip() for x in m.group(2).split(","))
+            p = _Parser(tokenize(m.group(3), ln), ln, prog)
+            body = p.expr(params)
+            p.done()
+            if extent_of(prog, body, ln) is not None:
+                raise RegionError(f"line {ln}: elemental {fn} must not read arrays")
+            prog.elementals[fn] = Elemental(params, body)
+            continue
+        toks = tokenize(line, ln)
+        if len(toks) < 3 or toks[0][0] != "name" or toks[1] != ("op", "="):
+            raise RegionError(f"line {ln}: expected an assignment")
+        target = toks[0][1]
+        rest = toks[2:]
+        if rest[0] == ("op", "["):                  # halo vector
+            vals, i = [], 1
+            while True:
+                sign = -1 if rest[i] == ("op", "-") else 1
+                i += sign < 0
+                if rest[i][0] != "num" or "." in rest[i][1]:
+                    raise RegionError(f"line {ln}: halo entries are integers")
+                vals.append(sign * int(rest[i][1]))
+                i += 1
+                if rest[i] == ("op", "]"):
+                    break
+                if rest[i] != ("op", ","):
+                    raise RegionError(f"line {ln}: bad halo vector")
+                i += 1
+            if len(vals) != 4 or min(vals) < 0 or i != len(rest) - 1:
+                raise RegionError(f"line {ln}: a halo is [left, right, down, up], non-negative")
+            prog.halos[target] = tuple(vals)
+            continue
+        if rest[0] == ("name", "region_ptr"):       # a view of an output array
+            p = _Parser(rest[1:], ln, prog)
+            arr, halo = p.region_args()
+            p.done()
+            if arr not in prog.outputs:
+                raise RegionError(f"line {ln}: region_ptr needs an output array, not {arr!r}")
+            if halo not in prog.halos:
+                raise RegionError(f"line {ln}: unknown halo {halo!r}")
+            if target in prog.views or target in prog.arrays:
+                raise RegionError(f"line {ln}: {target!r} already defined")
+            prog.views[target] = (arr, prog.halos[halo])
+            continue
+        p = _Parser(rest, ln, prog)
+        e = p.expr()
+        p.done()
+        ext = extent_of(prog, e, ln)
+        if target in prog.views:
+            arr, halo = prog.views[target]
+            a, b = prog.arrays[arr]
+            vext = (a - halo[0] - halo[1], b - halo[2] - halo[3])
+            if ext is not None and ext != vext:
+                raise RegionError(f"line {ln}: {target} has extent {fmt_extent(vext)}, "
+                                  f"the expression {fmt_extent(ext)}")
+            if any(v == target for v, _ in prog.stores):
+                raise RegionError(f"line {ln}: {target} stored twice")
+            prog.stores.append((target, e))
+            continue
+        if target in prog.arrays or target in prog.scalars:
+            raise RegionError(f"line {ln}: {target!r} already defined (temporaries are assigned once)")
+        if ext is None:
+            raise RegionError(f"line {ln}: {target} = a scalar expression; temporaries are arrays")
+        prog.arrays[target] = ext
+        prog.temps.append((target, e))
+    if not prog.stores:
+        raise RegionError("the program stores nothing")
+    exts = set()
+    for v, _ in prog.stores:
+        arr, halo = prog.views[v]
+        a, b = prog.arrays[arr]
+        exts.add((a - halo[0] - halo[1], b - halo[2] - halo[3]))
+    if exts != {(0, 0)}:
+        raise RegionError(f"the stored views must all have extent (nx, ny); found {sorted(exts)}")
+    return prog
+
+
+def load(path: str = PROGRAM) -> Program:
+    with open(path) as f:
+        return parse(f.read())
+
+
+# ---------------------------------------------------------------------------
+# Whole-array semantics (numpy): the meaning of a program.
+
+def interpret(prog: Program, arrays: dict, scalars: dict) -> dict:
+    """Evaluate the program on numpy arrays.  ``arrays`` maps every input
+    and output name to an array of shape (ny + 2, nx + 2) (rows = y); the
+    outputs' viewed parts are overwritten.  Returns ``arrays``."""
+    import numpy as np
+    vals = dict(arrays)
+
+    def region(name, halo):
+        a = vals[name]
+        l, r, d, u = halo
+        return a[d:a.shape[0] - u, l:a.shape[1] - r]
+
+    def ev(e, env):
+        if isinstance(e, Num):
+            return e.value
+        if isinstance(e, Sym):
+            return env[e.name] if e.name in env else scalars[e.name]
+        if isinstance(e, Region):
+            return region(e.array, e.halo)
+        if isinstance(e, Neg):
+            return -ev(e.a, env)
+        if isinstance(e, Square):
+            x = ev(e.a, env)
+            return x * x
+        if isinstance(e, Bin):
+            a, b = ev(e.a, env), ev(e.b, env)
+            return {"+": np.add, "-": np.subtract, "*": np.multiply, "/": np.divide}[e.op](a, b)
+        if isinstance(e, Call):
+            fn = prog.elementals[e.fn]
+            return ev(fn.body, dict(zip(fn.params, (ev(x, env) for x in e.args))))
+        raise TypeError(e)
+
+    for name, e in prog.temps:
+        vals[name] = np.array(ev(e, {}), dtype=np.float64)
+    for view, e in prog.stores:
+        arr, halo = prog.views[view]
+        region(arr, halo)[...] = ev(e, {})
+    return arrays
+
+
+# ---------------------------------------------------------------------------
+# Tile analysis and HIP generation.
+
+def reads(e, out=None):
+    """(array, (ox, oy)) pairs an expression reads: element k of the
+    expression reads element k + (left, down) of the array."""
+    out = [] if out is None else out
+    if isinstance(e, Region):
+        out.append((e.array, (e.halo[0], e.halo[2])))
+    elif isinstance(e, (Neg, Square)):
+        reads(e.a, out)
+    elif isinstance(e, Bin):
+        reads(e.a, out)
+        reads(e.b, out)
+    elif isinstance(e, Call):
+        for x in e.args:
+            reads(x, out)
+    return out
+
+
+def tile_ranges(prog: Program, tx: int, ty: int) -> dict:
+    """Per array, the box [x0, x1) x [y0, y1) of its elements a tile of
+    tx x ty output elements needs, relative to the tile's origin (element
+    k of every view of the tile is element k + view origin of its array)."""
+    need = {}
+
+    def add(name, box):
+        if name in need:
+            b = need[name]
+            need[name] = (min(b[0], box[0]), max(b[1], box[1]), min(b[2], box[2]), max(b[3], box[3]))
+        else:
+            need[name] = box
+
+    out_box = (0, tx, 0, ty)
+    for _, e in prog.stores:
+        for arr, (ox, oy) in reads(e):
+            add(arr, (ox, tx + ox, oy, ty + oy))
+    for name, e in reversed(prog.temps):
+        if name not in need:
+            continue                                  # a temporary no output reads
+        x0, x1, y0, y1 = need[name]
+        for arr, (ox, oy) in reads(e):
+            add(arr, (x0 + ox, x1 + ox, y0 + oy, y1 + oy))
+    return need, out_box
+
+
+def free_scalars(prog: Program, e, params, out=None) -> list:
+    """Program scalars an elemental body reads (passed to it as trailing arguments)."""
+    out = [] if out is None else out
+    if isinstance(e, Sym) and e.name not in params and e.name not in out:
+        out.append(e.name)
+    elif isinstance(e, (Neg, Square)):
+        free_scalars(prog, e.a, params, out)
+    elif isinstance(e, Bin):
+        free_scalars(prog, e.a, params, out)
+        free_scalars(prog, e.b, params, out)
+    elif isinstance(e, Call):
+        for x in e.args:
+            free_scalars(prog, x, params, out)
+        el = prog.elementals[e.fn]
+        for n in free_scalars(prog, el.body, el.params):
+            if n not in params and n not in out:
+                out.append(n)
+    return out
+
+
+def _c_num(v: float) -> str:
+    r = repr(float(v))
+    return f"T({r})"
+
+
+def _emit(e, at, prog, boxes, env=None) -> str:
+    """C expression of e at relative element `at` = (cx, cy) (C strings)."""
+    env = env or {}
+    if isinstance(e, Num):
+        return _c_num(e.value)
+    if isinstance(e, Sym):
+        return env.get(e.name, e.name)
+    if isinstance(e, Region):
+        x0, x1, y0, y1 = boxes[e.array]
+        ox, oy = e.halo[0], e.halo[2]
+        w = x1 - x0
+        return f"s_{e.array}[({at[1]} + {oy - y0}) * {w} + ({at[0]} + {ox - x0})]"
+    if isinstance(e, Neg):
+        return f"(-{_emit(e.a, at, prog, boxes, env)})"
+    if isinstance(e, Square):
+        return f"rgn_sq({_emit(e.a, at, prog, boxes, env)})"
+    if isinstance(e, Bin):
+        return f"({_emit(e.a, at, prog, boxes, env)} {e.op} {_emit(e.b, at, prog, boxes, env)})"
+    if isinstance(e, Call):
+        el = prog.elementals[e.fn]
+        args = [_emit(x, at, prog, boxes, env) for x in e.args]
+        args += [env.get(n, n) for n in free_scalars(prog, el.body, el.params)]
+        return f"rgn_{e.fn}({', '.join(args)})"
+    raise TypeError(e)
+
+
+def generate(prog: Program, tx: int = 64, ty: int = 8, source_name: str = "wave_advance.rgn") -> str:
+    """HIP source of the tile kernel for `prog` (tiles of tx x ty outputs,
+    one thread each).  The runtime around the translated statements (dt
+    from the device-side CFL ring, the signal-speed reduction and sticky
+    flag of the step epilogue) expects the outputs in the order h, hu, hv."""
+    if len(prog.inputs) != 3 or len(prog.outputs) != 3 or len(prog.stores) != 3:
+        raise RegionError("the generated step kernel takes three input and three output arrays")
+    boxes, _ = tile_ranges(prog, tx, ty)
+    nt = tx * ty
+    if nt % 64 or nt > 1024:
+        raise RegionError("tx * ty must be a multiple of 64, at most 1024")
+    order = {v: prog.outputs.index(prog.views[v][0]) for v, _ in prog.stores}
+    L = []
+    w = L.append
+    w(f"// Generated by paper_1107_2157_amd/regions.py from {source_name}; do not edit.")
+    w("//")
+    w(f"// Kernel `{prog.name}`: one thread per output element, tiles of {tx} x {ty};")
+    w("// inputs and array temporaries staged in LDS (element ranges per tile:")
+    for name in prog.inputs + [t for t, _ in prog.temps]:
+        if name in boxes:
+            x0, x1, y0, y1 = boxes[name]
+            w(f"//   {name}: x [{x0}, {x1}) y [{y0}, {y1}) of the tile origin, extent "
+              f"{fmt_extent(prog.arrays[name])})")
+    w("// Global boundary values are applied outside the kernel.")
+    w('#include "sw_common.h"')
+    w("")
+    w("using namespace sw;")
+    w("")
+    w("namespace {")
+    w("")
+    w("template <typename T> __device__ __forceinline__ T rgn_sq(T x) { return x * x; }")
+    for fn, el in prog.elementals.items():
+        args = ", ".join(f"T {p}" for p in list(el.params) + free_scalars(prog, el.body, el.params))
+        body = _emit(el.body, ("0", "0"), prog, boxes)
+        w(f"template <typename T> __device__ __forceinline__ T rgn_{fn}({args}) {{ return {body}; }}")
+    w("")
+    w(f"template <typename T>")
+    w(f"__global__ __launch_bounds__({nt}) void k_rgn_{prog.name}(SwLaunch a) {{")
+    w(f"    constexpr int TX = {tx}, TY = {ty}, NT = {nt};")
+    for name in prog.inputs + [t for t, _ in prog.temps]:
+        if name in boxes:
+            x0, x1, y0, y1 = boxes[name]
+            w(f"    __shared__ T s_{name}[{(x1 - x0) * (y1 - y0)}];")
+    w("    __shared__ double s_smax[NT / 64];")
+    w("    __shared__ int s_bad[NT / 64];")
+    w("    const int nx = a.nx, ny = a.ny;")
+    w("    const int64_t pitch = a.pitch;")
+    w("    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;")
+    w("    const double dt_ = step_dt(a);")
+    scal = {"dt": "(T)dt_", "dx": "(T)a.dx", "dy": "(T)a.dy", "g": "(T)a.g"}
+    for s in prog.scalars:
+        if s not in scal:
+            raise RegionError(f"scalar {s!r}: the runtime provides dt, dx, dy and g")
+        w(f"    const T {s} = {scal[s]};")
+    w("")
+    w("    // copy-in: element p of an input array is cell p - (1, 1); positions past")
+    w("    // the array (tiles at the high edges) are clamped and feed no stored element")
+    for k, name in enumerate(prog.inputs):
+        if name not in boxes:
+            continue
+        x0, x1, y0, y1 = boxes[name]
+        wd, ht = x1 - x0, y1 - y0
+        w(f"    for (int e = threadIdx.x; e < {wd * ht}; e += NT) {{")
+        w(f"        const int x = e % {wd}, y = e / {wd};")
+        w(f"        const int ci = min(i0 + {x0} + x, nx + 1) - 1, cj = min(j0 + {y0} + y, ny + 1) - 1;")
+        w(f"        s_{name}[e] = ((const T *)a.in[{k}])[(int64_t)cj * pitch + ci];")
+        w("    }")
+    w("    __syncthreads();")
+    # temporaries, by dependency level
+    level = {}
+    for name, e in prog.temps:
+        deps = [arr for arr, _ in reads(e) if arr in level]
+        level[name] = 1 + max((level[d] for d in deps), default=0)
+    for lv in sorted(set(level.values())):
+        w("")
+        w(f"    // array temporaries, level {lv}")
+        for name, e in prog.temps:
+            if level[name] != lv or name not in boxes:
+                continue
+            x0, x1, y0, y1 = boxes[name]
+            wd, ht = x1 - x0, y1 - y0
+            w(f"    for (int e = threadIdx.x; e < {wd * ht}; e += NT) {{")
+            w(f"        const int mx = e % {wd} + {x0}, my = e / {wd} + {y0};")
+            w(f"        s_{name}[e] = {_emit(e, ('mx', 'my'), prog, boxes)};")
+            w("    }")
+        w("    __syncthreads();")
+    w("")
+    w("    // output views: one element per thread")
+    w("    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;")
+    w("    const int i = i0 + tx, j = j0 + ty;")
+    w("    double smax = 0.0;")
+    w("    bool bad = false;")
+    w("    if (i < nx && j < ny) {")
+    outs = [None] * 3
+    for v, e in prog.stores:
+        outs[order[v]] = f"v_{v}"
+        w(f"        const T v_{v} = {_emit(e, ('tx', 'ty'), prog, boxes)};")
+    w("        const int64_t o = (int64_t)j * pitch + i;")
+    for k in range(3):
+        w(f"        ((T *)a.out[{k}])[o] = {outs[k]};")
+    w(f"        const T sp = signal_speed(U3<T>{{{outs[0]}, {outs[1]}, {outs[2]}}}, (T)a.g);")
+    w("        bad = !(sp <= finite_max<T>());")
+    w("        smax = (double)sp;")
+    w("    }")
+    w("    // step epilogue, once per block: max speed of the new state for the next dt")
+    w("    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;")
+    w("    smax = wave_max(smax);")
+    w("    const bool wbad = __ballot(bad) != 0;")
+    w("    if (lane == 0) {")
+    w("        s_smax[wave] = smax;")
+    w("        s_bad[wave] = wbad;")
+    w("    }")
+    w("    __syncthreads();")
+    w("    if (wave == 0) {")
+    w("        const double m = lane < NT / 64 ? s_smax[lane] : 0.0;")
+    w("        const bool b = lane < NT / 64 ? s_bad[lane] != 0 : false;")
+    w("        step_epilogue(a, m, b, dt_, blockIdx.x == 0 && blockIdx.y == 0,")
+    w("                      (int)(blockIdx.y * gridDim.x + blockIdx.x));")
+    w("    }")
+    w("}")
+    w("")
+    w("}  // namespace")
+    w("")
+    w("hipError_t sw_launch_rgn(const SwLaunch &a, hipStream_t s) {")
+    w("    if (a.scheme != 0) return hipErrorInvalidValue;")
+    w(f"    const dim3 grid((unsigned)((a.nx + {tx - 1}) / {tx}), (unsigned)((a.ny + {ty - 1}) / {ty}));")
+    w(f"    if (grid.y > 65535u) return hipErrorInvalidValue;")
+    w(f"    if (a.dtype == 0) k_rgn_{prog.name}<float><<<grid, {nt}, 0, s>>>(a);")
+    w(f"    else k_rgn_{prog.name}<double><<<grid, {nt}, 0, s>>>(a);")
+    w("    return hipGetLastError();")
+    w("}")
+    return "\n".join(L) + "\n"
+
+
+def write_generated() -> bool:
+    """Regenerate the kernel source from the program; write it only if it
+    changed.  Returns True if the file was written."""
+    src = generate(load(PROGRAM))
+    if os.path.exists(GENERATED):
+        with open(GENERATED) as f:
+            if f.read() == src:
+                return False
+    with open(GENERATED, "w") as f:
+        f.write(src)
+    return True
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--check", action="store_true", help="fail if the generated file is not up to date")
+    args = ap.parse_args(argv)
+    src = generate(load(PROGRAM))
+    if args.check:
+        with open(GENERATED) as f:
+            if f.read() != src:
+                print(f"{GENERATED} is out of date; run python -m paper_1107_2157_amd.regions", file=sys.stderr)
+                return 1
+        return 0
+    with open(GENERATED, "w") as f:
+        f.write(src)
+    print(f"wrote {GENERATED}")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

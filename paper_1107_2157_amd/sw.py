@@ -18,7 +18,7 @@ OK, EINVAL, ENOTSUP, ENOMEM, EHIP, EUNSTABLE = 0, -1, -2, -3, -4, -5
 F32, F64 = 0, 1
 REFLECT, PERIODIC = 0, 1
 SCHEME_PAPER, SCHEME_TRANSVERSE = 0, 1
-VARIANT_AUTO, VARIANT_CELL, VARIANT_FUSED, VARIANT_TBLOCK, VARIANT_UNFUSED, VARIANT_AOS = 0, 1, 2, 3, 4, 5
+VARIANT_AUTO, VARIANT_CELL, VARIANT_FUSED, VARIANT_TBLOCK, VARIANT_UNFUSED, VARIANT_AOS, VARIANT_GENERATED = range(7)
 
 _DT = {"f32": F32, "f64": F64, torch.float32: F32, torch.float64: F64}
 _TORCH_DT = {F32: torch.float32, F64: torch.float64}

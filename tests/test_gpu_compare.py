@@ -111,5 +111,5 @@ def test_refusals():
         f.set_tuning(variant=sw.VARIANT_AOS, rows=-1)
     assert e.value.status == sw.EINVAL
     with pytest.raises(sw.SwError) as e:
-        f.set_tuning(variant=6)
+        f.set_tuning(variant=7)
     assert e.value.status == sw.EINVAL

@@ -1,0 +1,73 @@
+"""The step kernel generated from region expressions (sw_step variant 6) on
+the GPU against the CPU FP64 oracle: ragged grids spanning several 64 x 8
+tiles, both boundary rules and their mix, CFL and fixed dt, degenerate
+shapes; and against the fused kernel, to rounding."""
+import math
+
+import pytest
+import torch
+
+import oracle
+from paper_1107_2157_amd import ics, sw
+from swtest import G, announce, rel_maxnorm
+
+pytestmark = pytest.mark.gpu
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def rounded(a, dtype):
+    t = torch.as_tensor(a, dtype=torch.float64)
+    return t.to(torch.float32).to(torch.float64) if dtype == "f32" else t
+
+
+def run(state, nsteps, dtype, bc, variant, dt_fixed=0.0):
+    h, hu, hv = (rounded(a, dtype) for a in state)
+    ny, nx = h.shape
+    announce(f"generated variant={variant} {dtype} {nx}x{ny} steps={nsteps} bc={bc} dt_fixed={dt_fixed}")
+    s = sw.Solver(nx, ny, g=G, dtype=dtype, bc_x=bc[0], bc_y=bc[1], cfl=0.0 if dt_fixed else 0.5,
+                  dt_fixed=dt_fixed, variant=variant)
+    s.set_state(h, hu, hv)
+    s.step(nsteps)
+    t, _, steps = s.sync_status()
+    assert steps == nsteps
+    return s.get_state(halo=True), (h, hu, hv), t
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("bc", [(sw.REFLECT, sw.REFLECT), (sw.PERIODIC, sw.PERIODIC), (sw.REFLECT, sw.PERIODIC),
+                                (sw.PERIODIC, sw.REFLECT)])
+@pytest.mark.parametrize("fixed", [False, True])
+def test_generated_matches_oracle(dtype, bc, fixed):
+    nx, ny = 301, 203
+    h, _, _ = ics.bumps_state(nx, ny, seed=41, periodic=False, count=4)
+    _, hu, hv = ics.random_state(nx, ny, seed=43, amp_h=0.0, amp_m=0.02)
+    dt = 0.5 / math.sqrt(G * float(h.max())) * 0.9 if fixed else 0.0
+    got, start, t = run((h, hu, hv), 100, dtype, bc, sw.VARIANT_GENERATED, dt)
+    H, U, V, t_ref = oracle.run(*(a.numpy() for a in start), 100, g=G, cfl=0.0 if fixed else 0.5, dt_fixed=dt,
+                                bcx=bc[0], bcy=bc[1])
+    err = rel_maxnorm([x[1:-1, 1:-1] for x in got], (H[1:-1, 1:-1], U[1:-1, 1:-1], V[1:-1, 1:-1]))
+    print(f"{dtype} bc={bc} fixed={fixed}: {err:.3e}")
+    assert err <= TOL[dtype]
+    assert abs(t - t_ref) <= (1e-12 if dtype == "f64" else 1e-5) * t_ref
+    # the halo of the result holds the boundary values of the new state
+    herr = rel_maxnorm(got, (H, U, V))
+    assert herr <= TOL[dtype]
+    fused, _, _ = run((h, hu, hv), 100, dtype, bc, sw.VARIANT_FUSED, dt)
+    assert rel_maxnorm(got, fused) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 9), (9, 1), (63, 7), (64, 8), (65, 9), (130, 17)])
+@pytest.mark.parametrize("bc", [sw.REFLECT, sw.PERIODIC])
+def test_generated_edge_shapes(shape, bc):
+    nx, ny = shape
+    st = ics.random_state(nx, ny, seed=nx * 13 + ny, amp_h=0.2, amp_m=0.05)
+    got, start, _ = run(st, 9, "f64", (bc, bc), sw.VARIANT_GENERATED)
+    H, U, V, _ = oracle.run(*(a.numpy() for a in start), 9, g=G, cfl=0.5, bcx=bc, bcy=bc)
+    assert rel_maxnorm(got, (H, U, V)) <= TOL["f64"], shape
+
+
+def test_generated_refused_for_the_transverse_scheme():
+    s = sw.Solver(32, 16, dtype="f32", scheme=sw.SCHEME_TRANSVERSE)
+    with pytest.raises(sw.SwError) as e:
+        s.set_tuning(variant=sw.VARIANT_GENERATED)
+    assert e.value.status == sw.ENOTSUP

@@ -1,0 +1,128 @@
+"""The region-expression front end on the CPU: the shipped program parses
+with the extents the paper's face arithmetic implies, the committed kernel
+is what the generator emits, the per-tile element ranges are those of a
+one-cell stencil, the program's whole-array meaning (numpy interpretation)
+is the oracle's step, and malformed programs are rejected with a reason."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1107_2157_amd import ics, regions
+
+G = 9.8
+
+
+def program_text():
+    with open(regions.PROGRAM) as f:
+        return f.read()
+
+
+def test_extents_of_the_shipped_program():
+    p = regions.load()
+    assert p.inputs == ["H", "U", "V"] and p.outputs == ["oH", "oU", "oV"]
+    for t in ("Hx", "Ux", "Vx"):
+        assert p.arrays[t] == (1, 0)          # (nx + 1) x ny x faces
+    for t in ("Hy", "Uy", "Vy"):
+        assert p.arrays[t] == (0, 1)          # nx x (ny + 1) y faces
+    assert [v for v, _ in p.stores] == ["pH", "pU", "pV"]
+    assert p.views["pH"] == ("oH", (1, 1, 1, 1))
+    assert set(p.elementals) == {"fu", "fv", "gv", "half"}
+
+
+def test_generated_kernel_is_up_to_date():
+    assert regions.main(["--check"]) == 0
+
+
+def test_tile_ranges_one_cell_stencil():
+    boxes, out = regions.tile_ranges(regions.load(), 64, 8)
+    assert out == (0, 64, 0, 8)
+    for a in ("H", "U", "V"):
+        assert boxes[a] == (0, 66, 0, 10)     # the tile plus one halo element on each side
+    for t in ("Hx", "Ux", "Vx"):
+        assert boxes[t] == (0, 65, 0, 8)      # 65 faces per row of 64 cells
+    for t in ("Hy", "Uy", "Vy"):
+        assert boxes[t] == (0, 64, 0, 9)
+
+
+@pytest.mark.parametrize("bc", [(oracle.REFLECT, oracle.REFLECT), (oracle.PERIODIC, oracle.PERIODIC),
+                                (oracle.REFLECT, oracle.PERIODIC)])
+def test_interpretation_is_the_oracle_step(bc):
+    """Run the program's statements as whole-array operations on halo arrays
+    and compare with the oracle's step on the same state and dt."""
+    nx, ny = 37, 23
+    h, _, _ = ics.bumps_state(nx, ny, seed=5, periodic=False, count=2)
+    _, hu, hv = ics.random_state(nx, ny, seed=6, amp_h=0.0, amp_m=0.03)
+    H, U, V = (oracle.with_halo(np.asarray(a, dtype=np.float64)) for a in (h, hu, hv))
+    oracle.fill_halo(H, U, V, bcx=bc[0], bcy=bc[1])
+    dt = 0.4 / (np.sqrt(G * H.max()) + 0.1)
+    rH, rU, rV = oracle.step(H, U, V, G, 1.0, 1.0, dt)
+    outs = {k: np.zeros_like(H) for k in ("oH", "oU", "oV")}
+    regions.interpret(regions.load(), {"H": H, "U": U, "V": V, **outs}, {"dt": dt, "dx": 1.0, "dy": 1.0, "g": G})
+    for got, ref in zip((outs["oH"], outs["oU"], outs["oV"]), (rH, rU, rV)):
+        scale = max(np.abs(ref[1:-1, 1:-1]).max(), 1e-3)
+        assert np.abs(got[1:-1, 1:-1] - ref[1:-1, 1:-1]).max() <= 1e-13 * scale
+    assert np.all(outs["oH"][0, :] == 0) and np.all(outs["oH"][:, 0] == 0)   # the view is the interior only
+
+
+def test_interpretation_catches_a_planted_sign_error():
+    """The comparison above is sensitive: flipping the sign of the flux
+    difference in the half-step moves the result far from the oracle."""
+    text = program_text().replace("0.5*(a + b) - c*(fb - fa)", "0.5*(a + b) + c*(fb - fa)")
+    nx, ny = 16, 12
+    h, hu, hv = ics.random_state(nx, ny, seed=8, amp_h=0.2, amp_m=0.05)
+    H, U, V = (oracle.with_halo(np.asarray(a, dtype=np.float64)) for a in (h, hu, hv))
+    oracle.fill_halo(H, U, V)
+    rH, _, _ = oracle.step(H, U, V, G, 1.0, 1.0, 0.05)
+    outs = {k: np.zeros_like(H) for k in ("oH", "oU", "oV")}
+    regions.interpret(regions.parse(text), {"H": H, "U": U, "V": V, **outs},
+                      {"dt": 0.05, "dx": 1.0, "dy": 1.0, "g": G})
+    assert np.abs(outs["oH"][1:-1, 1:-1] - rH[1:-1, 1:-1]).max() > 1e-6
+
+
+HEAD = """kernel k
+scalar dt, dx, dy, g
+in H, U, V
+out oH, oU, oV
+interior = [1, 1, 1, 1]
+lo = [0, 1, 1, 1]
+hi = [1, 0, 1, 1]
+"""
+TAIL = """pH = region_ptr(oH, interior)
+pU = region_ptr(oU, interior)
+pV = region_ptr(oV, interior)
+pH = region_cpy(H, interior)
+pU = region_cpy(U, interior)
+pV = region_cpy(V, interior)
+"""
+
+
+@pytest.mark.parametrize("body,msg", [
+    ("Hx = region_cpy(H, lo) + region_cpy(H, interior)\n", "extents differ"),       # an off-by-one region
+    ("Hx = region_cpy(Q, lo)\n", "unknown array"),
+    ("Hx = region_cpy(H, nowhere)\n", "unknown halo"),
+    ("Hx = region_cpy(H, lo)\nHx = region_cpy(H, hi)\n", "assigned once"),
+    ("Hx = region_cpy(oH, lo)\n", "output array"),
+    ("Hx = H + 1\n", "without region_cpy"),
+    ("Hx = 2*dt\n", "temporaries are arrays"),
+    ("Hx = f(region_cpy(H, lo))\n", "unknown function"),
+    ("bad = [1, 1, 1]\n", "left, right, down, up"),
+    ("Hx = region_cpy(H, lo)**3\n", r"only \*\*2"),
+])
+def test_rejected_programs(body, msg):
+    with pytest.raises(regions.RegionError, match=msg):
+        regions.parse(HEAD + body + TAIL)
+
+
+def test_rejected_store_extent_and_missing_store():
+    with pytest.raises(regions.RegionError, match="extent"):
+        regions.parse(HEAD + TAIL.replace("pU = region_cpy(U, interior)", "pU = region_cpy(U, lo)"))
+    with pytest.raises(regions.RegionError, match="stores nothing"):
+        regions.parse(HEAD)
+    with pytest.raises(regions.RegionError, match="stored twice"):
+        regions.parse(HEAD + TAIL + "pH = region_cpy(H, interior)\n")
+
+
+def test_elemental_scalars_become_arguments():
+    src = regions.generate(regions.load())
+    assert "rgn_fu(T h, T u, T g)" in src and "rgn_half(T a, T b, T fa, T fb, T c)" in src
+    assert "__syncthreads();" in src and "__shared__ T s_Hx[520];" in src
