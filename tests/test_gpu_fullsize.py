@@ -215,3 +215,61 @@ def test_surrogate_full_config_sampled_pixels():
             scale_ref = max(scale_ref, float(np.max(np.abs(want))))
     print(f"{len(errs)} pixels: max abs err {max(errs):.2e} (scale {scale_ref:.2e})")
     assert max(errs) <= 1e-2 * scale_ref
+
+
+def cached_tuning(key_tail):
+    """The committed cache's launch shape for this GPU and `key_tail`."""
+    p = torch.cuda.get_device_properties(0)
+    key = f"{p.gcnArchName.split(':')[0]}:{p.multi_processor_count}:{key_tail}"
+    best = None
+    with open(CACHE) as f:
+        for line in f:
+            parts = line.split()
+            if parts and parts[0] == key:
+                best = dict(zip(("variant", "rows", "vec", "occupancy", "prefetch", "order"), map(int, parts[1:7])))
+    return best
+
+
+def test_full_size_blocked_and_comparison_variants():
+    """The step variants bench.py times beside the headline, at 16384^2 FP32
+    periodic with a fixed dt: the autotuner's fixed-dt choice (temporal
+    blocking, K = 5), the fused kernel in the headline's tuned shape and the
+    unfused and AoS steps give bitwise the same state after 12 steps (two
+    blocked launches and two single steps); the kernel generated from region
+    expressions matches oracle patches at sampled cells."""
+    n, seed, k = 16384, ics.SEED_BUMPS_16384, 12
+    announce(f"full size {n}^2 f32 periodic, fixed dt: blocked / fused / unfused / AoS / generated, {k} steps")
+    st = ics.bumps_state(n, n, seed=seed, periodic=True, count=8, device="cuda")
+    dt = 0.5 / math.sqrt(G * float(st[0].max()))
+    s = solver_at(n, "f32", sw.PERIODIC, st, dt_fixed=dt)
+    assert s.get_tuning()["variant"] == sw.VARIANT_TBLOCK
+    s.step(k)
+    first = [s.interior(i).clone() for i in range(3)]
+    fused = cached_tuning(f"f32:0:{n}x{n}")
+    assert fused and fused["variant"] == sw.VARIANT_FUSED
+    for tun in (fused, {"variant": sw.VARIANT_UNFUSED}, {"variant": sw.VARIANT_AOS}):
+        announce(f"full size variant {tun}")
+        s.set_tuning(**tun)
+        s.state.cur = 0
+        s.set_state(*st)
+        s.reset_time()
+        s.step(k)
+        assert all(torch.equal(s.interior(i), first[i]) for i in range(3)), tun
+    del first
+    s.set_tuning(variant=sw.VARIANT_GENERATED)
+    s.state.cur = 0
+    s.set_state(*st)
+    s.reset_time()
+    s.step(k)
+    t, _, steps = s.sync_status()
+    assert steps == k and abs(t - k * dt) <= 1e-12 * k * dt
+    cells = sample_cells(n, n, np.random.default_rng(seed + 1), count=32, tile_rows=8, tile_cols=64,
+                         bumps=ics.draw_bumps(seed, n, n, count=8))
+    got = gpu_cells(s, cells)
+    ref0 = rounded_state(st, "f32")
+    del s, st
+    torch.cuda.empty_cache()
+    refs = [patch_reference(ref0, x, y, k, dt, True) for x, y in cells]
+    ref = [np.array([r[f] for r in refs]) for f in range(3)]
+    err = compare(got, ref, "f32")
+    print(f"generated kernel: {len(cells)} sampled cells, rel max-norm {err:.2e}")
