@@ -219,6 +219,39 @@ def run_comparison(steps, fused_tuning, sw, ics, torch):
     return out
 
 
+# Table 1 of the paper: ms per time step of its generated OpenCL kernel (work-group 16 x 8) on a
+# Tesla C2050, FP32, mean over 100 iterations of the time loop.  Context only (other hardware).
+PAPER_TABLE1_GPU_MS = {16: 0.017, 32: 0.02, 64: 0.02, 128: 0.036, 256: 0.092, 512: 0.32, 1024: 1.22,
+                       1280: 1.89, 2048: 4.82, 4096: 19.29}
+
+
+def run_table1(sw, ics, torch, steps=100):
+    """The widths of the paper's Table 1, FP32, reflective walls, CFL 0.5,
+    8 Gaussian bumps (the paper does not state its initial state): one
+    sw_step(100) call (one graph launch) per width, timed whole, as the
+    paper averaged 100 iterations of its time loop; the fused kernel in its
+    default launch shape."""
+    rows = []
+    for n, paper_ms in PAPER_TABLE1_GPU_MS.items():
+        s = sw.Solver(n, n, dtype="f32")
+        st = ics.bumps_state(n, n, seed=ics.SEED_BUMPS_4096, periodic=False, count=8, device="cuda")
+        for _ in range(2):                         # graph capture for both buffers, warm
+            s.state.cur = 0
+            s.set_state(*st)
+            s.step(steps)
+        s.state.cur = 0
+        s.set_state(*st)
+        s.reset_time()
+        t = timed(torch, lambda: s.step(steps))
+        s.sync_status()
+        ms = 1e3 * t / steps
+        rows.append({"width": n, "ms_per_step": ms, "gcells_per_s": n * n / (ms * 1e-3) / 1e9,
+                     "paper_c2050_ms": paper_ms, "ratio_to_paper": paper_ms / ms})
+        del s, st
+    torch.cuda.empty_cache()
+    return {"workload": "table1-widths-f32-reflect", "steps_per_call": steps, "rows": rows}
+
+
 def run_batch(steps, sw, ics, torch, tune_cache, per_grid_steps):
     """Batched workload: 512 grids, sides 64*(1 + floor(16u)) (seed 4), each
     with its own 1-8 Gaussian bumps (seed 4000 + k), FP32, reflective walls.
@@ -435,7 +468,7 @@ def main():
 
     also = []
     if not args.no_also and args.workload == "swe16384-f32-periodic":
-        for name in ("swe4096-f32-reflect", "swe4096-f64-reflect"):
+        for name in ("swe4096-f32-reflect", "swe4096-f64-reflect", "dam128-f64"):
             r = run_workload(name, WORKLOADS[name][4], args.warmup, sw, ics, torch, args.tune_cache)
             also.append({k: r[k] for k in ("workload", "dtype", "steps", "gcells_per_s", "ms_per_step",
                                             "kernel_us", "finite", "tuning")} |
@@ -450,8 +483,12 @@ def main():
     if not args.no_also and not args.no_batch and args.workload == "swe16384-f32-periodic":
         also.append(run_batch(500, sw, ics, torch, args.tune_cache, per_grid_steps=50))
 
+    if not args.no_also and args.workload == "swe16384-f32-periodic":
+        also.append(run_table1(sw, ics, torch))
+
     if not args.no_also and not args.no_surrogate and args.workload == "swe16384-f32-periodic":
         also.append(run_surrogate(sw, ics, torch))
+        also.append(run_surrogate(sw, ics, torch, n=1))      # batch 1: the launch-bound end
 
     line = {
         "metric": METRIC,

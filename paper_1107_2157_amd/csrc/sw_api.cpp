@@ -206,7 +206,7 @@ sw_status enqueue_steps(sw_ctx *ctx, const sw_state *state, int nsteps, const Sw
     SwTuning single = tun;    // the remaining steps: the fused kernel in its default shape
     if (tun.variant == 3) {
         single.variant = 2;
-        single.vec = sw_fused_default_vec((int)ctx->opts.dtype);
+        single.vec = sw_fused_default_vec((int)ctx->opts.dtype, ctx->grid.nx);
         single.rows = sw_fused_default_rows(ctx->grid.nx, ctx->grid.ny, single.vec);
         single.minw = 0;
         single.pd = 2;
@@ -380,7 +380,7 @@ sw_status resolve_tuning(const sw_ctx *ctx, const sw_tuning &in, SwTuning *out) 
         return SW_OK;
     }
     out->variant = variant;
-    out->vec = in.vec ? in.vec : sw_fused_default_vec((int)ctx->opts.dtype);
+    out->vec = in.vec ? in.vec : sw_fused_default_vec((int)ctx->opts.dtype, ctx->grid.nx);
     out->rows = in.rows ? in.rows : sw_fused_default_rows(ctx->grid.nx, ctx->grid.ny, out->vec);
     out->minw = in.occupancy;
     out->pd = in.prefetch ? in.prefetch : 2;
@@ -522,3 +522,7 @@ sw_status sw_reset_time(sw_ctx *ctx, void *stream) {
 }  // extern "C"
 
 bool sw_ctx_use_graph(const sw_ctx *ctx) { return ctx && ctx->use_graph; }
+
+void sw_ctx_drop_graphs(sw_ctx *ctx) {
+    if (ctx) drop_graphs(ctx);
+}

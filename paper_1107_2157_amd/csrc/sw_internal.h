@@ -60,7 +60,7 @@ int sw_fused_default_rows(int nx, int ny, int vec);
 bool sw_tb_supported(int dtype, int k);
 // waves per block: 4, 8, 12 or 16 (the tile is the same; each wave marches one chunk of its rows).
 hipError_t sw_launch_tb(const SwLaunch &a, int k, int waves, hipStream_t s);
-int sw_fused_default_vec(int dtype);
+int sw_fused_default_vec(int dtype, int nx);
 bool sw_fused_supported(int dtype, int vec, int minw, int pd);
 
 // The paper's comparison designs (paper scheme only).  Unfused: face states

@@ -1,8 +1,9 @@
 // Autotuner of the step kernel's launch shape.
 //
-// Candidates (fused kernel): cells per lane x register budget x rows per
-// tile.  Each candidate is timed with HIP events on the caller's stream over
-// a few steps of the caller's own state; the state (buf[cur] with its halo)
+// Candidates (fused kernel): cells per lane x register budget x prefetch
+// depth x rows per tile x tile order.  Each candidate is timed with HIP
+// events on the caller's stream over a few steps of the caller's own state,
+// as replays of sw_step's graphs; the state (buf[cur] with its halo)
 // and the context's time scalars are saved first and restored before every
 // trial and at the end, so tuning leaves the simulation where it was.  Every
 // fused shape produces bitwise identical cells, so the choice affects speed
@@ -75,6 +76,7 @@ sw_status sw_ctx_describe(const sw_ctx *ctx, sw_grid *grid, sw_opts *opts, sw_la
                           size_t *scalars_bytes);
 
 bool sw_ctx_use_graph(const sw_ctx *ctx);
+void sw_ctx_drop_graphs(sw_ctx *ctx);   // the context's captured graphs (none may be in flight)
 
 extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per_trial, const char *cache_path,
                                  void *stream, sw_tuning *best_out) {
@@ -101,11 +103,12 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
     if (opts.scheme != SW_SCHEME_PAPER) {
         cands.push_back(sw_tuning{1, 0, 0, 0, 0, 0});
     } else {
-        const int vecs_f32[] = {2, 4}, vecs_f64[] = {1, 2};
+        const int vecs_f32[] = {1, 2, 4}, vecs_f64[] = {1, 2};
         const int *vecs = opts.dtype == SW_F64 ? vecs_f64 : vecs_f32;
-        const int rows_list[] = {8, 16, 32, 64, 128};
+        const int nvec = opts.dtype == SW_F64 ? 2 : 3;
+        const int rows_list[] = {2, 4, 8, 16, 32, 64, 128};
         const int occs[] = {0, 3, 4};
-        for (int vi = 0; vi < 2; ++vi)
+        for (int vi = 0; vi < nvec; ++vi)
             for (int occ : occs)
                 for (int pd = 1; pd <= 3; ++pd)
                     if (sw_fused_supported((int)opts.dtype, vecs[vi], occ, pd))
@@ -147,9 +150,11 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
 
     sw_tuning prev{};
     sw_get_tuning(ctx, &prev);
-    // trials launch eagerly: a first graph call of a shape would time its capture
+    // trials replay graphs, as sw_step runs: eager launches would time the
+    // host's launch rate on small grids; each shape's two call lengths are
+    // captured in an untimed warm-up first
     const bool graph = sw_ctx_use_graph(ctx);
-    sw_set_graph(ctx, 0);
+    sw_set_graph(ctx, 1);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     double best_us = 1e300;
     hipError_t he = hipEventCreate(&e0);
@@ -157,8 +162,15 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
     if (he == hipSuccess) he = save();
     for (size_t i = 0; i < cands.size() && he == hipSuccess; ++i) {
         if (sw_set_tuning(ctx, &cands[i]) != SW_OK) continue;
+        // room for this shape's two graphs (the cache evicts all when full);
+        // the previous trial ended with an event synchronisation
+        sw_ctx_drop_graphs(ctx);
+        // blocked candidates: a whole number of K-step launches in the difference
+        const int kt = cands[i].variant == 3 ? cands[i].rows * steps_per_trial : steps_per_trial;
         if ((he = restore()) != hipSuccess) break;
-        if (sw_step(ctx, state, 1, stream) != SW_OK) continue;   // warm (code load, caches)
+        if (sw_step(ctx, state, 1, stream) != SW_OK) continue;        // capture + warm (code load, caches)
+        if (sw_step(ctx, state, 1 + kt, stream) != SW_OK) continue;
+        if ((he = restore()) != hipSuccess) break;
         // per-step time = (T(1 + k) - T(1)) / k: the per-call prologue cancels
         float ms1 = 0.f, msk = 0.f;
         if ((he = hipEventRecord(e0, s)) != hipSuccess) break;
@@ -166,8 +178,6 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
         if ((he = hipEventRecord(e1, s)) != hipSuccess) break;
         if ((he = hipEventSynchronize(e1)) != hipSuccess) break;
         if ((he = hipEventElapsedTime(&ms1, e0, e1)) != hipSuccess) break;
-        // blocked candidates: a whole number of K-step launches in the difference
-        const int kt = cands[i].variant == 3 ? cands[i].rows * steps_per_trial : steps_per_trial;
         if ((he = hipEventRecord(e0, s)) != hipSuccess) break;
         if (sw_step(ctx, state, 1 + kt, stream) != SW_OK) continue;
         if ((he = hipEventRecord(e1, s)) != hipSuccess) break;
@@ -181,6 +191,7 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
     }
     if (he == hipSuccess) he = restore();
     if (he == hipSuccess) he = hipStreamSynchronize(s);
+    sw_ctx_drop_graphs(ctx);                 // the trial shapes' graphs
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(backup);
