@@ -172,7 +172,8 @@ sw_status sw_set_variant(sw_ctx *ctx, int32_t variant);
 typedef struct {
     int32_t variant;    /* 0 auto, 1 per-cell baseline, 2 fused, 3 temporal blocking, 4 unfused, 5 AoS,
                            6 generated from region expressions */
-    int32_t rows;       /* fused, AoS: rows per tile (>= 1); blocked: steps per launch K (3, 5; 7 in SW_F32) */
+    int32_t rows;       /* fused, AoS: rows per tile (>= 1); blocked: steps per launch K (3, 5; 7 in SW_F32);
+                           generated: tile height 4, 8 or 16 (64 columns) */
     int32_t vec;        /* fused: cells per lane; SW_F32: 1, 2 or 4, SW_F64: 1 or 2; blocked: waves per tile (4, 8, 12, 16) */
     int32_t occupancy;  /* fused: register budget in waves per SIMD: 0 (compiler's choice), 3 or 4 */
     int32_t prefetch;   /* fused: rows loaded ahead of the row being updated: 1, 2 or 3 */

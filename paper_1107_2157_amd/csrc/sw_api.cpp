@@ -174,7 +174,7 @@ sw_status enqueue_steps(sw_ctx *ctx, const sw_state *state, int nsteps, const Sw
         for (; n < nsteps; ++n) {
             SwLaunch b = launch_of(ctx, state, cur);
             b.step = n;
-            SW_HIP(sw_launch_rgn(b, s));
+            SW_HIP(sw_launch_rgn(b, tun.rows, s));
             SW_HIP(sw_launch_fill_halo(launch_of(ctx, state, cur ^ 1), s));
             cur ^= 1;
         }
@@ -358,8 +358,15 @@ sw_status resolve_tuning(const sw_ctx *ctx, const sw_tuning &in, SwTuning *out) 
     if (variant == 0) variant = ctx->opts.scheme == SW_SCHEME_PAPER ? 2 : 1;
     if (variant >= 2 && ctx->opts.scheme != SW_SCHEME_PAPER)
         return fail(SW_ENOTSUP, "tuning: the fused, blocked, unfused, AoS and generated kernels implement the paper scheme only");
-    if (variant == 4 || variant == 6) {
-        *out = SwTuning{variant, 0, 0, 0, 0, 0};
+    if (variant == 4) {
+        *out = SwTuning{4, 0, 0, 0, 0, 0};
+        return SW_OK;
+    }
+    if (variant == 6) {
+        const int rows = in.rows ? in.rows : 8;
+        if (!sw_rgn_rows_supported(rows))
+            return fail(SW_EINVAL, "tuning: generated kernel has no %d-row tiles (4, 8 or 16)", rows);
+        *out = SwTuning{6, rows, 0, 0, 0, 0};
         return SW_OK;
     }
     if (variant == 5) {

@@ -82,7 +82,9 @@ hipError_t sw_launch_aos_convert(int dtype, const void *const soa[3], void *aos,
 hipError_t sw_launch_aos_step(const SwLaunch &a, const void *in, void *out, int rows, hipStream_t s);
 // The step generated from region expressions (wave_advance.rgn): new
 // interior of `out` and the CFL epilogue; the halo is filled separately.
-hipError_t sw_launch_rgn(const SwLaunch &a, hipStream_t s);
+// `rows`: tile height (64 columns), one of the instantiated heights.
+bool sw_rgn_rows_supported(int rows);
+hipError_t sw_launch_rgn(const SwLaunch &a, int rows, hipStream_t s);
 
 // The instantiated launch shapes: (dtype, cells per lane, register budget,
 // prefetch depth).

@@ -10,7 +10,10 @@ Elemental functions act element by element.  Arrays carry their halo in
 memory; global boundary values are applied outside the kernel.
 
 This module reads such a program (the ``.rgn`` language below), checks it,
-and emits a HIP kernel in the paper's generated design mapped onto gfx950:
+hoists elemental calls that the program repeats on shifted regions into
+temporaries of their own (the same operations on the same values, so the
+same bits, with fewer of them), and emits a HIP kernel in the paper's
+generated design mapped onto gfx950:
 one thread per output element; every input array is copied with the halo
 its regions need into LDS by the thread block; array temporaries (face
 quantities) are evaluated over the part of their extent the block needs and
@@ -375,6 +378,101 @@ def load(path: str = PROGRAM) -> Program:
 
 
 # ---------------------------------------------------------------------------
+# Hoisting elemental calls out of shifted regions.
+
+def _call_key(e):
+    """(fn, arrays, halo) if `e` applies an elemental function to regions of
+    arrays that all use one halo vector, else None."""
+    if not isinstance(e, Call) or not e.args or not all(isinstance(x, Region) for x in e.args):
+        return None
+    halos = {x.halo for x in e.args}
+    if len(halos) != 1:
+        return None
+    return e.fn, tuple(x.array for x in e.args), e.args[0].halo
+
+
+def _walk(e, fn):
+    fn(e)
+    if isinstance(e, (Neg, Square)):
+        _walk(e.a, fn)
+    elif isinstance(e, Bin):
+        _walk(e.a, fn)
+        _walk(e.b, fn)
+    elif isinstance(e, Call):
+        for x in e.args:
+            _walk(x, fn)
+
+
+def _rewrite(e, fn):
+    r = fn(e)
+    if r is not None:
+        return r
+    if isinstance(e, Neg):
+        return Neg(_rewrite(e.a, fn))
+    if isinstance(e, Square):
+        return Square(_rewrite(e.a, fn))
+    if isinstance(e, Bin):
+        return Bin(e.op, _rewrite(e.a, fn), _rewrite(e.b, fn))
+    if isinstance(e, Call):
+        return Call(e.fn, tuple(_rewrite(x, fn) for x in e.args))
+    return e
+
+
+def hoist(prog: Program) -> Program:
+    """A program that computes the same elements with fewer operations.
+    An elemental function applied to the same arrays under two or more
+    different halo vectors, f(region_cpy(A, h1), region_cpy(B, h1)) and
+    f(region_cpy(A, h2), region_cpy(B, h2)), evaluates f twice on most
+    elements.  Such calls become regions of a new temporary
+    T = f(region_cpy(A, 0), region_cpy(B, 0)) over the arrays' whole extent:
+    every element of T is the same operations on the same values, so each
+    result is bitwise what the original statement computed."""
+    zero = (0, 0, 0, 0)
+    uses = {}
+    for _, e in prog.temps + prog.stores:
+        def note(x):
+            k = _call_key(x)
+            if k is not None:
+                uses.setdefault(k[:2], set()).add(k[2])
+        _walk(e, note)
+    hoisted = {k: f"{k[0]}__{'_'.join(k[1])}" for k, halos in uses.items() if len(halos) > 1}
+    if not hoisted:
+        return prog
+    out = Program(prog.name, list(prog.scalars), list(prog.inputs), list(prog.outputs), dict(prog.elementals),
+                  dict(prog.arrays), [], dict(prog.views), [], dict(prog.halos))
+    defined = set(prog.inputs)
+
+    def sub(x):
+        k = _call_key(x)
+        if k is None or k[:2] not in hoisted:
+            return None
+        return Region(hoisted[k[:2]], k[2])
+
+    def define_needed(e):
+        # hoisted temporaries this statement reads, defined just before it
+        def need(x):
+            k = _call_key(x)
+            if k is not None and k[:2] in hoisted:
+                name = hoisted[k[:2]]
+                if name not in defined:
+                    fn, arrays = k[:2]
+                    body = Call(fn, tuple(Region(a, zero) for a in arrays))
+                    out.arrays[name] = prog.arrays[arrays[0]]
+                    out.temps.append((name, body))
+                    defined.add(name)
+        _walk(e, need)
+
+    for name, e in prog.temps:
+        define_needed(e)
+        out.temps.append((name, _rewrite(e, sub)))
+        defined.add(name)
+    for view, e in prog.stores:
+        define_needed(e)
+        out.stores.append((view, _rewrite(e, sub)))
+    return out
+
+
+# ---------------------------------------------------------------------------
 # Whole-array semantics (numpy): the meaning of a program.
 
 def interpret(prog: Program, arrays: dict, scalars: dict) -> dict:
@@ -514,13 +612,11 @@ def _emit(e, at, prog, boxes, env=None) -> str:
     raise TypeError(e)
 
 
-def generate(prog: Program, tx: int = 64, ty: int = 8, source_name: str = "wave_advance.rgn") -> str:
-    """HIP source of the tile kernel for `prog` (tiles of tx x ty outputs,
-    one thread each).  The runtime around the translated statements (dt
-    from the device-side CFL ring, the signal-speed reduction and sticky
-    flag of the step epilogue) expects the outputs in the order h, hu, hv."""
-    if len(prog.inputs) != 3 or len(prog.outputs) != 3 or len(prog.stores) != 3:
-        raise RegionError("the generated step kernel takes three input and three output arrays")
+TILE_ROWS = (4, 8, 16)      # tile heights the generated file instantiates (64 columns each)
+
+
+def _kernel(prog: Program, tx: int, ty: int) -> list:
+    """Lines of one tile kernel k_rgn_<name>_<ty> for tiles of tx x ty outputs."""
     boxes, _ = tile_ranges(prog, tx, ty)
     nt = tx * ty
     if nt % 64 or nt > 1024:
@@ -528,30 +624,13 @@ def generate(prog: Program, tx: int = 64, ty: int = 8, source_name: str = "wave_
     order = {v: prog.outputs.index(prog.views[v][0]) for v, _ in prog.stores}
     L = []
     w = L.append
-    w(f"// Generated by paper_1107_2157_amd/regions.py from {source_name}; do not edit.")
-    w("//")
-    w(f"// Kernel `{prog.name}`: one thread per output element, tiles of {tx} x {ty};")
-    w("// inputs and array temporaries staged in LDS (element ranges per tile:")
+    w(f"// Tiles of {tx} x {ty} outputs; element ranges per tile, relative to the tile origin:")
     for name in prog.inputs + [t for t, _ in prog.temps]:
         if name in boxes:
             x0, x1, y0, y1 = boxes[name]
-            w(f"//   {name}: x [{x0}, {x1}) y [{y0}, {y1}) of the tile origin, extent "
-              f"{fmt_extent(prog.arrays[name])})")
-    w("// Global boundary values are applied outside the kernel.")
-    w('#include "sw_common.h"')
-    w("")
-    w("using namespace sw;")
-    w("")
-    w("namespace {")
-    w("")
-    w("template <typename T> __device__ __forceinline__ T rgn_sq(T x) { return x * x; }")
-    for fn, el in prog.elementals.items():
-        args = ", ".join(f"T {p}" for p in list(el.params) + free_scalars(prog, el.body, el.params))
-        body = _emit(el.body, ("0", "0"), prog, boxes)
-        w(f"template <typename T> __device__ __forceinline__ T rgn_{fn}({args}) {{ return {body}; }}")
-    w("")
+            w(f"//   {name}: x [{x0}, {x1}) y [{y0}, {y1}), extent {fmt_extent(prog.arrays[name])}")
     w(f"template <typename T>")
-    w(f"__global__ __launch_bounds__({nt}) void k_rgn_{prog.name}(SwLaunch a) {{")
+    w(f"__global__ __launch_bounds__({nt}) void k_rgn_{prog.name}_{ty}(SwLaunch a) {{")
     w(f"    constexpr int TX = {tx}, TY = {ty}, NT = {nt};")
     for name in prog.inputs + [t for t, _ in prog.temps]:
         if name in boxes:
@@ -564,10 +643,10 @@ def generate(prog: Program, tx: int = 64, ty: int = 8, source_name: str = "wave_
     w("    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;")
     w("    const double dt_ = step_dt(a);")
     scal = {"dt": "(T)dt_", "dx": "(T)a.dx", "dy": "(T)a.dy", "g": "(T)a.g"}
-    for s in prog.scalars:
-        if s not in scal:
-            raise RegionError(f"scalar {s!r}: the runtime provides dt, dx, dy and g")
-        w(f"    const T {s} = {scal[s]};")
+    for sc in prog.scalars:
+        if sc not in scal:
+            raise RegionError(f"scalar {sc!r}: the runtime provides dt, dx, dy and g")
+        w(f"    const T {sc} = {scal[sc]};")
     w("")
     w("    // copy-in: element p of an input array is cell p - (1, 1); positions past")
     w("    // the array (tiles at the high edges) are clamped and feed no stored element")
@@ -582,7 +661,6 @@ def generate(prog: Program, tx: int = 64, ty: int = 8, source_name: str = "wave_
         w(f"        s_{name}[e] = ((const T *)a.in[{k}])[(int64_t)cj * pitch + ci];")
         w("    }")
     w("    __syncthreads();")
-    # temporaries, by dependency level
     level = {}
     for name, e in prog.temps:
         deps = [arr for arr, _ in reads(e) if arr in level]
@@ -634,16 +712,66 @@ def generate(prog: Program, tx: int = 64, ty: int = 8, source_name: str = "wave_
     w("                      (int)(blockIdx.y * gridDim.x + blockIdx.x));")
     w("    }")
     w("}")
+    return L
+
+
+def generate(prog: Program, tx: int = 64, tile_rows=TILE_ROWS, source_name: str = "wave_advance.rgn",
+             optimize: bool = True) -> str:
+    """HIP source of the tile kernels for `prog`: one per tile height in
+    `tile_rows` (tiles of tx x rows outputs, one thread each; with
+    `optimize`, elemental calls on shifted regions are hoisted into
+    temporaries first), and the launcher sw_launch_rgn(a, rows, stream).
+    The runtime around the translated statements (dt from the device-side
+    CFL ring, the signal-speed reduction and sticky flag of the step
+    epilogue) expects the outputs in the order h, hu, hv."""
+    if optimize:
+        prog = hoist(prog)
+    if len(prog.inputs) != 3 or len(prog.outputs) != 3 or len(prog.stores) != 3:
+        raise RegionError("the generated step kernel takes three input and three output arrays")
+    L = []
+    w = L.append
+    w(f"// Generated by paper_1107_2157_amd/regions.py from {source_name}; do not edit.")
+    w("//")
+    w(f"// Kernel `{prog.name}`: one thread per output element; inputs and array")
+    w("// temporaries staged in LDS per tile, barriers between dependency levels.")
+    w("// Global boundary values are applied outside the kernel.")
+    w('#include "sw_common.h"')
+    w("")
+    w("using namespace sw;")
+    w("")
+    w("namespace {")
+    w("")
+    w("template <typename T> __device__ __forceinline__ T rgn_sq(T x) { return x * x; }")
+    for fn, el in prog.elementals.items():
+        args = ", ".join(f"T {p}" for p in list(el.params) + free_scalars(prog, el.body, el.params))
+        bodyc = _emit(el.body, ("0", "0"), prog, {})
+        w(f"template <typename T> __device__ __forceinline__ T rgn_{fn}({args}) {{ return {bodyc}; }}")
+    for ty in tile_rows:
+        w("")
+        L.extend(_kernel(prog, tx, ty))
+    w("")
+    w(f"template <typename T> hipError_t launch_{prog.name}(const SwLaunch &a, int rows, hipStream_t s) {{")
+    w(f"    const unsigned gx = (unsigned)((a.nx + {tx - 1}) / {tx});")
+    for ty in tile_rows:
+        w(f"    if (rows == {ty}) {{")
+        w(f"        const dim3 grid(gx, (unsigned)((a.ny + {ty - 1}) / {ty}));")
+        w(f"        if (grid.y > 65535u) return hipErrorInvalidValue;")
+        w(f"        k_rgn_{prog.name}_{ty}<T><<<grid, {tx * ty}, 0, s>>>(a);")
+        w("        return hipGetLastError();")
+        w("    }")
+    w("    return hipErrorInvalidValue;")
+    w("}")
     w("")
     w("}  // namespace")
     w("")
-    w("hipError_t sw_launch_rgn(const SwLaunch &a, hipStream_t s) {")
+    w(f"// Tile heights instantiated: {', '.join(str(t) for t in tile_rows)}.")
+    w("bool sw_rgn_rows_supported(int rows) {")
+    w(f"    return {' || '.join(f'rows == {t}' for t in tile_rows)};")
+    w("}")
+    w("")
+    w("hipError_t sw_launch_rgn(const SwLaunch &a, int rows, hipStream_t s) {")
     w("    if (a.scheme != 0) return hipErrorInvalidValue;")
-    w(f"    const dim3 grid((unsigned)((a.nx + {tx - 1}) / {tx}), (unsigned)((a.ny + {ty - 1}) / {ty}));")
-    w(f"    if (grid.y > 65535u) return hipErrorInvalidValue;")
-    w(f"    if (a.dtype == 0) k_rgn_{prog.name}<float><<<grid, {nt}, 0, s>>>(a);")
-    w(f"    else k_rgn_{prog.name}<double><<<grid, {nt}, 0, s>>>(a);")
-    w("    return hipGetLastError();")
+    w(f"    return a.dtype == 0 ? launch_{prog.name}<float>(a, rows, s) : launch_{prog.name}<double>(a, rows, s);")
     w("}")
     return "\n".join(L) + "\n"
 

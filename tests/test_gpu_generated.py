@@ -66,6 +66,24 @@ def test_generated_edge_shapes(shape, bc):
     assert rel_maxnorm(got, (H, U, V)) <= TOL["f64"], shape
 
 
+@pytest.mark.parametrize("rows", [4, 16])
+def test_generated_tile_heights(rows):
+    """Every instantiated tile height gives the same bits as the default one."""
+    nx, ny = 150, 70
+    st = ics.random_state(nx, ny, seed=71, amp_h=0.2, amp_m=0.04)
+    ref, _, _ = run(st, 9, "f32", (sw.PERIODIC, sw.REFLECT), sw.VARIANT_GENERATED)
+    h, hu, hv = (rounded(a, "f32") for a in st)
+    s = sw.Solver(nx, ny, g=G, dtype="f32", bc_x=sw.PERIODIC, bc_y=sw.REFLECT)
+    s.set_tuning(variant=sw.VARIANT_GENERATED, rows=rows)
+    s.set_state(h, hu, hv)
+    s.step(9)
+    for a, b in zip(s.get_state(halo=True), ref):
+        assert torch.equal(a, b)
+    with pytest.raises(sw.SwError) as e:
+        s.set_tuning(variant=sw.VARIANT_GENERATED, rows=5)
+    assert e.value.status == sw.EINVAL
+
+
 def test_generated_refused_for_the_transverse_scheme():
     s = sw.Solver(32, 16, dtype="f32", scheme=sw.SCHEME_TRANSVERSE)
     with pytest.raises(sw.SwError) as e:

@@ -126,3 +126,39 @@ def test_elemental_scalars_become_arguments():
     src = regions.generate(regions.load())
     assert "rgn_fu(T h, T u, T g)" in src and "rgn_half(T a, T b, T fa, T fb, T c)" in src
     assert "__syncthreads();" in src and "__shared__ T s_Hx[520];" in src
+    assert "s_fu__H_U" in src and "s_fu__H_U" not in regions.generate(regions.load(), optimize=False)
+
+
+def test_hoisting_keeps_every_bit():
+    """Elemental calls repeated on shifted regions are hoisted into
+    temporaries (three cell fluxes on the inputs, four on the face states);
+    the hoisted program computes bitwise the same outputs."""
+    p = regions.load()
+    hp = regions.hoist(p)
+    new = [n for n, _ in hp.temps if n not in p.arrays]
+    assert sorted(new) == ["fu__H_U", "fu__Hx_Ux", "fv__H_U_V", "fv__Hx_Ux_Vx", "fv__Hy_Uy_Vy", "gv__H_V",
+                           "gv__Hy_Vy"]
+    assert hp.arrays["fu__H_U"] == (2, 2) and hp.arrays["fu__Hx_Ux"] == (1, 0)
+    nx, ny = 29, 19
+    h, hu, hv = ics.random_state(nx, ny, seed=12, amp_h=0.2, amp_m=0.05)
+    H, U, V = (oracle.with_halo(np.asarray(a, dtype=np.float64)) for a in (h, hu, hv))
+    oracle.fill_halo(H, U, V, bcx=oracle.PERIODIC, bcy=oracle.REFLECT)
+    res = []
+    for prog in (p, hp):
+        outs = {k: np.zeros_like(H) for k in ("oH", "oU", "oV")}
+        regions.interpret(prog, {"H": H, "U": U, "V": V, **outs}, {"dt": 0.05, "dx": 1.0, "dy": 0.5, "g": G})
+        res.append(outs)
+    for k in ("oH", "oU", "oV"):
+        assert np.array_equal(res[0][k], res[1][k])
+    # a call used under one halo only is left in place
+    text = HEAD + "Hx = fu2(region_cpy(H, lo), region_cpy(U, lo))\n" + TAIL
+    text = text.replace("interior = [1, 1, 1, 1]", "elemental fu2(h, u) = u*u/h\ninterior = [1, 1, 1, 1]")
+    q = regions.parse(text)
+    assert regions.hoist(q).temps == q.temps
+
+
+def test_tile_ranges_of_hoisted_temporaries():
+    boxes, _ = regions.tile_ranges(regions.hoist(regions.load()), 64, 8)
+    assert boxes["fu__H_U"] == (0, 66, 1, 9)      # read at the x faces only: the tile's rows
+    assert boxes["gv__H_V"] == (1, 65, 0, 10)     # read at the y faces only: the tile's columns
+    assert boxes["fu__Hx_Ux"] == (0, 65, 0, 8)
