@@ -135,6 +135,17 @@ sw_status sw_step(sw_ctx *ctx, sw_state *state, int32_t nsteps, void *stream);
  * may be NULL.  Returns SW_EUNSTABLE if the sticky flag is set. */
 sw_status sw_sync_status(sw_ctx *ctx, void *stream, double *t, double *last_dt, int64_t *steps);
 
+/* Sync.  Diagnostics of the interior of buf[cur] (the conserved quantities
+ * of section "Shallow Water Model"): out[0] = sum of h (the mass in cell
+ * units), out[1] = sum of hu, out[2] = sum of hv, out[3] = max signal speed
+ * max(|u|, |v|) + sqrt(g h) over the cells with finite values and h > 0,
+ * out[4] = min h, out[5] = number of cells with a non-finite value.  Sums
+ * in FP64 over per-block partials combined in a fixed order, so the same
+ * state gives the same bits.  Reads buf[cur] only (the halo is not used);
+ * `out` is host memory; synchronises the stream; allocates nothing.
+ * Errors: SW_EINVAL (NULL, misaligned planes, cur not 0 or 1), SW_EHIP. */
+sw_status sw_diagnostics(sw_ctx *ctx, const sw_state *state, void *stream, double out[6]);
+
 /* Async.  Zero the simulated time and step counter and clear the sticky flag. */
 sw_status sw_reset_time(sw_ctx *ctx, void *stream);
 

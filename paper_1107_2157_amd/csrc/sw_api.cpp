@@ -37,6 +37,7 @@ struct sw_ctx {
     // allocated by the first sw_step that needs it, freed by sw_destroy
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    double *diag = nullptr;   // partials and result of sw_diagnostics (allocated by sw_create)
 };
 
 namespace {
@@ -322,9 +323,11 @@ sw_status sw_create(sw_grid grid, sw_halo halo, double g, double dx, const sw_op
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipMalloc((void **)&c->sc, sizeof(SwScalars));
     if (e == hipSuccess) e = hipMemset(c->sc, 0, sizeof(SwScalars));
+    if (e == hipSuccess) e = hipMalloc((void **)&c->diag, sw_diag_scratch_bytes());
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
         if (c->sc) (void)hipFree(c->sc);
+        if (c->diag) (void)hipFree(c->diag);
         if (c->cap) (void)hipStreamDestroy(c->cap);
         delete c;
         return fail(e == hipErrorOutOfMemory ? SW_ENOMEM : SW_EHIP, "create: %s", hipGetErrorString(e));
@@ -338,6 +341,7 @@ sw_status sw_destroy(sw_ctx *ctx) {
     (void)use_device(ctx);
     drop_graphs(ctx);
     if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->diag) (void)hipFree(ctx->diag);
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     if (ctx->sc) (void)hipFree(ctx->sc);
     delete ctx;
@@ -515,6 +519,19 @@ sw_status sw_sync_status(sw_ctx *ctx, void *stream, double *t, double *last_dt, 
     if (last_dt) *last_dt = h.last_dt;
     if (steps) *steps = h.steps;
     if (h.unstable) return fail(SW_EUNSTABLE, "a step produced h <= 0 or a non-finite value");
+    return SW_OK;
+}
+
+sw_status sw_diagnostics(sw_ctx *ctx, const sw_state *state, void *stream, double out[6]) {
+    if (!ctx || !out) return fail(SW_EINVAL, "diagnostics: NULL argument");
+    sw_status st = check_state(ctx, state, false);
+    if (st != SW_OK) return st;
+    if ((st = use_device(ctx)) != SW_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    SW_HIP(sw_launch_diagnostics(launch_of(ctx, state, state->cur), ctx->diag, s));
+    const size_t nres = sw_diag_scratch_bytes() / sizeof(double);
+    SW_HIP(hipMemcpyAsync(out, ctx->diag + nres - 6, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+    SW_HIP(hipStreamSynchronize(s));
     return SW_OK;
 }
 

@@ -41,6 +41,12 @@ hipError_t sw_launch_reset(SwScalars *sc, int clear_time, hipStream_t s);
 // signal speed into slot 0.
 hipError_t sw_launch_prologue(const SwLaunch &a, hipStream_t s);
 hipError_t sw_launch_fill_halo(const SwLaunch &a, hipStream_t s);
+// Diagnostics of the interior of `in` (sum h, sum hu, sum hv, max signal
+// speed, min h, non-finite cells): the six doubles land at
+// scratch[sw_diag_scratch_bytes() / 8 - 6 ...]; scratch holds
+// sw_diag_scratch_bytes() bytes of device memory.
+size_t sw_diag_scratch_bytes();
+hipError_t sw_launch_diagnostics(const SwLaunch &a, double *scratch, hipStream_t s);
 // Tuning of a step launch.
 struct SwTuning {
     int variant;     // 1 per-cell baseline, 2 fused, 3 temporal blocking (fixed dt; rows = steps per launch),

@@ -122,6 +122,68 @@ template <typename T> hipError_t launch_step_cell(const SwLaunch &a, hipStream_t
     return hipGetLastError();
 }
 
+// Diagnostics of the interior: per block, in a fixed order, the sums of h,
+// hu, hv (FP64), the max signal speed, the min h and the count of cells
+// with a non-finite value; a second single-block pass combines the
+// partials in a fixed order, so the result does not depend on timing.
+constexpr int kDiagBlocks = 1024;
+constexpr int kDiagThreads = 256;
+
+__device__ __forceinline__ void diag_combine(double *a, const double *b) {
+    a[0] += b[0];
+    a[1] += b[1];
+    a[2] += b[2];
+    a[3] = fmax(a[3], b[3]);
+    a[4] = fmin(a[4], b[4]);
+    a[5] += b[5];
+}
+
+// Block reduction of each thread's 6 values in a fixed tree order; thread 0
+// ends with the result.
+__device__ __forceinline__ void diag_block_reduce(double v[6]) {
+    __shared__ double sh[kDiagThreads][6];
+    for (int k = 0; k < 6; ++k) sh[threadIdx.x][k] = v[k];
+    __syncthreads();
+    for (int w = kDiagThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) diag_combine(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    for (int k = 0; k < 6; ++k) v[k] = sh[0][k];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kDiagThreads) void k_diag_partial(SwLaunch a, double *part) {
+    const T *P[3] = {(const T *)a.in[0], (const T *)a.in[1], (const T *)a.in[2]};
+    const int nx = a.nx, ny = a.ny;
+    const T g = (T)a.g;
+    double v[6] = {0.0, 0.0, 0.0, 0.0, INFINITY, 0.0};
+    // block b takes rows b, b + kDiagBlocks, ...; thread t columns t, t + 256, ...
+    for (int j = blockIdx.x; j < ny; j += kDiagBlocks) {
+        const int64_t row = (int64_t)j * a.pitch;
+        for (int i = threadIdx.x; i < nx; i += kDiagThreads) {
+            const U3<T> c = {P[0][row + i], P[1][row + i], P[2][row + i]};
+            const bool finite = isfinite((double)c.h) && isfinite((double)c.p) && isfinite((double)c.q);
+            v[0] += (double)c.h;
+            v[1] += (double)c.p;
+            v[2] += (double)c.q;
+            if (finite && c.h > T(0)) v[3] = fmax(v[3], (double)signal_speed(c, g));
+            v[4] = fmin(v[4], (double)c.h);
+            v[5] += finite ? 0.0 : 1.0;
+        }
+    }
+    diag_block_reduce(v);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 6; ++k) part[blockIdx.x * 6 + k] = v[k];
+}
+
+__global__ __launch_bounds__(kDiagThreads) void k_diag_final(double *part, double *out) {
+    double v[6] = {0.0, 0.0, 0.0, 0.0, INFINITY, 0.0};
+    for (int b = threadIdx.x; b < kDiagBlocks; b += kDiagThreads) diag_combine(v, part + b * 6);
+    diag_block_reduce(v);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 6; ++k) out[k] = v[k];
+}
+
 }  // namespace
 
 hipError_t sw_launch_reset(SwScalars *sc, int clear_time, hipStream_t s) {
@@ -143,6 +205,15 @@ hipError_t sw_launch_fill_halo(const SwLaunch &a, hipStream_t s) {
     unsigned blocks = (unsigned)((n + 255) / 256);
     if (a.dtype) k_fill_halo<double><<<blocks, 256, 0, s>>>(a);
     else k_fill_halo<float><<<blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+size_t sw_diag_scratch_bytes() { return (size_t)(kDiagBlocks + 1) * 6 * sizeof(double); }
+
+hipError_t sw_launch_diagnostics(const SwLaunch &a, double *scratch, hipStream_t s) {
+    if (a.dtype) k_diag_partial<double><<<kDiagBlocks, kDiagThreads, 0, s>>>(a, scratch);
+    else k_diag_partial<float><<<kDiagBlocks, kDiagThreads, 0, s>>>(a, scratch);
+    k_diag_final<<<1, kDiagThreads, 0, s>>>(scratch, scratch + kDiagBlocks * 6);
     return hipGetLastError();
 }
 

@@ -93,6 +93,8 @@ SIGNATURES = {
     "sw_sync_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "sw_reset_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sw_diagnostics": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(State), ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_double)]),
     "sw_set_variant": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "sw_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "sw_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
@@ -270,6 +272,14 @@ class Solver:
 
     def reset_time(self, stream=None):
         check(lib().sw_reset_time(self.ctx, _stream_handle(stream)), "sw_reset_time")
+
+    def diagnostics(self, stream=None) -> dict:
+        """Sums of h, hu, hv, max signal speed, min h and non-finite cell count of buf[cur]."""
+        out = (ctypes.c_double * 6)()
+        check(lib().sw_diagnostics(self.ctx, ctypes.byref(self.state), _stream_handle(stream), out),
+              "sw_diagnostics")
+        return {"mass": out[0], "sum_hu": out[1], "sum_hv": out[2], "max_speed": out[3], "min_h": out[4],
+                "nonfinite": int(out[5])}
 
 
 class Batch:
