@@ -172,7 +172,8 @@ sw_status sw_reset_time(sw_ctx *ctx, void *stream);
  * identical states; the baseline and variant 6 agree with them up to
  * rounding order.
  * Errors: SW_EINVAL for an unknown variant; sw_step reports SW_ENOTSUP for a
- * variant the options exclude. */
+ * variant the options exclude (also variants 3 and 6 for grids taller than
+ * 65535 rows of tiles: tiles of 40-92 rows blocked, 4-16 rows generated). */
 sw_status sw_set_variant(sw_ctx *ctx, int32_t variant);
 
 /* Launch shape of the step kernel (what the autotuner searches).  Zero

@@ -370,6 +370,9 @@ sw_status resolve_tuning(const sw_ctx *ctx, const sw_tuning &in, SwTuning *out) 
         const int rows = in.rows ? in.rows : 8;
         if (!sw_rgn_rows_supported(rows))
             return fail(SW_EINVAL, "tuning: generated kernel has no %d-row tiles (4, 8 or 16)", rows);
+        if ((ctx->grid.ny + rows - 1) / rows > 65535)
+            return fail(SW_ENOTSUP, "tuning: %d rows exceed the generated kernel's 65535 tile rows of %d",
+                        ctx->grid.ny, rows);
         *out = SwTuning{6, rows, 0, 0, 0, 0};
         return SW_OK;
     }
@@ -384,6 +387,10 @@ sw_status resolve_tuning(const sw_ctx *ctx, const sw_tuning &in, SwTuning *out) 
         const int k = in.rows ? in.rows : 5;
         if (!sw_tb_supported((int)ctx->opts.dtype, k))
             return fail(SW_EINVAL, "tuning: %d steps per blocked launch not available for this dtype", k);
+        if ((ctx->grid.ny + sw_tb_tile_rows((int)ctx->opts.dtype, k) - 1) / sw_tb_tile_rows((int)ctx->opts.dtype, k) >
+            65535)
+            return fail(SW_ENOTSUP, "tuning: %d rows exceed the blocked kernel's 65535 tile rows of %d", ctx->grid.ny,
+                        sw_tb_tile_rows((int)ctx->opts.dtype, k));
         const int waves = in.vec ? in.vec : (ctx->opts.dtype == SW_F64 ? 8 : 16);
         if (waves != 4 && waves != 8 && waves != 12 && waves != 16)
             return fail(SW_EINVAL, "tuning: %d waves per blocked tile (4, 8, 12 or 16)", waves);

@@ -64,6 +64,7 @@ hipError_t sw_launch_fused_cfg(const SwLaunch &a, int rows, int vec, int minw, i
 int sw_fused_default_rows(int nx, int ny, int vec);
 // Temporal blocking (fixed dt, paper scheme): k steps of every cell per launch.
 bool sw_tb_supported(int dtype, int k);
+int sw_tb_tile_rows(int dtype, int k);   // output rows per blocked tile (one grid row of tiles per block row)
 // waves per block: 4, 8, 12 or 16 (the tile is the same; each wave marches one chunk of its rows).
 hipError_t sw_launch_tb(const SwLaunch &a, int k, int waves, hipStream_t s);
 int sw_fused_default_vec(int dtype, int nx);

@@ -251,6 +251,7 @@ __global__ __launch_bounds__(64 * NW) void k_step_tb(SwLaunch a) {
 template <typename T, int K> hipError_t launch_tb(const SwLaunch &a, int waves, hipStream_t s) {
     constexpr int TX = kTbCols - 2 * K, TY = tb_staged_rows<T>() - 2 * K;
     dim3 grid((a.nx + TX - 1) / TX, (a.ny + TY - 1) / TY);
+    if (grid.y > 65535u) return hipErrorInvalidValue;   // refused earlier by the tuning check
     if (waves == 16) k_step_tb<T, K, 16><<<grid, 1024, 0, s>>>(a);
     else if (waves == 12) k_step_tb<T, K, 12><<<grid, 768, 0, s>>>(a);
     else if (waves == 8) k_step_tb<T, K, 8><<<grid, 512, 0, s>>>(a);
@@ -261,6 +262,8 @@ template <typename T, int K> hipError_t launch_tb(const SwLaunch &a, int waves, 
 }  // namespace
 
 bool sw_tb_supported(int dtype, int k) { return k == 3 || k == 5 || (dtype == 0 && k == 7); }
+
+int sw_tb_tile_rows(int dtype, int k) { return (dtype == 0 ? tb_staged_rows<float>() : tb_staged_rows<double>()) - 2 * k; }
 
 hipError_t sw_launch_tb(const SwLaunch &a, int k, int waves, hipStream_t s) {
     if (a.dt_fixed <= 0 || a.scheme != 0) return hipErrorInvalidValue;

@@ -89,3 +89,20 @@ def test_generated_refused_for_the_transverse_scheme():
     with pytest.raises(sw.SwError) as e:
         s.set_tuning(variant=sw.VARIANT_GENERATED)
     assert e.value.status == sw.ENOTSUP
+
+
+def test_tall_grids_refused_by_tiled_variants():
+    """More than 65535 rows of tiles: the generated kernel (4-row tiles) and
+    the blocked kernel (FP64, K = 5: 40-row tiles) refuse with SW_ENOTSUP
+    when the shape is chosen, instead of failing at launch."""
+    s = sw.Solver(1, 65535 * 4 + 1, g=G, dtype="f32")
+    with pytest.raises(sw.SwError) as e:
+        s.set_tuning(variant=sw.VARIANT_GENERATED, rows=4)
+    assert e.value.status == sw.ENOTSUP
+    s.set_tuning(variant=sw.VARIANT_GENERATED, rows=8)          # 32768 rows of tiles: fine
+    del s
+    b = sw.Solver(1, 65535 * 40 + 1, g=G, dtype="f64", cfl=0.0, dt_fixed=1e-3)
+    with pytest.raises(sw.SwError) as e:
+        b.set_tuning(variant=sw.VARIANT_TBLOCK, rows=5)
+    assert e.value.status == sw.ENOTSUP
+    b.set_tuning(variant=sw.VARIANT_TBLOCK, rows=3)             # 44-row tiles: 59580 rows of tiles
