@@ -1,6 +1,8 @@
 """Invariants of the scheme checked on the GPU path (through the C ABI):
 lake at rest (bitwise), mass conservation, mirror symmetry of a centred dam
-break (bitwise), determinism, and the sticky instability flag."""
+break (bitwise), determinism, the sticky instability flag, and the linear
+gravity-wave speed sqrt(g H) through the fused, blocked and generated
+kernels."""
 import math
 
 import numpy as np
@@ -189,3 +191,40 @@ def test_graph_replays_equal_eager_launches(variant, dtype):
     for k, (e, g) in enumerate(zip(*runs)):
         assert e[:3] == g[:3], f"call {k}"
         assert e[3] == g[3], f"call {k}: time / step counters"
+
+
+def _peak(profile, lo, hi):
+    k = lo + int(np.argmax(profile[lo:hi]))
+    ym, y0, yp = profile[k - 1], profile[k], profile[k + 1]
+    return k + 0.5 * (ym - yp) / (ym - 2 * y0 + yp)
+
+
+@pytest.mark.parametrize("variant", [sw.VARIANT_FUSED, sw.VARIANT_TBLOCK, sw.VARIANT_GENERATED])
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_linear_gravity_wave_speed(variant, axis):
+    """A small Gaussian rise on still water of depth 1 splits into two pulses
+    moving at sqrt(g H): the right-moving peak's speed between steps 400 and
+    1200 (fixed dt, periodic walls, FP64) is within 1 % of sqrt(g)."""
+    n, w, sigma, eps, x0 = 2048, 4, 24.0, 1e-3, 512.0
+    x = np.arange(n) + 0.5
+    pulse = 1.0 + eps * np.exp(-((x - x0) ** 2) / (2 * sigma ** 2))
+    h = np.tile(pulse, (w, 1))
+    if axis == "y":
+        h = h.T.copy()
+    z = np.zeros_like(h)
+    dt = 0.5 / math.sqrt(G)
+    announce(f"gravity wave variant={variant} axis={axis}")
+    s = sw.Solver(h.shape[1], h.shape[0], g=G, dtype="f64", bc_x=sw.PERIODIC, bc_y=sw.PERIODIC, cfl=0.0,
+                  dt_fixed=dt, variant=variant)
+    pos = []
+    for nsteps in (400, 1200):
+        s.state.cur = 0
+        s.set_state(torch.from_numpy(h), torch.from_numpy(z), torch.from_numpy(z))
+        s.reset_time()
+        s.step(nsteps)
+        s.sync_status()
+        H = s.get_state()[0].numpy()
+        prof = H[0] if axis == "x" else H[:, 0]
+        pos.append(_peak(prof, int(x0) + 50, n - 10))
+    speed = (pos[1] - pos[0]) / (800 * dt)
+    assert abs(speed - math.sqrt(G)) / math.sqrt(G) < 0.01, speed
