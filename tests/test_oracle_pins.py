@@ -290,41 +290,6 @@ def test_convergence_order(scheme, two_d):
         assert order >= 1.8, (errs, order)
 
 
-# --------------------------------------------------------------------------
-# The paper's printed Fortran statements for h (reading of the signs)
-# --------------------------------------------------------------------------
-def region_cpy(a, halo):
-    """Interior of ``a`` (Fortran (x, y) indexing stored here as [y, x]) with
-    ``halo = [left, right, down, up]`` cells removed, as a copy."""
-    lt, rt, dn, up = halo
-    ny, nx = a.shape
-    return a[dn:ny - up, lt:nx - rt].copy()
-
-
-def test_fortran_h_statements_give_the_oracle_h():
-    """Cross-check of the sign reading: the paper's h face statement and h
-    update statement, evaluated with region copies, give the oracle's h."""
-    h, hu, hv = (a.numpy() for a in ics.random_state(11, 9, seed=8))
-    H, U, V = (oracle.with_halo(a) for a in (h, hu, hv))
-    oracle.fill_halo(H, U, V, REFLECT, REFLECT)
-    dt, dx, dy = 0.07, 1.0, 1.3
-    face_lt, face_rt, face_dn, face_up = [0, 1, 1, 1], [1, 0, 1, 1], [1, 1, 0, 1], [1, 1, 1, 0]
-    Hx = 0.5 * (region_cpy(H, face_lt) + region_cpy(H, face_rt)) + (0.5 * dt / dx) * (region_cpy(U, face_lt) - region_cpy(U, face_rt))
-    # the h update needs the face momenta Ux (x faces) and Vy (y faces)
-    FU = lambda Hh, Uu, Vv: Uu * Uu / Hh + 0.5 * G * Hh * Hh
-    GV = lambda Hh, Uu, Vv: Vv * Vv / Hh + 0.5 * G * Hh * Hh
-    Ux = 0.5 * (region_cpy(U, face_lt) + region_cpy(U, face_rt)) + (0.5 * dt / dx) * (
-        FU(region_cpy(H, face_lt), region_cpy(U, face_lt), None) - FU(region_cpy(H, face_rt), region_cpy(U, face_rt), None))
-    Vy = 0.5 * (region_cpy(V, face_dn) + region_cpy(V, face_up)) + (0.5 * dt / dy) * (
-        GV(region_cpy(H, face_dn), None, region_cpy(V, face_dn)) - GV(region_cpy(H, face_up), None, region_cpy(V, face_up)))
-    assert Hx.shape == (9, 12) and Vy.shape == (10, 11)
-    f_lt, f_rt, f_dn, f_up = [0, 1, 0, 0], [1, 0, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]
-    pH = region_cpy(H, [1, 1, 1, 1]) + (dt / dx) * (region_cpy(Ux, f_lt) - region_cpy(Ux, f_rt)) \
-        + (dt / dy) * (region_cpy(Vy, f_dn) - region_cpy(Vy, f_up))
-    oH, _, _ = oracle.step(H, U, V, G, dx, dy, dt, SCHEME_PAPER)
-    assert np.array_equal(interior(oH), pH)
-
-
 def test_unstable_state_is_reported():
     h = np.full((6, 6), 1.0)
     h[2, 3] = -0.5
