@@ -416,8 +416,8 @@ def main():
                     help="fixed launch shape 'variant,rows,vec,occupancy' instead of the autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the domain-decomposed path "
-              "is not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no "
+              "domain-decomposed path", file=sys.stderr)
         sys.exit(2)
 
     import torch
