@@ -29,6 +29,19 @@ namespace {
 // 64 x RY values in LDS, two tiles per CU (75 KB in FP32, 77 KB in FP64).
 // With 16 (FP32) or 12 / 8 (FP64) waves, RY - 2 - 2s rows split into equal
 // chunks at every step s, so no wave waits for a longer one at the barrier.
+// x neighbours for the row march: lane l receives x from lane l + 1 (next)
+// or l - 1 (prev); the wave's edge lane, which is never a live cell of a
+// blocked step, receives 0.  In FP32 that form lets the compiler fold the
+// lane move into the add or subtract that consumes it (a DPP operand).
+__device__ __forceinline__ float tb_next(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float tb_prev(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double tb_next(double x) { return from_next_lane(x, x); }
+__device__ __forceinline__ double tb_prev(double x) { return from_prev_lane(x, x); }
+
 template <typename T> constexpr int tb_staged_rows() { return sizeof(T) == 4 ? 98 : 50; }
 constexpr int kTbCols = 64;
 
@@ -131,10 +144,10 @@ __device__ __forceinline__ void tb_march(T *const B[3], const T E0[3], const T E
         R[1] = fma(-lx, fp, hp);
         R[2] = fma(-lx, fq, hq);
 #pragma unroll
-        for (int kk = 0; kk < 3; ++kk) Rn[kk] = from_next_lane(R[kk], R[kk]);
+        for (int kk = 0; kk < 3; ++kk) Rn[kk] = tb_next(R[kk]);
         xface_flux<T>(L[0] + Rn[0], L[1] + Rn[1], L[2] + Rn[2], k, fr);
 #pragma unroll
-        for (int kk = 0; kk < 3; ++kk) S[kk] = fma(-mx, fr[kk] - from_prev_lane(fr[kk], fr[kk]), U[kk]);
+        for (int kk = 0; kk < 3; ++kk) S[kk] = fma(-mx, fr[kk] - tb_prev(fr[kk]), U[kk]);
     };
     T U[3], N[3];
     load(r0, U);
