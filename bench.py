@@ -172,9 +172,10 @@ def run_comparison(steps, fused_tuning, sw, ics, torch):
     the headline workload: the fused kernel in the headline's tuned shape,
     the unfused step (face states of the first half-step written to HBM and
     read back by a second kernel), the AoS step (one (h, hu, hv, 0) vector
-    per cell; each call converts the state in and out) and the kernel
-    generated from region expressions (LDS tiles, one thread per cell, halo
-    filled by a separate launch).  Per-step times come from two calls of
+    per cell; each call converts the state in and out) and the kernels
+    generated from region expressions in both designs (row march in
+    registers; the paper's LDS tiles with one thread per cell), halo filled
+    by a separate launch.  Per-step times come from two calls of
     different length, so the per-call work (prologue, AoS conversions)
     cancels.  The fused, unfused and AoS final states must be bitwise equal;
     the generated kernel's differs by rounding."""
@@ -192,7 +193,7 @@ def run_comparison(steps, fused_tuning, sw, ics, torch):
     finals = []
     k_cal = steps // 5
     for label, tuning in (("fused", fused_tuning), ("unfused", {"variant": 4}), ("aos", {"variant": 5}),
-                          ("generated", {"variant": 6})):
+                          ("generated", {"variant": 6, "vec": 2}), ("generated_lds", {"variant": 6, "vec": 1})):
         s.set_tuning(**tuning)
         for k in (k_cal, steps):                   # graph capture (and workspace) outside the timed calls
             restart()
@@ -206,14 +207,15 @@ def run_comparison(steps, fused_tuning, sw, ics, torch):
         per_step = (t - t_cal) / (steps - k_cal)
         out[label] = {"tuning": s.get_tuning(), "gcells_per_s": n * n / per_step / 1e9,
                       "ms_per_step": 1e3 * per_step, "ms_per_call": 1e3 * t}
-    for label in ("unfused", "aos", "generated"):
+    for label in ("unfused", "aos", "generated", "generated_lds"):
         out[label]["ratio_to_fused"] = out[label]["gcells_per_s"] / out["fused"]["gcells_per_s"]
     out["unfused_to_aos"] = out["unfused"]["gcells_per_s"] / out["aos"]["gcells_per_s"]
     out["generated_to_aos"] = out["generated"]["gcells_per_s"] / out["aos"]["gcells_per_s"]
-    out["bitwise_equal"] = all(torch.equal(a, b) and torch.equal(a, c) for a, b, c, _ in zip(*finals))
-    # the generated kernel evaluates the program's own expressions: equal to rounding
-    out["generated"]["max_rel_diff_to_fused"] = max(
-        float((g.double() - f.double()).abs().max() / f.double().abs().max()) for f, g in zip(finals[0], finals[3]))
+    out["bitwise_equal"] = all(torch.equal(a, b) and torch.equal(a, c) for a, b, c, _, _ in zip(*finals))
+    # the generated kernels evaluate the program's own expressions: equal to rounding
+    for label, k in (("generated", 3), ("generated_lds", 4)):
+        out[label]["max_rel_diff_to_fused"] = max(
+            float((g.double() - f.double()).abs().max() / f.double().abs().max()) for f, g in zip(finals[0], finals[k]))
     del s, ic, finals
     torch.cuda.empty_cache()
     return out

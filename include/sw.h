@@ -163,12 +163,14 @@ sw_status sw_reset_time(sw_ctx *ctx, void *stream);
  * Measurements" of the paper (paper scheme, either dt mode); the first
  * sw_step that uses one allocates its workspace (six face planes of
  * (ny + 1) * pitch elements, or two AoS copies of a buffer), kept until
- * sw_destroy.  6 = generated: the kernel that the region-expression front
+ * sw_destroy.  6 = generated: a kernel that the region-expression front
  * end emits from the step written as whole-array statements (the paper's
  * contribution, sections "Region functions" and "Source-To-Source
- * Transformations"): inputs and face temporaries staged in LDS per tile, one
- * thread per cell; boundary values are filled by a separate launch after
- * each step (paper scheme, either dt mode).  Variants 2-5 give bitwise
+ * Transformations"), in one of two designs: a row march that keeps each
+ * array's rows in registers and shifts x neighbours across lanes (default),
+ * or the paper's own, inputs and face temporaries staged in LDS per tile
+ * with one thread per cell; boundary values are filled by a separate launch
+ * after each step (paper scheme, either dt mode).  Variants 2-5 give bitwise
  * identical states; the baseline and variant 6 agree with them up to
  * rounding order.
  * Errors: SW_EINVAL for an unknown variant; sw_step reports SW_ENOTSUP for a
@@ -185,8 +187,9 @@ typedef struct {
     int32_t variant;    /* 0 auto, 1 per-cell baseline, 2 fused, 3 temporal blocking, 4 unfused, 5 AoS,
                            6 generated from region expressions */
     int32_t rows;       /* fused, AoS: rows per tile (>= 1); blocked: steps per launch K (3, 5; 7 in SW_F32);
-                           generated: tile height 4, 8 or 16 (64 columns) */
-    int32_t vec;        /* fused: cells per lane; SW_F32: 1, 2 or 4, SW_F64: 1 or 2; blocked: waves per tile (4, 8, 12, 16) */
+                           generated: tile height 4, 8 or 16 (design 1) or rows per wave 4, 8, 16, 32 (design 2) */
+    int32_t vec;        /* fused: cells per lane; SW_F32: 1, 2 or 4, SW_F64: 1 or 2; blocked: waves per tile (4, 8, 12, 16);
+                           generated: design, 1 = LDS tiles (the paper's), 2 = row march in registers (default) */
     int32_t occupancy;  /* fused: register budget in waves per SIMD: 0 (compiler's choice), 3 or 4 */
     int32_t prefetch;   /* fused: rows loaded ahead of the row being updated: 1, 2 or 3 */
     int32_t order;      /* fused: tile order: 0 row-block-major per XCD, 1 vertically grouped per XCD, 2 plain */

@@ -175,7 +175,7 @@ sw_status enqueue_steps(sw_ctx *ctx, const sw_state *state, int nsteps, const Sw
         for (; n < nsteps; ++n) {
             SwLaunch b = launch_of(ctx, state, cur);
             b.step = n;
-            SW_HIP(sw_launch_rgn(b, tun.rows, s));
+            SW_HIP(sw_launch_rgn(b, tun.vec, tun.rows, s));
             SW_HIP(sw_launch_fill_halo(launch_of(ctx, state, cur ^ 1), s));
             cur ^= 1;
         }
@@ -367,13 +367,15 @@ sw_status resolve_tuning(const sw_ctx *ctx, const sw_tuning &in, SwTuning *out) 
         return SW_OK;
     }
     if (variant == 6) {
-        const int rows = in.rows ? in.rows : 8;
-        if (!sw_rgn_rows_supported(rows))
-            return fail(SW_EINVAL, "tuning: generated kernel has no %d-row tiles (4, 8 or 16)", rows);
-        if ((ctx->grid.ny + rows - 1) / rows > 65535)
+        const int design = in.vec ? in.vec : 2;
+        const int rows = in.rows ? in.rows : (design == 2 ? 16 : 8);
+        if (!sw_rgn_rows_supported(design, rows))
+            return fail(SW_EINVAL, "tuning: generated kernel has no design %d with %d rows (design 1: 4, 8 or 16; "
+                        "design 2: 4, 8, 16 or 32)", design, rows);
+        if (design == 1 && (ctx->grid.ny + rows - 1) / rows > 65535)
             return fail(SW_ENOTSUP, "tuning: %d rows exceed the generated kernel's 65535 tile rows of %d",
                         ctx->grid.ny, rows);
-        *out = SwTuning{6, rows, 0, 0, 0, 0};
+        *out = SwTuning{6, rows, design, 0, 0, 0};
         return SW_OK;
     }
     if (variant == 5) {

@@ -89,9 +89,10 @@ hipError_t sw_launch_aos_convert(int dtype, const void *const soa[3], void *aos,
 hipError_t sw_launch_aos_step(const SwLaunch &a, const void *in, void *out, int rows, hipStream_t s);
 // The step generated from region expressions (wave_advance.rgn): new
 // interior of `out` and the CFL epilogue; the halo is filled separately.
-// `rows`: tile height (64 columns), one of the instantiated heights.
-bool sw_rgn_rows_supported(int rows);
-hipError_t sw_launch_rgn(const SwLaunch &a, int rows, hipStream_t s);
+// design 1: LDS tiles of `rows` x 64 (one thread per cell); design 2: a
+// row march, `rows` rows per wave (registers and lane shifts, no LDS).
+bool sw_rgn_rows_supported(int design, int rows);
+hipError_t sw_launch_rgn(const SwLaunch &a, int design, int rows, hipStream_t s);
 
 // The instantiated launch shapes: (dtype, cells per lane, register budget,
 // prefetch depth).

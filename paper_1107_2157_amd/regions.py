@@ -613,6 +613,182 @@ def _emit(e, at, prog, boxes, env=None) -> str:
 
 
 TILE_ROWS = (4, 8, 16)      # tile heights the generated file instantiates (64 columns each)
+MARCH_ROWS = (4, 8, 16, 32)  # rows per wave of the row-march kernels
+
+
+# ---------------------------------------------------------------------------
+# Row-march code generation.
+#
+# The second design keeps no LDS tile: a wave owns a strip of 64 columns
+# (one lane per column) and walks up its rows.  Every array is placed in
+# output coordinates: array X's element e sits at output position
+# e - anchor(X), chosen so that its first read is at offset (0, 0).  A read
+# of X by a statement evaluated at output position k then sits at k + d
+# with d = read offset + anchor(reader) - anchor(X); d.x in {-1, 0, 1}
+# becomes a lane shift (DPP), d.y an index into X's ring of rows.  At march
+# row j every array holds its rows j + lo .. j + hi in registers (lo, hi =
+# the least and greatest d.y at which anything needs it) and computes only
+# row j + hi, in program order, so every value it reads is already there.
+# Lanes whose values depend on a shift across the wave's edge are invalid;
+# the strip's stored columns are the lanes valid for every output.
+
+@dataclass
+class MarchPlan:
+    anchor: dict          # array -> (ax, ay)
+    lo: dict              # array -> least row offset needed
+    hi: dict              # array -> greatest row offset needed
+    valid: dict           # array -> (first, last) valid lane
+    order: list           # arrays in evaluation order (inputs, then temporaries)
+    out_lanes: tuple      # (first, last) lane stored
+    warmup: int           # march rows before the first stored one
+
+
+def march_plan(prog: Program) -> MarchPlan:
+    anchor, dys = {}, {}
+    users = [(("store", v), e, (0, 0)) for v, e in prog.stores]
+
+    def visit(e, a_e, need):
+        for arr, (ox, oy) in reads(e):
+            if arr not in anchor:
+                anchor[arr] = (ox + a_e[0], oy + a_e[1])
+            d = (ox + a_e[0] - anchor[arr][0], oy + a_e[1] - anchor[arr][1])
+            if abs(d[0]) > 1:
+                raise RegionError(f"row march: a read of {arr} {d[0]} columns away (only -1, 0, 1)")
+            dys.setdefault(arr, set()).update(n + d[1] for n in need)
+
+    for _, e, a in users:
+        visit(e, a, {0})
+    for name, e in reversed(prog.temps):
+        if name not in anchor:
+            continue                                     # read by nothing
+        visit(e, anchor[name], dys[name])
+    order = [x for x in prog.inputs if x in anchor] + [t for t, _ in prog.temps if t in anchor]
+    lo = {x: min(dys[x]) for x in order}
+    hi = {x: max(dys[x]) for x in order}
+    valid = {x: (0, 63) for x in prog.inputs}
+
+    def lanes(e, a_e):
+        first, last = 0, 63
+        for arr, (ox, oy) in reads(e):
+            dx = ox + a_e[0] - anchor[arr][0]
+            f, l = valid[arr]
+            first, last = max(first, f - dx), min(last, l - dx)
+        return first, last
+
+    for name, e in prog.temps:
+        if name in anchor:
+            valid[name] = lanes(e, anchor[name])
+    out = (0, 63)
+    for _, e in prog.stores:
+        f, l = lanes(e, (0, 0))
+        out = (max(out[0], f), min(out[1], l))
+    if out[1] < out[0]:
+        raise RegionError("row march: no lane of a 64-lane strip is valid")
+    warmup = max(hi[x] - lo[x] for x in order)
+    return MarchPlan(anchor, lo, hi, valid, order, out, warmup)
+
+
+def _emit_march(e, plan: MarchPlan, prog: Program, a_e, row) -> str:
+    """C expression of e evaluated at output row offset `row` (relative to
+    the march row) for an expression anchored at a_e."""
+    if isinstance(e, Num):
+        return _c_num(e.value)
+    if isinstance(e, Sym):
+        return e.name
+    if isinstance(e, Region):
+        ax, ay = plan.anchor[e.array]
+        dx, dy = e.halo[0] + a_e[0] - ax, e.halo[2] + a_e[1] - ay
+        reg = f"r_{e.array}[{row + dy - plan.lo[e.array]}]"
+        return reg if dx == 0 else (f"rgn_next({reg})" if dx > 0 else f"rgn_prev({reg})")
+    if isinstance(e, Neg):
+        return f"(-{_emit_march(e.a, plan, prog, a_e, row)})"
+    if isinstance(e, Square):
+        return f"rgn_sq({_emit_march(e.a, plan, prog, a_e, row)})"
+    if isinstance(e, Bin):
+        return f"({_emit_march(e.a, plan, prog, a_e, row)} {e.op} {_emit_march(e.b, plan, prog, a_e, row)})"
+    if isinstance(e, Call):
+        el = prog.elementals[e.fn]
+        args = [_emit_march(x, plan, prog, a_e, row) for x in e.args]
+        args += list(free_scalars(prog, el.body, el.params))
+        return f"rgn_{e.fn}({', '.join(args)})"
+    raise TypeError(e)
+
+
+def _march_kernel(prog: Program, plan: MarchPlan) -> list:
+    L = []
+    w = L.append
+    first, last = plan.out_lanes
+    width = last - first + 1
+    order_out = {v: prog.outputs.index(prog.views[v][0]) for v, _ in prog.stores}
+    w(f"// Row march: a wave owns {width} output columns (lanes {first}..{last} of 64) and ROWS rows;")
+    w("// per array, rows j + lo .. j + hi of march row j in registers (anchor, lo, hi, valid lanes):")
+    for x in plan.order:
+        w(f"//   {x}: anchor {plan.anchor[x]}, rows {plan.lo[x]}..{plan.hi[x]}, lanes {plan.valid[x][0]}..{plan.valid[x][1]}")
+    w("template <typename T, int ROWS>")
+    w(f"__global__ __launch_bounds__(256) void k_rgn_{prog.name}_march(SwLaunch a, int nstrips, int nrb) {{")
+    w("    const int lane = threadIdx.x & 63;")
+    w("    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);")
+    w("    const int tile = (int)blockIdx.x * 4 + wave;")
+    w("    const int s = tile % nstrips, rb = tile / nstrips;")
+    w("    const int nx = a.nx, ny = a.ny;")
+    w("    const int64_t pitch = a.pitch;")
+    w("    const double dt_ = step_dt(a);")
+    scal = {"dt": "(T)dt_", "dx": "(T)a.dx", "dy": "(T)a.dy", "g": "(T)a.g"}
+    for sc in prog.scalars:
+        w(f"    const T {sc} = {scal[sc]};")
+    w("    double smax = 0.0;")
+    w("    bool bad = false;")
+    w("    if (rb < nrb) {")
+    w(f"        const int col = s * {width} + lane - {first};              // output column of this lane")
+    w(f"        const bool store_lane = lane >= {first} && lane <= {last} && col < nx;")
+    w("        const int j0 = rb * ROWS, j1 = min(j0 + ROWS, ny);")
+    for x in plan.order:
+        w(f"        T r_{x}[{plan.hi[x] - plan.lo[x] + 1}];")
+    for k, x in enumerate(prog.inputs):
+        if x not in plan.anchor:
+            continue
+        ax, ay = plan.anchor[x]
+        w(f"        const T *in_{x} = (const T *)a.in[{k}];")
+        w(f"        const int cx_{x} = min(max(col + {ax} - 1, -1), nx);   // element - 1: the cell, clamped to the halo")
+    w(f"        for (int j = j0 - {plan.warmup}; j < j1; ++j) {{")
+    w("            // shift every ring down one row")
+    for x in plan.order:
+        n = plan.hi[x] - plan.lo[x] + 1
+        if n > 1:
+            w(f"            for (int r = 0; r < {n - 1}; ++r) r_{x}[r] = r_{x}[r + 1];")
+    for k, x in enumerate(prog.inputs):
+        if x not in plan.anchor:
+            continue
+        ax, ay = plan.anchor[x]
+        top = plan.hi[x] - plan.lo[x]
+        w(f"            {{   // input {x}: row j + {plan.hi[x]}")
+        w(f"                const int cy = min(max(j + {plan.hi[x]} + {ay} - 1, -1), ny);")
+        w(f"                r_{x}[{top}] = in_{x}[(int64_t)cy * pitch + cx_{x}];")
+        w("            }")
+    for name, e in prog.temps:
+        if name not in plan.anchor:
+            continue
+        top = plan.hi[name] - plan.lo[name]
+        w(f"            r_{name}[{top}] = {_emit_march(e, plan, prog, plan.anchor[name], plan.hi[name])};")
+    w("            if (j >= j0) {")
+    outs = [None] * 3
+    for v, e in prog.stores:
+        outs[order_out[v]] = f"v_{v}"
+        w(f"                const T v_{v} = {_emit_march(e, plan, prog, (0, 0), 0)};")
+    w("                if (store_lane) {")
+    w("                    const int64_t o = (int64_t)j * pitch + col;")
+    for k in range(3):
+        w(f"                    ((T *)a.out[{k}])[o] = {outs[k]};")
+    w(f"                    const T sp = signal_speed(U3<T>{{{outs[0]}, {outs[1]}, {outs[2]}}}, (T)a.g);")
+    w("                    bad |= !(sp <= finite_max<T>());")
+    w("                    smax = fmax(smax, (double)sp);")
+    w("                }")
+    w("            }")
+    w("        }")
+    w("    }")
+    w("    step_epilogue(a, smax, bad, dt_, blockIdx.x == 0 && wave == 0, (int)blockIdx.x * 4 + wave);")
+    w("}")
+    return L
 
 
 def _kernel(prog: Program, tx: int, ty: int) -> list:
@@ -749,6 +925,43 @@ def generate(prog: Program, tx: int = 64, tile_rows=TILE_ROWS, source_name: str 
     for ty in tile_rows:
         w("")
         L.extend(_kernel(prog, tx, ty))
+    plan = march_plan(prog)
+    w("")
+    w("// x neighbours in the row march: the wave's edge lane receives 0 (it is never")
+    w("// a stored column), which lets the compiler fold the shift into its consumer.")
+    w("__device__ __forceinline__ float rgn_next(float x) {")
+    w("    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, true));")
+    w("}")
+    w("__device__ __forceinline__ float rgn_prev(float x) {")
+    w("    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, true));")
+    w("}")
+    w("__device__ __forceinline__ double rgn_next(double x) {")
+    w("    const long long v = __double_as_longlong(x);")
+    w("    const int lo = __builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, true);")
+    w("    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0x130, 0xf, 0xf, true);")
+    w("    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);")
+    w("}")
+    w("__device__ __forceinline__ double rgn_prev(double x) {")
+    w("    const long long v = __double_as_longlong(x);")
+    w("    const int lo = __builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, true);")
+    w("    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0x138, 0xf, 0xf, true);")
+    w("    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);")
+    w("}")
+    w("")
+    L.extend(_march_kernel(prog, plan))
+    w("")
+    width = plan.out_lanes[1] - plan.out_lanes[0] + 1
+    w(f"template <typename T> hipError_t launch_{prog.name}_march(const SwLaunch &a, int rows, hipStream_t s) {{")
+    w(f"    const int nstrips = (a.nx + {width - 1}) / {width};")
+    w("    const int nrb = (a.ny + rows - 1) / rows;")
+    w("    const int64_t blocks = ((int64_t)nstrips * nrb + 3) / 4;")
+    w("    if (blocks > 0x3fffffff) return hipErrorInvalidValue;")
+    for i, r in enumerate(MARCH_ROWS):
+        kw = "if" if i == 0 else "else if"
+        w(f"    {kw} (rows == {r}) k_rgn_{prog.name}_march<T, {r}><<<(unsigned)blocks, 256, 0, s>>>(a, nstrips, nrb);")
+    w(f"    else return hipErrorInvalidValue;")
+    w("    return hipGetLastError();")
+    w("}")
     w("")
     w(f"template <typename T> hipError_t launch_{prog.name}(const SwLaunch &a, int rows, hipStream_t s) {{")
     w(f"    const unsigned gx = (unsigned)((a.nx + {tx - 1}) / {tx});")
@@ -764,13 +977,18 @@ def generate(prog: Program, tx: int = 64, tile_rows=TILE_ROWS, source_name: str 
     w("")
     w("}  // namespace")
     w("")
-    w(f"// Tile heights instantiated: {', '.join(str(t) for t in tile_rows)}.")
-    w("bool sw_rgn_rows_supported(int rows) {")
-    w(f"    return {' || '.join(f'rows == {t}' for t in tile_rows)};")
+    w(f"// Designs: 1 = LDS tiles of {', '.join(str(t) for t in tile_rows)} rows; "
+      f"2 = row march of {', '.join(str(t) for t in MARCH_ROWS)} rows per wave.")
+    w("bool sw_rgn_rows_supported(int design, int rows) {")
+    w(f"    if (design == 1) return {' || '.join(f'rows == {t}' for t in tile_rows)};")
+    w(f"    if (design == 2) return {' || '.join(f'rows == {t}' for t in MARCH_ROWS)};")
+    w("    return false;")
     w("}")
     w("")
-    w("hipError_t sw_launch_rgn(const SwLaunch &a, int rows, hipStream_t s) {")
+    w("hipError_t sw_launch_rgn(const SwLaunch &a, int design, int rows, hipStream_t s) {")
     w("    if (a.scheme != 0) return hipErrorInvalidValue;")
+    w("    if (design == 2)")
+    w(f"        return a.dtype == 0 ? launch_{prog.name}_march<float>(a, rows, s) : launch_{prog.name}_march<double>(a, rows, s);")
     w(f"    return a.dtype == 0 ? launch_{prog.name}<float>(a, rows, s) : launch_{prog.name}<double>(a, rows, s);")
     w("}")
     return "\n".join(L) + "\n"

@@ -235,8 +235,9 @@ def test_full_size_blocked_and_comparison_variants():
     periodic with a fixed dt: the autotuner's fixed-dt choice (temporal
     blocking, K = 5), the fused kernel in the headline's tuned shape and the
     unfused and AoS steps give bitwise the same state after 12 steps (two
-    blocked launches and two single steps); the kernel generated from region
-    expressions matches oracle patches at sampled cells."""
+    blocked launches and two single steps); the kernels generated from region
+    expressions (row march and LDS tiles) match oracle patches at sampled
+    cells."""
     n, seed, k = 16384, ics.SEED_BUMPS_16384, 12
     announce(f"full size {n}^2 f32 periodic, fixed dt: blocked / fused / unfused / AoS / generated, {k} steps")
     st = ics.bumps_state(n, n, seed=seed, periodic=True, count=8, device="cuda")
@@ -256,20 +257,23 @@ def test_full_size_blocked_and_comparison_variants():
         s.step(k)
         assert all(torch.equal(s.interior(i), first[i]) for i in range(3)), tun
     del first
-    s.set_tuning(variant=sw.VARIANT_GENERATED)
-    s.state.cur = 0
-    s.set_state(*st)
-    s.reset_time()
-    s.step(k)
-    t, _, steps = s.sync_status()
-    assert steps == k and abs(t - k * dt) <= 1e-12 * k * dt
-    cells = sample_cells(n, n, np.random.default_rng(seed + 1), count=32, tile_rows=8, tile_cols=64,
+    cells = sample_cells(n, n, np.random.default_rng(seed + 1), count=32, tile_rows=8, tile_cols=62,
                          bumps=ics.draw_bumps(seed, n, n, count=8))
-    got = gpu_cells(s, cells)
+    got = {}
+    for design in (2, 1):                      # the row march (default) and the paper's LDS tiles
+        s.set_tuning(variant=sw.VARIANT_GENERATED, vec=design)
+        s.state.cur = 0
+        s.set_state(*st)
+        s.reset_time()
+        s.step(k)
+        t, _, steps = s.sync_status()
+        assert steps == k and abs(t - k * dt) <= 1e-12 * k * dt
+        got[design] = gpu_cells(s, cells)
     ref0 = rounded_state(st, "f32")
     del s, st
     torch.cuda.empty_cache()
     refs = [patch_reference(ref0, x, y, k, dt, True) for x, y in cells]
     ref = [np.array([r[f] for r in refs]) for f in range(3)]
-    err = compare(got, ref, "f32")
-    print(f"generated kernel: {len(cells)} sampled cells, rel max-norm {err:.2e}")
+    for design, g in got.items():
+        err = compare(g, ref, "f32")
+        print(f"generated kernel, design {design}: {len(cells)} sampled cells, rel max-norm {err:.2e}")
