@@ -79,6 +79,10 @@ sw_status resolve(const sw_batch *b, const sw_tuning &t, Resolved *r) {
     if (!sw_fused_supported((int)b->opts.dtype, r->vec, r->minw, r->pd))
         return sw_fail(SW_EINVAL, "batch tuning: vec %d / occupancy %d / prefetch %d not available", r->vec, r->minw,
                        r->pd);
+    for (int i = 0; i < b->n; ++i)   // the fused kernel reaches a tile's rows through 32-bit buffer offsets
+        if (!sw_fused_tile_fits(r->rows, b->lay[i].pitch, b->lay[i].elem_bytes))
+            return sw_fail(SW_EINVAL, "batch tuning: %d rows per tile of grid %d exceed the fused kernel's 2 GiB tile span",
+                           r->rows, i);
     return SW_OK;
 }
 
@@ -285,7 +289,7 @@ sw_status sw_batch_create(int32_t n, const sw_grid *grids, sw_halo halo, double 
     size_t at = 0;
     for (int i = 0; i < n; ++i) {
         b->off[i] = at;
-        at += 3 * align_up((size_t)lay[i].plane_elems * (size_t)lay[i].elem_bytes);
+        at += align_up((size_t)lay[i].buffer_elems * (size_t)lay[i].elem_bytes);   // three interleaved planes
     }
     b->region = at;
     hipError_t e = hipGetDevice(&b->device);
@@ -327,7 +331,7 @@ sw_status sw_batch_bind(sw_batch *b, void *arena) {
     b->arena = (char *)arena;
     std::vector<SwBatchGrid> d(b->n);
     for (int i = 0; i < b->n; ++i) {
-        const size_t pb = align_up((size_t)b->lay[i].plane_elems * (size_t)b->lay[i].elem_bytes);
+        const size_t pb = (size_t)b->lay[i].plane_offset * (size_t)b->lay[i].elem_bytes;
         for (int buf = 0; buf < 2; ++buf)
             for (int k = 0; k < 3; ++k)
                 d[i].plane[buf][k] = b->arena + buf * b->region + b->off[i] + k * pb +
@@ -349,7 +353,7 @@ sw_status sw_batch_view(const sw_batch *b, int32_t i, sw_state *view, sw_layout 
     if (!b || !view) return sw_fail(SW_EINVAL, "batch_view: NULL argument");
     if (i < 0 || i >= b->n) return sw_fail(SW_EINVAL, "batch_view: grid %d of %d", i, b->n);
     if (!b->arena) return sw_fail(SW_EINVAL, "batch_view: no arena bound");
-    const size_t pb = align_up((size_t)b->lay[i].plane_elems * (size_t)b->lay[i].elem_bytes);
+    const size_t pb = (size_t)b->lay[i].plane_offset * (size_t)b->lay[i].elem_bytes;
     for (int buf = 0; buf < 2; ++buf)
         for (int k = 0; k < 3; ++k) view->plane[buf][k] = b->arena + buf * b->region + b->off[i] + k * pb;
     view->cur = b->cur;

@@ -140,19 +140,25 @@ template <typename T> struct alignas(4 * sizeof(T)) V4 {
     T h, p, q, z;
 };
 
-// Whole planes (halo and padding included) between the two layouts.
+// Rows (halo and padding included) between the two layouts: element i of row
+// j is s[j * sp + i] in each plane and o[j * op + i] in the AoS array.
 template <typename T>
-__global__ __launch_bounds__(256) void k_to_aos(const T *h, const T *p, const T *q, V4<T> *o, int64_t n) {
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
-        o[t] = V4<T>{h[t], p[t], q[t], T(0)};
+__global__ __launch_bounds__(256) void k_to_aos(const T *h, const T *p, const T *q, int64_t sp, V4<T> *o, int64_t op,
+                                                int64_t row, int64_t n) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = t / row, i = t - j * row, so = j * sp + i;
+        o[j * op + i] = V4<T>{h[so], p[so], q[so], T(0)};
+    }
 }
 template <typename T>
-__global__ __launch_bounds__(256) void k_from_aos(const V4<T> *a, T *h, T *p, T *q, int64_t n) {
+__global__ __launch_bounds__(256) void k_from_aos(const V4<T> *a, int64_t op, T *h, T *p, T *q, int64_t sp, int64_t row,
+                                                  int64_t n) {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-        const V4<T> v = a[t];
-        h[t] = v.h;
-        p[t] = v.p;
-        q[t] = v.q;
+        const int64_t j = t / row, i = t - j * row, so = j * sp + i;
+        const V4<T> v = a[j * op + i];
+        h[so] = v.h;
+        p[so] = v.p;
+        q[so] = v.q;
     }
 }
 
@@ -306,19 +312,22 @@ hipError_t sw_launch_unfused(const SwLaunch &a, const SwFaces &f, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t sw_launch_aos_convert(int dtype, const void *const soa[3], void *aos, int64_t n, bool to_aos,
-                                 hipStream_t s) {
+hipError_t sw_launch_aos_convert(int dtype, const void *const soa[3], int64_t soa_pitch, void *aos, int64_t aos_pitch,
+                                 int64_t rows, bool to_aos, hipStream_t s) {
+    // each plane's row is aos_pitch elements: the AoS rows hold exactly one plane row
+    const int64_t row = aos_pitch, n = rows * row;
+    if (rows < 0 || row < 1 || soa_pitch < row) return hipErrorInvalidValue;
     const unsigned gb = grid_for(n);
     if (dtype == 0) {
-        if (to_aos) k_to_aos<float><<<gb, 256, 0, s>>>((const float *)soa[0], (const float *)soa[1],
-                                                         (const float *)soa[2], (V4<float> *)aos, n);
-        else k_from_aos<float><<<gb, 256, 0, s>>>((const V4<float> *)aos, (float *)soa[0], (float *)soa[1],
-                                                   (float *)soa[2], n);
+        const float *const *q = (const float *const *)soa;
+        if (to_aos) k_to_aos<float><<<gb, 256, 0, s>>>(q[0], q[1], q[2], soa_pitch, (V4<float> *)aos, aos_pitch, row, n);
+        else k_from_aos<float><<<gb, 256, 0, s>>>((const V4<float> *)aos, aos_pitch, (float *)soa[0], (float *)soa[1],
+                                                   (float *)soa[2], soa_pitch, row, n);
     } else {
-        if (to_aos) k_to_aos<double><<<gb, 256, 0, s>>>((const double *)soa[0], (const double *)soa[1],
-                                                          (const double *)soa[2], (V4<double> *)aos, n);
-        else k_from_aos<double><<<gb, 256, 0, s>>>((const V4<double> *)aos, (double *)soa[0], (double *)soa[1],
-                                                    (double *)soa[2], n);
+        const double *const *q = (const double *const *)soa;
+        if (to_aos) k_to_aos<double><<<gb, 256, 0, s>>>(q[0], q[1], q[2], soa_pitch, (V4<double> *)aos, aos_pitch, row, n);
+        else k_from_aos<double><<<gb, 256, 0, s>>>((const V4<double> *)aos, aos_pitch, (double *)soa[0],
+                                                    (double *)soa[1], (double *)soa[2], soa_pitch, row, n);
     }
     return hipGetLastError();
 }

@@ -80,6 +80,10 @@ int sw_fused_default_vec(int dtype, int nx) {
     return nx >= 2048 ? 4 : (nx >= 512 ? 2 : 1);
 }
 
+bool sw_fused_tile_fits(int rows, int64_t pitch, int elem_bytes) {
+    return rows >= 1 && ((int64_t)rows + 2) * pitch * (int64_t)elem_bytes <= 0x7fffffff;
+}
+
 bool sw_fused_supported(int dtype, int vec, int minw, int pd) {
 #define SW_FUSED_SUP(T, V, M, P) \
     if ((dtype == 1) == (sizeof(T) == 8) && vec == V && minw == M && pd == P) return true;

@@ -69,6 +69,9 @@ int sw_tb_tile_rows(int dtype, int k);   // output rows per blocked tile (one gr
 hipError_t sw_launch_tb(const SwLaunch &a, int k, int waves, hipStream_t s);
 int sw_fused_default_vec(int dtype, int nx);
 bool sw_fused_supported(int dtype, int vec, int minw, int pd);
+// A fused tile of `rows` rows (plus its two halo rows) of `pitch`-element rows
+// fits the kernel's 32-bit buffer offsets.
+bool sw_fused_tile_fits(int rows, int64_t pitch, int elem_bytes);
 
 // The paper's comparison designs (paper scheme only).  Unfused: face states
 // of the first half-step in HBM planes, x face i of row j at x[k][j * pitch
@@ -80,12 +83,13 @@ struct SwFaces {
     int64_t pitch;
 };
 hipError_t sw_launch_unfused(const SwLaunch &a, const SwFaces &f, hipStream_t s);
-// AoS: whole planes (halo and padding included, n elements) converted
-// between the three SoA planes and one array of (h, hu, hv, 0) vectors; the
-// step reads and writes such arrays (`in`, `out` point at interior cell
-// (0, 0), same pitch as the planes).
-hipError_t sw_launch_aos_convert(int dtype, const void *const soa[3], void *aos, int64_t n, bool to_aos,
-                                 hipStream_t s);
+// AoS: `rows` rows of `row` elements (halo and padding included) converted
+// between the three SoA planes (row stride soa_pitch) and one array of
+// (h, hu, hv, 0) vectors (row stride aos_pitch); the step reads and writes
+// such arrays (`in`, `out` point at interior cell (0, 0); a.pitch is the AoS
+// row stride).
+hipError_t sw_launch_aos_convert(int dtype, const void *const soa[3], int64_t soa_pitch, void *aos, int64_t aos_pitch,
+                                 int64_t rows, bool to_aos, hipStream_t s);
 hipError_t sw_launch_aos_step(const SwLaunch &a, const void *in, void *out, int rows, hipStream_t s);
 // The step generated from region expressions (wave_advance.rgn): new
 // interior of `out` and the CFL epilogue; the halo is filled separately.

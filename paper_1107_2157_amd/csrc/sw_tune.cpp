@@ -121,8 +121,10 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
                     if (sw_tb_supported((int)opts.dtype, k)) cands.push_back(sw_tuning{3, k, waves, 0, 0, 0});
     }
 
-    // save buf[cur] (whole planes, halo included) and the time scalars
-    const size_t plane_bytes = (size_t)lay.plane_elems * (size_t)lay.elem_bytes;
+    // save buf[cur] (every row of each plane, halo included) and the time scalars
+    const size_t eb = (size_t)lay.elem_bytes, row_bytes = (size_t)lay.plane_offset * eb;
+    const size_t pitch_bytes = (size_t)lay.pitch * eb, nrows = (size_t)grid.ny + 2;
+    const size_t plane_bytes = row_bytes * nrows;
     void *backup = nullptr, *scal_backup = nullptr;
     if (hipMalloc(&backup, 3 * plane_bytes) != hipSuccess) return SW_ENOMEM;
     if (hipMalloc(&scal_backup, scal_bytes) != hipSuccess) {
@@ -132,8 +134,8 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
     const int cur0 = state->cur;
     auto save = [&]() -> hipError_t {
         for (int k = 0; k < 3; ++k) {
-            hipError_t e = hipMemcpyAsync((char *)backup + k * plane_bytes, state->plane[cur0][k], plane_bytes,
-                                          hipMemcpyDeviceToDevice, s);
+            hipError_t e = hipMemcpy2DAsync((char *)backup + k * plane_bytes, row_bytes, state->plane[cur0][k],
+                                            pitch_bytes, row_bytes, nrows, hipMemcpyDeviceToDevice, s);
             if (e != hipSuccess) return e;
         }
         return hipMemcpyAsync(scal_backup, scal, scal_bytes, hipMemcpyDeviceToDevice, s);
@@ -141,8 +143,8 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
     auto restore = [&]() -> hipError_t {
         state->cur = cur0;
         for (int k = 0; k < 3; ++k) {
-            hipError_t e = hipMemcpyAsync(state->plane[cur0][k], (char *)backup + k * plane_bytes, plane_bytes,
-                                          hipMemcpyDeviceToDevice, s);
+            hipError_t e = hipMemcpy2DAsync(state->plane[cur0][k], pitch_bytes, (char *)backup + k * plane_bytes,
+                                            row_bytes, row_bytes, nrows, hipMemcpyDeviceToDevice, s);
             if (e != hipSuccess) return e;
         }
         return hipMemcpyAsync(scal, scal_backup, scal_bytes, hipMemcpyDeviceToDevice, s);

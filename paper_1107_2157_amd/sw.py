@@ -51,7 +51,8 @@ class Opts(ctypes.Structure):
 
 class Layout(ctypes.Structure):
     _fields_ = [("pitch", ctypes.c_int64), ("origin", ctypes.c_int64),
-                ("plane_elems", ctypes.c_int64), ("elem_bytes", ctypes.c_int32),
+                ("plane_elems", ctypes.c_int64), ("plane_offset", ctypes.c_int64),
+                ("buffer_elems", ctypes.c_int64), ("elem_bytes", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 
@@ -192,13 +193,13 @@ class Solver:
         self.ctx = ctx
         self.layout = Layout()
         check(lib().sw_get_layout(ctx, ctypes.byref(self.layout)), "sw_get_layout")
-        n = self.layout.plane_elems
-        self.planes = [[torch.zeros(n, dtype=self.torch_dtype, device=device) for _ in range(3)]
-                       for _ in range(2)]
+        # one allocation per buffer; the rows of its three planes interleave
+        L = self.layout
+        self.buffers = [torch.zeros(L.buffer_elems, dtype=self.torch_dtype, device=device) for _ in range(2)]
         self.state = State()
         for b in range(2):
             for k in range(3):
-                self.state.plane[b][k] = self.planes[b][k].data_ptr()
+                self.state.plane[b][k] = self.buffers[b].data_ptr() + k * L.plane_offset * L.elem_bytes
         self.state.cur = 0
         if variant != VARIANT_AUTO:
             self.set_variant(variant)
@@ -216,8 +217,8 @@ class Solver:
         """(ny + 2, nx + 2) strided view of plane k (0 h, 1 hu, 2 hv) with its halo."""
         b = self.state.cur if buf is None else buf
         L = self.layout
-        return torch.as_strided(self.planes[b][k], (self.ny + 2, self.nx + 2), (L.pitch, 1),
-                                L.origin - L.pitch - 1)
+        return torch.as_strided(self.buffers[b], (self.ny + 2, self.nx + 2), (L.pitch, 1),
+                                k * L.plane_offset + L.origin - L.pitch - 1)
 
     def interior(self, k: int, buf: int | None = None) -> torch.Tensor:
         return self.halo_view(k, buf)[1:-1, 1:-1]

@@ -32,10 +32,15 @@ def test_layout_rules():
             L = sw.layout_query(nx, 7, dtype)
             assert L.elem_bytes == eb
             assert (L.origin * eb) % 256 == 0 and (L.pitch * eb) % 256 == 0
-            assert L.pitch >= nx + 2 + (256 // eb) - 1          # left ghost + interior + right ghost
-            assert (L.origin - 1) % L.pitch + nx + 1 < L.pitch  # right ghost inside the row
-            assert L.plane_elems == L.pitch * 9
-            assert (L.pitch * eb) % 65536 != 0
+            row = L.plane_offset
+            assert L.pitch == 3 * row                           # rows of h, hu, hv interleave
+            assert (row * eb) % 256 == 0
+            assert row >= nx + 2 + (256 // eb) - 1              # left ghost + interior + right ghost
+            assert (L.origin - 1) % L.pitch + nx + 1 < row      # right ghost inside the plane's row
+            assert L.buffer_elems == L.pitch * 9
+            assert L.plane_elems == L.pitch * 8 + row           # plane 2 ends where the buffer ends
+            assert 2 * row + L.plane_elems == L.buffer_elems
+            assert (row * eb) % 65536 != 0
 
 
 @pytest.mark.parametrize("nx,ny,dtype", [(0, 5, 0), (5, 0, 0), (-3, 4, 1), (5, 5, 7), (2 ** 21 + 1, 4, 1),

@@ -135,6 +135,50 @@ def test_fused_tunings_bitwise_identical():
         assert ran >= 30
 
 
+def test_fused_tile_span_limit():
+    """The fused kernel reaches a tile's rows through 32-bit buffer offsets.
+    On the widest grid (nx = 2^21, FP64: 50 MB from one row of a plane to the
+    next, three planes interleaved) 40 rows per tile fit below 2 GiB and 41
+    are refused when the shape is chosen."""
+    s = sw.Solver(2 ** 21, 1, dtype="f64")
+    assert s.layout.pitch * 8 * 42 <= 2 ** 31 - 1 < s.layout.pitch * 8 * 43
+    s.set_tuning(variant=sw.VARIANT_FUSED, rows=40)
+    with pytest.raises(sw.SwError) as e:
+        s.set_tuning(variant=sw.VARIANT_FUSED, rows=41)
+    assert e.value.status == sw.EINVAL
+
+
+@pytest.mark.parametrize("variant", [sw.VARIANT_FUSED, sw.VARIANT_TBLOCK, sw.VARIANT_UNFUSED, sw.VARIANT_AOS,
+                                     sw.VARIANT_GENERATED])
+def test_separate_plane_allocations_step_like_interleaved(variant):
+    """The library's layout interleaves the rows of h, hu and hv in one
+    allocation per buffer; planes placed in six separate allocations of
+    plane_elems elements each are stepped to bitwise the same state."""
+    nx, ny = 300, 77
+    st = ics.bumps_state(nx, ny, seed=33, periodic=False, count=4)
+    dt = 0.1 if variant == sw.VARIANT_TBLOCK else 0.0
+    kw = dict(dtype="f32", bc_x=sw.PERIODIC, bc_y=sw.REFLECT, cfl=0.0 if dt else 0.5, dt_fixed=dt)
+    announce(f"separate planes variant={variant}")
+    a = sw.Solver(nx, ny, variant=variant, **kw)
+    b = sw.Solver(nx, ny, variant=variant, **kw)
+    L = b.layout
+    planes = [[torch.zeros(L.plane_elems, dtype=torch.float32, device="cuda") for _ in range(3)] for _ in range(2)]
+    for buf in range(2):
+        for k in range(3):
+            b.state.plane[buf][k] = planes[buf][k].data_ptr()
+
+    def halo_view(k, buf=None):
+        p = planes[b.state.cur if buf is None else buf][k]
+        return torch.as_strided(p, (ny + 2, nx + 2), (L.pitch, 1), L.origin - L.pitch - 1)
+    b.halo_view = halo_view
+    for s in (a, b):
+        s.set_state(*st)
+        s.step(11)
+    for x, y in zip(a.get_state(halo=True), b.get_state(halo=True)):
+        assert torch.equal(x, y)
+    assert a.sync_status() == b.sync_status()
+
+
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_restart_and_checkpoint_are_bitwise(variant, dtype):
