@@ -320,8 +320,9 @@ def run_surrogate(sw, ics, torch, n=256, size=256, nsteps=64):
     ref, t_solver = surrogate.solver_run(u0, nsteps)
     gate = dict(mass_rel_tol=1e-4, project_mass=True)
     b = sw.Batch([(size, size)] * n, dtype="f32")
-    surrogate.rollout(net, u0, nsteps, gate, batch=b)                       # warm
-    got, fb, t_sur = surrogate.rollout(net, u0, nsteps, gate, batch=b)
+    fbs = torch.zeros(n, dtype=torch.int32, device="cuda")
+    surrogate.rollout(net, u0, nsteps, gate, batch=b, fallbacks=fbs)        # warm: captures the rollout's graph
+    got, fb, t_sur = surrogate.rollout(net, u0, nsteps, gate, batch=b, fallbacks=fbs)
     e, e_strict = surrogate.rel_l2_h(got[:, 0], ref[:, 0])
     p, _ = surrogate.rel_l2_h(u0[:, 0], ref[:, 0])
     l2 = torch.zeros(n, dtype=torch.float64, device="cuda")

@@ -364,9 +364,15 @@ sw_status sw_surrogate_train_step(sw_net *net, const float *u, const float *u8, 
  * step count and unstable flag, and its fallbacks entry is set to nsteps / jump.  The first
  * judged call on a batch allocates the solver's copy (about the batch's arena
  * size), kept until the network is destroyed or judges another batch.
- * No host sync. */
+ * Without the judge, the rollout is captured once into a hipGraph per
+ * (batch, its tuning and binding, current buffer, nsteps, gate, fallbacks)
+ * and replayed on later calls (kept up to 8 per network; sw_surrogate_set_norm
+ * drops them); the judged rollout is launched eagerly.  No host sync. */
 sw_status sw_surrogate_advance(sw_net *net, sw_batch *solver, int32_t nsteps, const sw_gate *gate,
                                int32_t *fallbacks, double *l2, void *stream);
+/* 1 (default): unjudged rollouts replay captured graphs; 0: eager launches.
+ * Results are identical either way.  Errors: SW_EINVAL for a NULL network. */
+sw_status sw_surrogate_set_graph(sw_net *net, int32_t enable);
 
 const char *sw_strerror(sw_status status);
 const char *sw_last_error_detail(void);

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -48,6 +49,7 @@ struct sw_batch {
     int ntiles = 0;
     int table_rows = -1, table_vec = -1, table_order = -1;
     bool use_graph = true;
+    uint64_t gen = 0;                 // renewed whenever launch arguments change (bind, tile table)
     hipStream_t cap = nullptr;
     struct Graph {
         int nsteps, cur;
@@ -60,6 +62,11 @@ struct sw_batch {
 namespace {
 
 constexpr size_t kAlign = 256;
+
+// Process-wide source of batch generations: a graph captured by another
+// object over a batch's launches is valid while the batch's generation is
+// unchanged (a batch created later at the same address gets a new one).
+std::atomic<uint64_t> g_next_gen{1};
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -128,6 +135,7 @@ sw_status build_tiles(sw_batch *b, const Resolved &r) {
     }
     BHIP(hipMemcpy(b->d_tiles, tiles.data(), total * sizeof(SwBatchTile), hipMemcpyHostToDevice));
     b->ntiles = (int)total;
+    b->gen = g_next_gen.fetch_add(1);
     b->table_rows = r.rows;
     b->table_vec = r.vec;
     b->table_order = r.order;
@@ -199,7 +207,16 @@ int sw_batch_internal_info(const sw_batch *b, SwBatchInfo *info) {
     info->same_ny = b->grids[0].ny;
     for (auto &g : b->grids)
         if (g.nx != info->same_nx || g.ny != info->same_ny) info->same_nx = info->same_ny = -1;
+    info->gen = b->gen;
     return SW_OK;
+}
+
+int sw_batch_internal_prepare(sw_batch *b) {
+    sw_status st = check_bound(b);
+    if (st != SW_OK) return st;
+    Resolved r;
+    if ((st = resolve(b, b->tuning, &r)) != SW_OK) return st;
+    return build_tiles(b, r);
 }
 
 int sw_batch_internal_step_masked(sw_batch *b, int nsteps, const int32_t *active, hipStream_t s) {
@@ -329,6 +346,7 @@ sw_status sw_batch_bind(sw_batch *b, void *arena) {
     BHIP(hipGetDevice(&dev));
     if (dev != b->device) BHIP(hipSetDevice(b->device));
     b->arena = (char *)arena;
+    b->gen = g_next_gen.fetch_add(1);
     std::vector<SwBatchGrid> d(b->n);
     for (int i = 0; i < b->n; ++i) {
         const size_t pb = (size_t)b->lay[i].plane_offset * (size_t)b->lay[i].elem_bytes;

@@ -58,8 +58,12 @@ struct SwBatchInfo {
     SwBatchScalars *d_sc;
     int n, cur, dtype, bc_x, bc_y;
     int same_nx, same_ny;          // common grid size, or -1 if sizes differ
+    uint64_t gen;                  // changes whenever the batch's launch arguments do
 };
 int sw_batch_internal_info(const sw_batch *b, SwBatchInfo *info);   // returns sw_status
+// Resolve the tuning and build the tile table now (it allocates and copies
+// synchronously), so that later enqueues only launch kernels.
+int sw_batch_internal_prepare(sw_batch *b);
 // Eager: reset, prologue and nsteps steps for the grids with active[g] != 0
 // (device array), starting from the current buffer.  Does not flip the
 // batch's current buffer (nsteps must be even).

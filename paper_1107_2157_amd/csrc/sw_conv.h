@@ -38,9 +38,11 @@ struct SwNorm {
 // target (u8 - u) / out_scale as FP32 [B][H][W][4].
 hipError_t sw_sur_prep_dense(const float *u, const float *u8, int B, int H, int W, int bc_x, int bc_y, SwNorm nrm,
                              void *x0, float *target, hipStream_t s);
-// Batch planes (current buffer, halo filled) of grids [0, B) -> X0.
+// Batch planes (current buffer, halo filled) of grids [0, B) -> X0; clears
+// the gate statistics st[0, B) of the jump (struct SwGateStats below).
+struct SwGateStats;
 hipError_t sw_sur_prep_planes(const SwBatchGrid *grids, int cur, int B, int H, int W, SwNorm nrm, void *x0,
-                              hipStream_t s);
+                              SwGateStats *st, hipStream_t s);
 // MSE loss over the three channels: per-block partial sums into partial[nblocks],
 // and dZ = 2 (pred - target) / (3 B H W) as BF16 NHWC with halo, 8 channels.
 hipError_t sw_sur_loss(const float *pred, const float *target, int B, int H, int W, float *partial, int nblocks,
@@ -83,12 +85,11 @@ struct SwGateStats {
 hipError_t sw_sur_delta_sum(const float *delta, int B, int H, int W, SwGateStats *st, hipStream_t s);
 hipError_t sw_sur_apply(const float *delta, const SwBatchGrid *grids, int cur, int B, int H, int W, SwNorm nrm,
                         int project, int bcx, int bcy, SwGateStats *st, hipStream_t s);
-hipError_t sw_sur_gate(SwGateStats *st, int B, double mass_tol, double hmin, int *active, int *fallbacks,
-                       hipStream_t s);
-// Rejected grids (active != 0): copy U^n (buffer cur, halos included) over
-// the prediction in buffer cur ^ 1, where the solver then takes the jump.
-hipError_t sw_sur_restore(const SwBatchGrid *grids, int cur, int B, int H, int W, const int *active, hipStream_t s);
-hipError_t sw_sur_zero_stats(SwGateStats *st, int B, hipStream_t s);
+// The gate's verdict per grid (active[b] = 1 and fallbacks[b] += 1 for a
+// rejected jump); rejected grids get U^n (buffer cur, halos included) copied
+// over the prediction in buffer cur ^ 1, where the solver then takes the jump.
+hipError_t sw_sur_gate_restore(const SwBatchGrid *grids, int cur, int B, int H, int W, SwGateStats *st,
+                               double mass_tol, double hmin, int *active, int *fallbacks, hipStream_t s);
 
 // Judge: per grid, relative L2(h) of the rollout (batch grids `a`, current
 // buffer cur_a) against the plain solver's run (`ref`, buffer cur_ref); grids

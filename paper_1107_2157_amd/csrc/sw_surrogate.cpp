@@ -52,6 +52,19 @@ struct sw_net {
     SwNorm nrm{};
     int64_t adam_t = 0;
     std::vector<void *> allocs;
+    // unjudged rollouts replay one hipGraph per (batch and its generation,
+    // start buffer, nsteps, gate, fallbacks array), captured on the first call
+    bool use_graph = true;
+    hipStream_t cap = nullptr;
+    struct Graph {
+        const sw_batch *solver;
+        uint64_t gen;
+        int cur, nsteps;
+        sw_gate gate;
+        const int32_t *fallbacks;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
 };
 
 namespace {
@@ -66,6 +79,11 @@ sw_status dalloc(sw_net *n, void **p, size_t bytes) {
 }
 
 size_t act_bytes(const sw_net *n, int B, int ch) { return (size_t)B * (n->H + 2) * (n->W + 2) * ch * 2; }
+
+void drop_graphs(sw_net *n) {
+    for (auto &g : n->graphs) (void)hipGraphExecDestroy(g.exec);
+    n->graphs.clear();
+}
 
 sw_status use_dev(const sw_net *n) {
     int d = -1;
@@ -253,6 +271,9 @@ sw_status sw_surrogate_create(const sw_net_cfg *cfg, int32_t H, int32_t W, int32
 
 sw_status sw_surrogate_destroy(sw_net *n) {
     if (!n) return SW_OK;
+    (void)use_dev(n);
+    drop_graphs(n);
+    if (n->cap) (void)hipStreamDestroy(n->cap);
     drop_shadow(n);
     for (void *p : n->allocs) (void)hipFree(p);
     delete n;
@@ -275,6 +296,14 @@ sw_status sw_surrogate_set_norm(sw_net *n, const float in_offset[3], const float
         n->nrm.in_scale[c] = in_scale[c];
         n->nrm.out_scale[c] = out_scale[c];
     }
+    drop_graphs(n);   // captured rollouts hold the old values
+    return SW_OK;
+}
+
+sw_status sw_surrogate_set_graph(sw_net *n, int32_t enable) {
+    if (!n) return sw_fail(SW_EINVAL, "surrogate_set_graph: NULL network");
+    n->use_graph = enable != 0;
+    if (!n->use_graph) drop_graphs(n);
     return SW_OK;
 }
 
@@ -336,6 +365,36 @@ sw_status sw_surrogate_train_step(sw_net *n, const float *u, const float *u8, in
     return relayout(n, s);
 }
 
+namespace {
+// The rollout's launches on stream s (no host sync, no allocation once the
+// batch is prepared): halo fill, then per jump the network step, the gate, the
+// restore of rejected grids and their masked solver steps.  Leaves the batch's
+// current buffer at the final state.
+sw_status enqueue_rollout(sw_net *n, sw_batch *solver, const SwBatchInfo &bi, int32_t nsteps, const sw_gate *gate,
+                          int32_t *fallbacks, hipStream_t s) {
+    const int B = bi.n;
+    int cur = bi.cur;
+    sw_status st;
+    if ((st = sw_batch_fill_halo(solver, s)) != SW_OK) return st;
+    for (int j = 0; j < nsteps / n->cfg.jump; ++j) {
+        // U^n in buffer cur; every grid's U^{n+jump} ends in buffer cur ^ 1
+        SHIP(sw_sur_prep_planes(bi.d_grids, cur, B, n->H, n->W, n->nrm, n->x0, n->stats, s));
+        if ((st = forward(n, B, false, s)) != SW_OK) return st;
+        if (gate->project_mass) SHIP(sw_sur_delta_sum(n->delta, B, n->H, n->W, n->stats, s));
+        SHIP(sw_sur_apply(n->delta, bi.d_grids, cur, B, n->H, n->W, n->nrm, gate->project_mass, bi.bc_x, bi.bc_y,
+                          n->stats, s));
+        // the gate; rejected grids: U^n over the prediction, then the plain solver takes the jump (an
+        // even number of steps, so it ends where it started); accepted grids keep the prediction
+        SHIP(sw_sur_gate_restore(bi.d_grids, cur, B, n->H, n->W, n->stats, gate->mass_rel_tol, gate->hmin, n->active,
+                                 fallbacks, s));
+        cur ^= 1;
+        if ((st = (sw_status)sw_batch_internal_set_cur(solver, cur)) != SW_OK) return st;
+        if ((st = (sw_status)sw_batch_internal_step_masked(solver, n->cfg.jump, n->active, s)) != SW_OK) return st;
+    }
+    return SW_OK;
+}
+}  // namespace
+
 sw_status sw_surrogate_advance(sw_net *n, sw_batch *solver, int32_t nsteps, const sw_gate *gate,
                                int32_t *fallbacks, double *l2, void *stream) {
     if (!n || !solver || !gate) return sw_fail(SW_EINVAL, "surrogate_advance: NULL argument");
@@ -353,38 +412,62 @@ sw_status sw_surrogate_advance(sw_net *n, sw_batch *solver, int32_t nsteps, cons
     if (gate->judge && !(gate->l2_tol >= 0)) return sw_fail(SW_EINVAL, "surrogate_advance: l2_tol %g", gate->l2_tol);
     hipStream_t s = (hipStream_t)stream;
     const int B = bi.n;
-    int cur = bi.cur;
     if (gate->judge) {   // the plain solver's copy of U^n, and the books at the start
         if (n->shadow && !sw_batch_internal_compatible(n->shadow, solver)) drop_shadow(n);
         if (!n->shadow && (st = (sw_status)sw_batch_internal_clone(solver, &n->shadow, &n->shadow_arena)) != SW_OK)
             return st;
         if ((st = (sw_status)sw_batch_internal_copy_state(n->shadow, solver, s)) != SW_OK) return st;
         SHIP(sw_sur_judge_begin(bi.d_sc, B, n->judge, s));
-    }
-    if ((st = sw_batch_fill_halo(solver, stream)) != SW_OK) return st;
-    for (int j = 0; j < nsteps / n->cfg.jump; ++j) {
-        // U^n in buffer cur; every grid's U^{n+jump} ends in buffer cur ^ 1
-        SHIP(sw_sur_prep_planes(bi.d_grids, cur, B, n->H, n->W, n->nrm, n->x0, s));
-        if ((st = forward(n, B, false, s)) != SW_OK) return st;
-        SHIP(sw_sur_zero_stats(n->stats, B, s));
-        if (gate->project_mass) SHIP(sw_sur_delta_sum(n->delta, B, n->H, n->W, n->stats, s));
-        SHIP(sw_sur_apply(n->delta, bi.d_grids, cur, B, n->H, n->W, n->nrm, gate->project_mass, bi.bc_x, bi.bc_y,
-                          n->stats, s));
-        SHIP(sw_sur_gate(n->stats, B, gate->mass_rel_tol, gate->hmin, n->active, fallbacks, s));
-        // rejected grids: U^n over the prediction, then the plain solver takes the jump (an even
-        // number of steps, so it ends where it started); accepted grids keep the prediction
-        SHIP(sw_sur_restore(bi.d_grids, cur, B, n->H, n->W, n->active, s));
-        cur ^= 1;
-        if ((st = (sw_status)sw_batch_internal_set_cur(solver, cur)) != SW_OK) return st;
-        if ((st = (sw_status)sw_batch_internal_step_masked(solver, n->cfg.jump, n->active, s)) != SW_OK) return st;
-    }
-    if (gate->judge) {   // the plain solver over the same span, then the verdict per grid
+        if ((st = enqueue_rollout(n, solver, bi, nsteps, gate, fallbacks, s)) != SW_OK) return st;
+        // the plain solver over the same span, then the verdict per grid
         if ((st = sw_batch_step(n->shadow, nsteps, stream)) != SW_OK) return st;
         SwBatchInfo si;
         if ((st = (sw_status)sw_batch_internal_info(n->shadow, &si)) != SW_OK) return st;
-        SHIP(sw_sur_judge(bi.d_grids, cur, si.d_grids, si.cur, B, n->H, n->W, n->judge, bi.d_sc, si.d_sc,
+        SwBatchInfo now;
+        if ((st = (sw_status)sw_batch_internal_info(solver, &now)) != SW_OK) return st;
+        SHIP(sw_sur_judge(bi.d_grids, now.cur, si.d_grids, si.cur, B, n->H, n->W, n->judge, bi.d_sc, si.d_sc,
                           gate->l2_tol, nsteps / n->cfg.jump, n->reject, fallbacks, l2, s));
+        return SW_OK;
     }
+    if (!n->use_graph || nsteps == 0) return enqueue_rollout(n, solver, bi, nsteps, gate, fallbacks, s);
+    // graph replay: everything the launches bake in is part of the key
+    if ((st = (sw_status)sw_batch_internal_prepare(solver)) != SW_OK) return st;
+    if ((st = (sw_status)sw_batch_internal_info(solver, &bi)) != SW_OK) return st;
+    hipGraphExec_t exec = nullptr;
+    for (auto &g : n->graphs)
+        if (g.solver == solver && g.gen == bi.gen && g.cur == bi.cur && g.nsteps == nsteps && g.fallbacks == fallbacks &&
+            g.gate.mass_rel_tol == gate->mass_rel_tol && g.gate.hmin == gate->hmin &&
+            (g.gate.project_mass != 0) == (gate->project_mass != 0))
+            exec = g.exec;
+    if (exec) {
+        const int njumps = nsteps / n->cfg.jump;
+        if ((st = (sw_status)sw_batch_internal_set_cur(solver, bi.cur ^ (njumps & 1))) != SW_OK) return st;
+    } else {
+        if (n->graphs.size() >= 8) drop_graphs(n);
+        if (!n->cap) SHIP(hipStreamCreateWithFlags(&n->cap, hipStreamNonBlocking));
+        SHIP(hipStreamBeginCapture(n->cap, hipStreamCaptureModeThreadLocal));
+        st = enqueue_rollout(n, solver, bi, nsteps, gate, fallbacks, n->cap);   // leaves the batch's final buffer current
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(n->cap, &graph);
+        if (st != SW_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)sw_batch_internal_set_cur(solver, bi.cur);
+            return st;
+        }
+        if (e != hipSuccess) {
+            (void)sw_batch_internal_set_cur(solver, bi.cur);
+            return sw_fail(SW_EHIP, "surrogate_advance: capture: %s", hipGetErrorString(e));
+        }
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            (void)sw_batch_internal_set_cur(solver, bi.cur);
+            return sw_fail(SW_EHIP, "surrogate_advance: instantiate: %s", hipGetErrorString(e));
+        }
+        sw_net::Graph g{solver, bi.gen, bi.cur, nsteps, *gate, fallbacks, exec};
+        n->graphs.push_back(g);
+    }
+    SHIP(hipGraphLaunch(exec, s));
     return SW_OK;
 }
 

@@ -74,10 +74,21 @@ __global__ __launch_bounds__(256) void k_prep_dense(const float *u, const float 
     }
 }
 
+// Network input of a jump from every grid's buffer cur; also clears the
+// jump's gate statistics (st, one entry per grid) for the kernels after the
+// network.
 __global__ __launch_bounds__(256) void k_prep_planes(const SwBatchGrid *grids, int cur, int B, int H, int W, SwNorm nrm,
-                                                     __bf16 *x0) {
+                                                     __bf16 *x0, SwGateStats *st) {
     const int Wp = W + 2, Hp = H + 2;
     const int64_t n = (int64_t)B * Hp * Wp;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid < B) {
+        st[gid].mass_old = 0.0;
+        st[gid].mass_new = 0.0;
+        st[gid].dh_sum = 0.0;
+        st[gid].hmin = 3.0e38f;
+        st[gid].nonfinite = 0u;
+    }
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
         const int b = (int)(idx / ((int64_t)Hp * Wp));
         const int r = (int)(idx - (int64_t)b * Hp * Wp);
@@ -349,25 +360,19 @@ __global__ void k_relayout(const float *master, const SwLayerDesc *layers, int n
     if (L.wd) reinterpret_cast<__bf16 *>(L.wd)[(int64_t)ci * L.kpd + (8 - tap) * L.cdp + co] = (__bf16)w;
 }
 
-__global__ void k_zero_stats(SwGateStats *st, int B) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    st[b].mass_old = 0.0;
-    st[b].mass_new = 0.0;
-    st[b].dh_sum = 0.0;
-    st[b].hmin = 3.0e38f;
-    st[b].nonfinite = 0u;
-}
-
-// Per grid (blockIdx.y): sum of the normalised dh over its pixels.
+// Per grid (blockIdx.y): sum of the normalised dh over its pixels (one
+// atomic per block: the four waves' sums are added in LDS first).
 __global__ __launch_bounds__(256) void k_delta_sum(const float *delta, int H, int W, SwGateStats *st) {
+    __shared__ double s_acc[4];
     const int b = blockIdx.y;
     const int64_t n = (int64_t)H * W;
     double acc = 0.0;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
         acc += delta[((int64_t)b * n + p) * 4];
     acc = wave_sum_d(acc);
-    if ((threadIdx.x & 63) == 0) atomicAdd(&st[b].dh_sum, acc);
+    if ((threadIdx.x & 63) == 0) s_acc[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(&st[b].dh_sum, (s_acc[0] + s_acc[1]) + (s_acc[2] + s_acc[3]));
 }
 
 __global__ __launch_bounds__(256) void k_apply(const float *delta, const SwBatchGrid *grids, int cur, int H, int W,
@@ -401,30 +406,44 @@ __global__ __launch_bounds__(256) void k_apply(const float *delta, const SwBatch
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) hmin = fminf(hmin, __shfl_xor(hmin, o));
     const unsigned long long anybad = __ballot(bad);
+    // the four waves' partial results meet in LDS: one set of atomics per block
+    __shared__ double s_mo[4], s_mn[4];
+    __shared__ float s_hmin[4];
+    __shared__ int s_bad[4];
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&st[b].mass_old, mo);
-        atomicAdd(&st[b].mass_new, mn);
+        s_mo[w] = mo;
+        s_mn[w] = mn;
+        s_hmin[w] = hmin;
+        s_bad[w] = anybad != 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&st[b].mass_old, (s_mo[0] + s_mo[1]) + (s_mo[2] + s_mo[3]));
+        atomicAdd(&st[b].mass_new, (s_mn[0] + s_mn[1]) + (s_mn[2] + s_mn[3]));
+        const float hm = fminf(fminf(s_hmin[0], s_hmin[1]), fminf(s_hmin[2], s_hmin[3]));
         // min over non-negative values by integer order; a non-positive depth is recorded as 0
-        atomicMin(reinterpret_cast<int *>(&st[b].hmin), __float_as_int(hmin > 0.f ? hmin : 0.f));
-        if (anybad) atomicOr(&st[b].nonfinite, 1u);
+        atomicMin(reinterpret_cast<int *>(&st[b].hmin), __float_as_int(hm > 0.f ? hm : 0.f));
+        if (s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3]) atomicOr(&st[b].nonfinite, 1u);
     }
 }
 
-__global__ void k_gate(SwGateStats *st, int B, double mass_tol, double hmin, int *active, int *fallbacks) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    const SwGateStats s = st[b];
-    const double drift = fabs(s.mass_new - s.mass_old) / fabs(s.mass_old);
-    const int reject = !(drift <= mass_tol) || !((double)s.hmin > hmin) || s.nonfinite != 0u;
-    st[b].fallback = reject;
-    active[b] = reject;
-    if (fallbacks) fallbacks[b] += reject;
-}
-
-// Rejected grids: copy the whole halo'd rectangle of buffer cur into cur ^ 1.
-__global__ __launch_bounds__(256) void k_restore(const SwBatchGrid *grids, int cur, int H, int W, const int *active) {
+// Per grid (blockIdx.y): the gate's verdict on the jump from its statistics
+// (mass drift, least depth, non-finite values; every block derives it, block
+// 0 records it in active, st and fallbacks), then for a rejected grid the
+// whole halo'd rectangle of buffer cur copied into cur ^ 1.
+__global__ __launch_bounds__(256) void k_gate_restore(const SwBatchGrid *grids, int cur, int H, int W, SwGateStats *st,
+                                                      double mass_tol, double hmin, int *active, int *fallbacks) {
     const int b = blockIdx.y;
-    if (!active[b]) return;
+    const double mass_old = st[b].mass_old, mass_new = st[b].mass_new;
+    const double drift = fabs(mass_new - mass_old) / fabs(mass_old);
+    const int reject = !(drift <= mass_tol) || !((double)st[b].hmin > hmin) || st[b].nonfinite != 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st[b].fallback = reject;
+        active[b] = reject;
+        if (fallbacks) fallbacks[b] += reject;
+    }
+    if (!reject) return;
     const SwBatchGrid &g = grids[b];
     const int64_t n = (int64_t)(H + 2) * (W + 2);
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
@@ -516,8 +535,9 @@ hipError_t sw_sur_prep_dense(const float *u, const float *u8, int B, int H, int 
 }
 
 hipError_t sw_sur_prep_planes(const SwBatchGrid *grids, int cur, int B, int H, int W, SwNorm nrm, void *x0,
-                              hipStream_t s) {
-    k_prep_planes<<<grid_for((int64_t)B * (H + 2) * (W + 2)), 256, 0, s>>>(grids, cur, B, H, W, nrm, (__bf16 *)x0);
+                              SwGateStats *st, hipStream_t s) {
+    // every grid's statistics entry needs a thread: the grid covers B threads at least
+    k_prep_planes<<<grid_for((int64_t)B * (H + 2) * (W + 2)), 256, 0, s>>>(grids, cur, B, H, W, nrm, (__bf16 *)x0, st);
     return hipGetLastError();
 }
 
@@ -583,33 +603,31 @@ hipError_t sw_sur_relayout(const float *master, const SwLayerDesc *layers, int n
     return hipGetLastError();
 }
 
-hipError_t sw_sur_zero_stats(SwGateStats *st, int B, hipStream_t s) {
-    k_zero_stats<<<(B + 255) / 256, 256, 0, s>>>(st, B);
-    return hipGetLastError();
+// Blocks per grid of the per-grid passes: up to one element per thread for
+// small batches (their few grids would otherwise leave most CUs idle and
+// walk the pixels serially), 64 per grid from 256 grids up.
+unsigned per_grid_blocks(int64_t n, int B) {
+    const int cap = B >= 256 ? 64 : std::max(64, 16384 / std::max(B, 1));
+    return grid_for(n, cap);
 }
 
 hipError_t sw_sur_delta_sum(const float *delta, int B, int H, int W, SwGateStats *st, hipStream_t s) {
-    dim3 grid(grid_for((int64_t)H * W, 64), B);
+    dim3 grid(per_grid_blocks((int64_t)H * W, B), B);
     k_delta_sum<<<grid, 256, 0, s>>>(delta, H, W, st);
     return hipGetLastError();
 }
 
 hipError_t sw_sur_apply(const float *delta, const SwBatchGrid *grids, int cur, int B, int H, int W, SwNorm nrm,
                         int project, int bcx, int bcy, SwGateStats *st, hipStream_t s) {
-    dim3 grid(grid_for((int64_t)H * W, 64), B);
+    dim3 grid(per_grid_blocks((int64_t)H * W, B), B);
     k_apply<<<grid, 256, 0, s>>>(delta, grids, cur, H, W, nrm, project, bcx, bcy, st);
     return hipGetLastError();
 }
 
-hipError_t sw_sur_gate(SwGateStats *st, int B, double mass_tol, double hmin, int *active, int *fallbacks,
-                       hipStream_t s) {
-    k_gate<<<(B + 255) / 256, 256, 0, s>>>(st, B, mass_tol, hmin, active, fallbacks);
-    return hipGetLastError();
-}
-
-hipError_t sw_sur_restore(const SwBatchGrid *grids, int cur, int B, int H, int W, const int *active, hipStream_t s) {
-    dim3 grid(grid_for((int64_t)(H + 2) * (W + 2), 64), B);
-    k_restore<<<grid, 256, 0, s>>>(grids, cur, H, W, active);
+hipError_t sw_sur_gate_restore(const SwBatchGrid *grids, int cur, int B, int H, int W, SwGateStats *st,
+                               double mass_tol, double hmin, int *active, int *fallbacks, hipStream_t s) {
+    dim3 grid(per_grid_blocks((int64_t)(H + 2) * (W + 2), B), B);
+    k_gate_restore<<<grid, 256, 0, s>>>(grids, cur, H, W, st, mass_tol, hmin, active, fallbacks);
     return hipGetLastError();
 }
 

@@ -94,15 +94,17 @@ def rel_l2_h(h, h_ref):
 
 
 def rollout(net, u0: torch.Tensor, nsteps: int, gate: dict | None = None, l2: torch.Tensor | None = None,
-            batch: "sw.Batch | None" = None):
+            batch: "sw.Batch | None" = None, fallbacks: torch.Tensor | None = None):
     """Surrogate rollout of a dense [n][3][H][W] state: returns (final state,
     fallbacks per grid, seconds).  gate: keyword arguments of
     ``Surrogate.advance`` (judge mode writes ``l2``); ``batch`` reuses a batch
-    of the right shape."""
+    of the right shape and ``fallbacks`` an int32 counter array (zeroed here):
+    with both reused, repeated calls replay the rollout's captured graph."""
     n, _, H, W = u0.shape
     b = batch if batch is not None else sw.Batch([(W, H)] * n, dtype="f32")
     b.load(u0)
-    fb = torch.zeros(n, dtype=torch.int32, device="cuda")
+    fb = fallbacks if fallbacks is not None else torch.zeros(n, dtype=torch.int32, device="cuda")
+    fb.zero_()
     gate = gate or {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -136,6 +136,7 @@ SIGNATURES = {
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sw_surrogate_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                                ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p]),
+    "sw_surrogate_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "sw_surrogate_advance": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Gate),
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sw_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -479,6 +480,10 @@ class Surrogate:
         f3 = ctypes.c_float * 3
         check(lib().sw_surrogate_set_norm(self.handle, f3(*in_offset), f3(*in_scale), f3(*out_scale)),
               "sw_surrogate_set_norm")
+
+    def set_graph(self, enable: bool):
+        """Unjudged rollouts replay captured graphs (True, the default) or launch eagerly."""
+        check(lib().sw_surrogate_set_graph(self.handle, 1 if enable else 0), "sw_surrogate_set_graph")
 
     def forward(self, u: torch.Tensor) -> torch.Tensor:
         """u: [B][3][H][W] FP32 on the GPU -> normalised delta [B][H][W][4]."""

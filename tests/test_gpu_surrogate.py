@@ -235,3 +235,74 @@ def test_binding_rejects_mismatched_tensors():
         b.load(torch.zeros(2, 3, 40, 64))
     with pytest.raises(ValueError):
         b.load(torch.zeros(1, 3, 40, 64, device="cuda"))
+
+
+def _rollout_runs(net, b, u0, nsteps, gate, graph, reps):
+    """reps rollouts from u0 (time and step counters cleared) through one
+    fallbacks array: (state, fallbacks, solver steps taken, simulated time)
+    of each, with eager work (a forward pass, copies) and synchronisations
+    between the calls."""
+    net.set_graph(graph)
+    fb = torch.zeros(b.n, dtype=torch.int32, device="cuda")
+    out = []
+    for _ in range(reps):
+        b.load(u0)
+        b.reset_time()
+        fb.zero_()
+        net.advance(b, nsteps, fallbacks=fb, **gate)
+        state = b.export()
+        t, steps, _ = b.sync_status()
+        out.append((state, fb.clone(), list(steps), list(t)))
+        net.forward(u0)
+        torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("case", ["accepted", "rejected"])
+def test_graph_replays_equal_eager_rollouts(case):
+    """Unjudged rollouts are captured into a hipGraph on the first call and
+    replayed afterwards; every replay gives bitwise the eager rollout's
+    state, fallback counts, solver step counts and time, both when the
+    network's jumps are accepted (trained weights) and when every jump is
+    rejected (a forced mass drift), so that the masked solver steps run
+    inside the graph."""
+    if case == "accepted":
+        n, nsteps = 2, 32
+        net, _ = surrogate.load_weights(surrogate.WEIGHTS_256, n)
+        u0 = surrogate.initial_states(n, 256, 256, ics.SEED_SURR_EVAL0)
+        gate = dict(mass_rel_tol=1e-4, project_mass=True)
+    else:
+        n, nsteps = 3, 24
+        u0 = states(n, 64, 64, 71)
+        net = sw.Surrogate(64, 64, n, jump=8, seed=3)
+        p = net.get_params()
+        p[-3] += 1.0
+        net.set_params(p)
+        gate = dict(project_mass=False)
+    H, W = u0.shape[2], u0.shape[3]
+    announce(f"surrogate graph replays {case}")
+    b = sw.Batch([(W, H)] * n, dtype="f32")
+    (ref, fb_ref, steps_ref, t_ref), = _rollout_runs(net, b, u0, nsteps, gate, graph=False, reps=1)
+    assert fb_ref.tolist() == ([0] * n if case == "accepted" else [nsteps // 8] * n)
+    assert steps_ref == ([0] * n if case == "accepted" else [nsteps] * n)
+    for state, fb, steps, t in _rollout_runs(net, b, u0, nsteps, gate, graph=True, reps=4):
+        assert torch.equal(state, ref)
+        assert torch.equal(fb, fb_ref) and steps == steps_ref and t == t_ref
+
+
+def test_set_norm_drops_captured_rollouts():
+    """The normalisation is baked into a captured rollout by value: after
+    set_norm the next rollout is captured anew and equals the eager rollout
+    under the new normalisation."""
+    n, H, W, nsteps = 2, 64, 64, 16
+    u0 = states(n, H, W, 81)
+    net = sw.Surrogate(H, W, n, jump=8, seed=2)
+    b = sw.Batch([(W, H)] * n, dtype="f32")
+    gate = dict(mass_rel_tol=10.0, project_mass=True)
+    net.set_norm(OFF, SCALE, (0.01, 0.01, 0.01))
+    (a_graph, *_), = _rollout_runs(net, b, u0, nsteps, gate, graph=True, reps=1)
+    net.set_norm(OFF, SCALE, (0.03, 0.02, 0.02))
+    (b_graph, *_), = _rollout_runs(net, b, u0, nsteps, gate, graph=True, reps=1)
+    (b_eager, *_), = _rollout_runs(net, b, u0, nsteps, gate, graph=False, reps=1)
+    assert torch.equal(b_graph, b_eager)
+    assert not torch.equal(a_graph, b_graph)
