@@ -162,3 +162,37 @@ def test_tile_ranges_of_hoisted_temporaries():
     assert boxes["fu__H_U"] == (0, 66, 1, 9)      # read at the x faces only: the tile's rows
     assert boxes["gv__H_V"] == (1, 65, 0, 10)     # read at the y faces only: the tile's columns
     assert boxes["fu__Hx_Ux"] == (0, 65, 0, 8)
+
+
+def test_march_plan_of_the_shipped_program():
+    """The row-march analysis of the (hoisted) step, against what the
+    one-cell stencil implies: the inputs are read one row below and above
+    the stored row (a ring of three rows, two warm-up rows), the x-face
+    arrays only on the stored row; an x face i needs the cell i + 1, so it is
+    valid on lanes 0..62, and a stored cell needs the faces on both sides
+    (lanes 1..62: 62 of 64 columns per strip)."""
+    m = regions.march_plan(regions.hoist(regions.load()))
+    for a in ("H", "U", "V"):
+        assert (m.lo[a], m.hi[a], m.valid[a]) == (-1, 1, (0, 63))
+    for a in ("Hx", "Ux", "Vx"):
+        assert (m.lo[a], m.hi[a], m.valid[a]) == (0, 0, (0, 62))
+    for a in ("Hy", "Uy", "Vy"):
+        assert (m.lo[a], m.hi[a]) == (-1, 0)       # the y faces below and above a stored row
+    assert m.out_lanes == (1, 62) and m.warmup == 2
+    assert m.order[:3] == ["H", "U", "V"]          # inputs first, then temporaries in program order
+    src = regions.generate(regions.load())
+    assert "k_rgn_wave_advance_march" in src
+
+
+def test_march_rejects_reads_two_columns_away():
+    """A well-formed program that stores H shifted one column left plus a
+    temporary reading H one column right (every region nx wide) is valid
+    region arithmetic, but it reads H two columns apart, and the row march
+    shifts across lanes by one column at most: the planner says so."""
+    text = (HEAD + "wa = [0, 2, 1, 1]\nwb = [2, 0, 1, 1]\nnone = [0, 0, 0, 0]\n"
+            + "Hx = region_cpy(H, wb)\n"
+            + TAIL.replace("pH = region_cpy(H, interior)\n", "pH = region_cpy(H, wa) + region_cpy(Hx, none)\n"))
+    prog = regions.parse(text)
+    assert prog.arrays["Hx"] == (0, 0)
+    with pytest.raises(regions.RegionError, match="only -1, 0, 1"):
+        regions.march_plan(prog)
