@@ -204,7 +204,8 @@ typedef struct {
     int32_t vec;        /* fused: cells per lane; SW_F32: 1, 2 or 4, SW_F64: 1 or 2; blocked: waves per tile (4, 8, 12, 16);
                            generated: design, 1 = LDS tiles (the paper's), 2 = row march in registers (default) */
     int32_t occupancy;  /* fused: register budget in waves per SIMD: 0 (compiler's choice), 3 or 4 */
-    int32_t prefetch;   /* fused: rows loaded ahead of the row being updated: 1, 2 or 3 */
+    int32_t prefetch;   /* fused, generated row march: rows loaded ahead of the row being updated: 1, 2 or 3
+                           (defaults: fused 2, row march 1); generated LDS tiles: 0 */
     int32_t order;      /* fused: tile order: 0 row-block-major per XCD, 1 vertically grouped per XCD, 2 plain */
 } sw_tuning;
 

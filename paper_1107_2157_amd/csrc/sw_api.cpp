@@ -191,7 +191,7 @@ sw_status enqueue_steps(sw_ctx *ctx, const sw_state *state, int nsteps, const Sw
         for (; n < nsteps; ++n) {
             SwLaunch b = launch_of(ctx, state, cur);
             b.step = n;
-            SW_HIP(sw_launch_rgn(b, tun.vec, tun.rows, s));
+            SW_HIP(sw_launch_rgn(b, tun.vec, tun.rows, tun.pd, s));
             SW_HIP(sw_launch_fill_halo(launch_of(ctx, state, cur ^ 1), s));
             cur ^= 1;
         }
@@ -373,6 +373,8 @@ sw_status sw_get_layout(const sw_ctx *ctx, sw_layout *out) {
 }
 
 namespace {
+constexpr int kRgnDefaultPrefetch = 1;   // generated row march: input rows loaded ahead by default
+
 // Resolve defaults; returns SW_OK or an error for unsupported settings.
 sw_status resolve_tuning(const sw_ctx *ctx, const sw_tuning &in, SwTuning *out) {
     int variant = in.variant;
@@ -393,7 +395,12 @@ sw_status resolve_tuning(const sw_ctx *ctx, const sw_tuning &in, SwTuning *out) 
         if (design == 1 && (ctx->grid.ny + rows - 1) / rows > 65535)
             return fail(SW_ENOTSUP, "tuning: %d rows exceed the generated kernel's 65535 tile rows of %d",
                         ctx->grid.ny, rows);
-        *out = SwTuning{6, rows, design, 0, 0, 0};
+        // row march: input rows loaded ahead of the row being updated (1 = none beyond the ring)
+        const int pf = design == 2 ? (in.prefetch ? in.prefetch : kRgnDefaultPrefetch) : in.prefetch;
+        if (design == 2 ? (pf < 1 || pf > 3) : pf != 0)
+            return fail(SW_EINVAL, "tuning: generated design %d takes prefetch %s", design,
+                        design == 2 ? "1, 2 or 3" : "0");
+        *out = SwTuning{6, rows, design, 0, pf, 0};
         return SW_OK;
     }
     if (variant == 5) {

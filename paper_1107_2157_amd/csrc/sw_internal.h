@@ -94,9 +94,10 @@ hipError_t sw_launch_aos_step(const SwLaunch &a, const void *in, void *out, int 
 // The step generated from region expressions (wave_advance.rgn): new
 // interior of `out` and the CFL epilogue; the halo is filled separately.
 // design 1: LDS tiles of `rows` x 64 (one thread per cell); design 2: a
-// row march, `rows` rows per wave (registers and lane shifts, no LDS).
+// row march, `rows` rows per wave (registers and lane shifts, no LDS) with
+// `prefetch` input rows loaded ahead of the row being updated (1-3; design 1: 0).
 bool sw_rgn_rows_supported(int design, int rows);
-hipError_t sw_launch_rgn(const SwLaunch &a, int design, int rows, hipStream_t s);
+hipError_t sw_launch_rgn(const SwLaunch &a, int design, int rows, int prefetch, hipStream_t s);
 
 // The instantiated launch shapes: (dtype, cells per lane, register budget,
 // prefetch depth).

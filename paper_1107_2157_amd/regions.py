@@ -614,6 +614,7 @@ def _emit(e, at, prog, boxes, env=None) -> str:
 
 TILE_ROWS = (4, 8, 16)      # tile heights the generated file instantiates (64 columns each)
 MARCH_ROWS = (4, 8, 16, 32)  # rows per wave of the row-march kernels
+MARCH_PREFETCH = (1, 2, 3)   # input rows loaded ahead of the row being updated
 
 
 # ---------------------------------------------------------------------------
@@ -724,11 +725,16 @@ def _march_kernel(prog: Program, plan: MarchPlan) -> list:
     w("// per array, rows j + lo .. j + hi of march row j in registers (anchor, lo, hi, valid lanes):")
     for x in plan.order:
         w(f"//   {x}: anchor {plan.anchor[x]}, rows {plan.lo[x]}..{plan.hi[x]}, lanes {plan.valid[x][0]}..{plan.valid[x][1]}")
-    w("template <typename T, int ROWS>")
+    w("// PF input rows beyond the ring are loaded ahead into p_<array> (PF = 0: each")
+    w("// row is loaded in the iteration that first reads it).  Tiles: block b runs")
+    w("// on XCD b % 8 and every XCD takes a contiguous run of the row-block-major")
+    w("// tile sequence, so tiles sharing warm-up rows meet in the same L2.")
+    w("template <typename T, int ROWS, int PF>")
     w(f"__global__ __launch_bounds__(256) void k_rgn_{prog.name}_march(SwLaunch a, int nstrips, int nrb) {{")
     w("    const int lane = threadIdx.x & 63;")
     w("    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);")
-    w("    const int tile = (int)blockIdx.x * 4 + wave;")
+    w("    const int per_xcd = gridDim.x >> 3;                  // the grid is a multiple of 8 blocks")
+    w("    const int tile = (((int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3)) << 2) + wave;")
     w("    const int s = tile % nstrips, rb = tile / nstrips;")
     w("    const int nx = a.nx, ny = a.ny;")
     w("    const int64_t pitch = a.pitch;")
@@ -750,6 +756,13 @@ def _march_kernel(prog: Program, plan: MarchPlan) -> list:
         ax, ay = plan.anchor[x]
         w(f"        const T *in_{x} = (const T *)a.in[{k}];")
         w(f"        const int cx_{x} = min(max(col + {ax} - 1, -1), nx);   // element - 1: the cell, clamped to the halo")
+        w(f"        T p_{x}[PF > 0 ? PF : 1];")
+        w("        if constexpr (PF > 0) {")
+        w("            for (int k = 0; k < PF; ++k) {")
+        w(f"                const int cy = min(max(j0 - {plan.warmup} + {plan.hi[x]} + k + {ay} - 1, -1), ny);")
+        w(f"                p_{x}[k] = in_{x}[(int64_t)cy * pitch + cx_{x}];")
+        w("            }")
+        w("        }")
     w(f"        for (int j = j0 - {plan.warmup}; j < j1; ++j) {{")
     w("            // shift every ring down one row")
     for x in plan.order:
@@ -761,7 +774,12 @@ def _march_kernel(prog: Program, plan: MarchPlan) -> list:
             continue
         ax, ay = plan.anchor[x]
         top = plan.hi[x] - plan.lo[x]
-        w(f"            {{   // input {x}: row j + {plan.hi[x]}")
+        w(f"            if constexpr (PF > 0) {{   // input {x}: row j + {plan.hi[x]} from the prefetch ring")
+        w(f"                r_{x}[{top}] = p_{x}[0];")
+        w(f"                for (int k = 0; k + 1 < PF; ++k) p_{x}[k] = p_{x}[k + 1];")
+        w(f"                const int cy = min(max(j + {plan.hi[x]} + PF + {ay} - 1, -1), ny);")
+        w(f"                p_{x}[PF - 1] = in_{x}[(int64_t)cy * pitch + cx_{x}];")
+        w("            } else {")
         w(f"                const int cy = min(max(j + {plan.hi[x]} + {ay} - 1, -1), ny);")
         w(f"                r_{x}[{top}] = in_{x}[(int64_t)cy * pitch + cx_{x}];")
         w("            }")
@@ -896,7 +914,9 @@ def generate(prog: Program, tx: int = 64, tile_rows=TILE_ROWS, source_name: str 
     """HIP source of the tile kernels for `prog`: one per tile height in
     `tile_rows` (tiles of tx x rows outputs, one thread each; with
     `optimize`, elemental calls on shifted regions are hoisted into
-    temporaries first), and the launcher sw_launch_rgn(a, rows, stream).
+    temporaries first), the row-march kernels (rows per wave x input rows
+    loaded ahead), and the launcher sw_launch_rgn(a, design, rows,
+    prefetch, stream).
     The runtime around the translated statements (dt from the device-side
     CFL ring, the signal-speed reduction and sticky flag of the step
     epilogue) expects the outputs in the order h, hu, hv."""
@@ -951,14 +971,19 @@ def generate(prog: Program, tx: int = 64, tile_rows=TILE_ROWS, source_name: str 
     L.extend(_march_kernel(prog, plan))
     w("")
     width = plan.out_lanes[1] - plan.out_lanes[0] + 1
-    w(f"template <typename T> hipError_t launch_{prog.name}_march(const SwLaunch &a, int rows, hipStream_t s) {{")
+    w(f"template <typename T> hipError_t launch_{prog.name}_march(const SwLaunch &a, int rows, int prefetch, hipStream_t s) {{")
     w(f"    const int nstrips = (a.nx + {width - 1}) / {width};")
     w("    const int nrb = (a.ny + rows - 1) / rows;")
-    w("    const int64_t blocks = ((int64_t)nstrips * nrb + 3) / 4;")
-    w("    if (blocks > 0x3fffffff) return hipErrorInvalidValue;")
-    for i, r in enumerate(MARCH_ROWS):
-        kw = "if" if i == 0 else "else if"
-        w(f"    {kw} (rows == {r}) k_rgn_{prog.name}_march<T, {r}><<<(unsigned)blocks, 256, 0, s>>>(a, nstrips, nrb);")
+    w("    int64_t blocks = ((int64_t)nstrips * nrb + 3) / 4;")
+    w("    blocks = (blocks + 7) / 8 * 8;                   // whole runs per XCD; the extra tiles are idle")
+    w("    if (blocks > 0x1fffffff) return hipErrorInvalidValue;   // 4 * blocks tile indices fit an int")
+    first = True
+    for r in MARCH_ROWS:
+        for p in MARCH_PREFETCH:
+            kw = "if" if first else "else if"
+            first = False
+            w(f"    {kw} (rows == {r} && prefetch == {p}) "
+              f"k_rgn_{prog.name}_march<T, {r}, {p - 1}><<<(unsigned)blocks, 256, 0, s>>>(a, nstrips, nrb);")
     w(f"    else return hipErrorInvalidValue;")
     w("    return hipGetLastError();")
     w("}")
@@ -985,10 +1010,12 @@ def generate(prog: Program, tx: int = 64, tile_rows=TILE_ROWS, source_name: str 
     w("    return false;")
     w("}")
     w("")
-    w("hipError_t sw_launch_rgn(const SwLaunch &a, int design, int rows, hipStream_t s) {")
+    w("hipError_t sw_launch_rgn(const SwLaunch &a, int design, int rows, int prefetch, hipStream_t s) {")
     w("    if (a.scheme != 0) return hipErrorInvalidValue;")
     w("    if (design == 2)")
-    w(f"        return a.dtype == 0 ? launch_{prog.name}_march<float>(a, rows, s) : launch_{prog.name}_march<double>(a, rows, s);")
+    w(f"        return a.dtype == 0 ? launch_{prog.name}_march<float>(a, rows, prefetch, s)")
+    w(f"                            : launch_{prog.name}_march<double>(a, rows, prefetch, s);")
+    w("    if (prefetch != 0) return hipErrorInvalidValue;")
     w(f"    return a.dtype == 0 ? launch_{prog.name}<float>(a, rows, s) : launch_{prog.name}<double>(a, rows, s);")
     w("}")
     return "\n".join(L) + "\n"

@@ -72,23 +72,27 @@ def test_generated_edge_shapes(shape, bc, design):
     assert rel_maxnorm(got, (H, U, V)) <= TOL["f64"], shape
 
 
-@pytest.mark.parametrize("design,rows", [(1, 4), (1, 16), (2, 4), (2, 32)])
-def test_generated_tile_heights(design, rows):
-    """Every instantiated tile height (LDS design) or march length (row
-    march) gives the same bits as the default shape of its design."""
+@pytest.mark.parametrize("design,rows,prefetch", [(1, 4, 0), (1, 16, 0), (2, 4, 2), (2, 8, 3), (2, 16, 1),
+                                                 (2, 32, 3)])
+def test_generated_tile_heights(design, rows, prefetch):
+    """Every instantiated tile height (LDS design) or march length and
+    input prefetch depth (row march) gives the same bits as the default
+    shape of its design."""
     nx, ny = 150, 70
     st = ics.random_state(nx, ny, seed=71, amp_h=0.2, amp_m=0.04)
     ref, _, _ = run(st, 9, "f32", (sw.PERIODIC, sw.REFLECT), sw.VARIANT_GENERATED, design=design)
     h, hu, hv = (rounded(a, "f32") for a in st)
     s = sw.Solver(nx, ny, g=G, dtype="f32", bc_x=sw.PERIODIC, bc_y=sw.REFLECT)
-    s.set_tuning(variant=sw.VARIANT_GENERATED, rows=rows, vec=design)
+    s.set_tuning(variant=sw.VARIANT_GENERATED, rows=rows, vec=design, prefetch=prefetch)
+    assert s.get_tuning()["prefetch"] == (prefetch or 0)
     s.set_state(h, hu, hv)
     s.step(9)
     for a, b in zip(s.get_state(halo=True), ref):
         assert torch.equal(a, b)
-    with pytest.raises(sw.SwError) as e:
-        s.set_tuning(variant=sw.VARIANT_GENERATED, rows=5)
-    assert e.value.status == sw.EINVAL
+    for bad in (dict(rows=5), dict(prefetch=4 if design == 2 else 1)):
+        with pytest.raises(sw.SwError) as e:
+            s.set_tuning(variant=sw.VARIANT_GENERATED, vec=design, **bad)
+        assert e.value.status == sw.EINVAL
 
 
 def test_generated_refused_for_the_transverse_scheme():
