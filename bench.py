@@ -391,7 +391,35 @@ def cpu_baseline(name, ics):
     sec = time.perf_counter() - t0
     return {"value": n * nrows * k / sec / 1e9, "unit": "Gcell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{n}x{nrows} band of the same initial state, periodic, FP64, {k} steps, {sec:.1f} s, "
-                      f"single thread"}
+                      f"single thread",
+            "all_cores": cpu_all_cores(h, hu, hv, k)}
+
+
+def cpu_all_cores(h, hu, hv, k):
+    """The same oracle, unchanged and single-threaded, in one child process
+    per host core (at most the 16-core share of one GPU), each stepping its
+    own copy of the band k steps at once: aggregate cell-updates / wall time.
+    The children import only numpy and the oracle."""
+    import subprocess
+    import tempfile
+    import numpy as np
+    procs = min(16, len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "16")))
+    code = ("import sys, numpy as np; sys.path.insert(0, sys.argv[1]); import oracle; "
+            "h, hu, hv = (np.load(sys.argv[2] + f'/{c}.npy') for c in 'huv'); "
+            "oracle.run(h, hu, hv, int(sys.argv[3]), bcx=oracle.PERIODIC, bcy=oracle.PERIODIC)")
+    with tempfile.TemporaryDirectory() as d:
+        for c, a in zip("huv", (h, hu, hv)):
+            np.save(os.path.join(d, f"{c}.npy"), np.ascontiguousarray(a))
+        t0 = time.perf_counter()
+        ps = [subprocess.Popen([sys.executable, "-c", code, ROOT, d, str(k)]) for _ in range(procs)]
+        rcs = [p.wait() for p in ps]
+        sec = time.perf_counter() - t0
+    if any(rcs):
+        return None
+    cells = h.shape[0] * h.shape[1]
+    return {"value": procs * cells * k / sec / 1e9, "unit": "Gcell-updates/s", "cores": procs, "kind": "oracle",
+            "sample": f"{procs} processes, each the {h.shape[1]}x{h.shape[0]} band for {k} steps, {sec:.1f} s wall "
+                      f"(process start included)"}
 
 
 def main():
