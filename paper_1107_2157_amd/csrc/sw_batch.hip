@@ -14,10 +14,16 @@ using namespace sw::tile;
 namespace {
 
 // dt of grid `grid` for step `step` (wave-wide).
-__device__ __forceinline__ double batch_dt(const SwBatchLaunch &a, int grid) {
-    if (a.dt_fixed > 0) return a.dt_fixed;
+// The grid's dt in two halves (its ring stripe, a load; then the wave max
+// and the division), so that the step kernel issues its first row loads in
+// between.
+__device__ __forceinline__ double batch_dt_stripe(const SwBatchLaunch &a, int grid) {
+    if (a.dt_fixed > 0) return 0.0;
     const int lane = threadIdx.x & 63;
-    double v = lane < kBatchStripes ? __longlong_as_double((long long)a.sc[grid].smax[a.step % 3][lane]) : 0.0;
+    return lane < kBatchStripes ? __longlong_as_double((long long)a.sc[grid].smax[a.step % 3][lane]) : 0.0;
+}
+__device__ __forceinline__ double batch_dt_finish(const SwBatchLaunch &a, double v) {
+    if (a.dt_fixed > 0) return a.dt_fixed;
     return a.cfl * fmin(a.dx, a.dy) / wave_max(v);
 }
 
@@ -46,7 +52,7 @@ __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_batch_step(SwBat
     const SwBatchTile tt = a.tiles[tile];
     if (a.active && !a.active[tt.grid]) return;
     const SwBatchGrid &gd = a.grids[tt.grid];
-    const double dt = batch_dt(a, tt.grid);
+    const double stripe = batch_dt_stripe(a, tt.grid);
     TileArgs t;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -63,7 +69,8 @@ __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_batch_step(SwBat
     t.rows = a.rows;
     T smax = T(0);
     bool bad = false;
-    fused_tile<T, VEC, PD>(t, dt, a.g, a.dx, a.dy, smax, bad);
+    double dt = 0.0;
+    fused_tile<T, VEC, PD>(t, [&] { return batch_dt_finish(a, stripe); }, a.g, a.dx, a.dy, smax, bad, dt);
     batch_reduce(a, tt.grid, (a.step + 1) % 3, tile, (double)smax, bad);
     if (tt.s == 0 && tt.rb == 0) {               // the grid's first tile keeps its books
         const int lane = threadIdx.x & 63;

@@ -108,6 +108,19 @@ __device__ __forceinline__ double step_dt(const SwLaunch &a) {
     return a.cfl * fmin(a.dx, a.dy) / read_smax(a.sc, a.step % 3);
 }
 
+// step_dt in two halves, so that a kernel can issue its first row loads while
+// the ring slot is in flight: the lane's stripe of the slot (a load; 0 with a
+// fixed dt), then the wave max and the division (wave-wide, uniform control
+// flow).  step_dt_finish(a, step_dt_stripe(a)) is step_dt(a), bit for bit.
+__device__ __forceinline__ double step_dt_stripe(const SwLaunch &a) {
+    if (a.dt_fixed > 0) return 0.0;
+    return __longlong_as_double((long long)a.sc->smax[a.step % 3][threadIdx.x & 63]);
+}
+__device__ __forceinline__ double step_dt_finish(const SwLaunch &a, double stripe) {
+    if (a.dt_fixed > 0) return a.dt_fixed;
+    return a.cfl * fmin(a.dx, a.dy) / wave_max(stripe);
+}
+
 // Wave-wide: max-reduce the lanes' signal speeds into stripe `stripe` of
 // ring slot `slot` and raise the sticky flag if any lane saw a broken cell.
 __device__ __forceinline__ void reduce_speed(SwScalars *sc, int slot, int stripe, double smax, bool bad) {

@@ -30,7 +30,8 @@ __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_step_fused(SwLau
         s = tile % nstrips;
         rb = tile / nstrips;
     }
-    const double dt = step_dt(a);
+    const double stripe = step_dt_stripe(a);   // issued first; waited for after the tile's first row loads
+    double dt = 0.0;
     T smax = T(0);
     bool bad = false;
     if (rb < nrb) {
@@ -39,7 +40,9 @@ __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_step_fused(SwLau
         t.pitch = a.pitch;
         t.nx = a.nx; t.ny = a.ny; t.bc_x = a.bc_x; t.bc_y = a.bc_y;
         t.s = s; t.rb = rb; t.rows = rows;
-        fused_tile<T, VEC, PD>(t, dt, a.g, a.dx, a.dy, smax, bad);
+        fused_tile<T, VEC, PD>(t, [&] { return step_dt_finish(a, stripe); }, a.g, a.dx, a.dy, smax, bad, dt);
+    } else {
+        dt = step_dt_finish(a, stripe);
     }
 
     step_epilogue(a, (double)smax, bad, dt, blockIdx.x == 0 && wave == 0, (int)blockIdx.x * 4 + wave);

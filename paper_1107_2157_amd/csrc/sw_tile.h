@@ -160,14 +160,15 @@ struct TileArgs {
     int s, rb, rows;
 };
 
-template <typename T, int VEC, int PD>
-__device__ __forceinline__ void fused_tile(const TileArgs &t, double dt, double g_, double dx, double dy, T &smax,
-                                           bool &bad) {
+template <typename T, int VEC, int PD, typename DtFn>
+__device__ __forceinline__ void fused_tile(const TileArgs &t, DtFn &&dt_of, double g_, double dx, double dy, T &smax,
+                                           bool &bad, double &dt_out) {
     constexpr int W = 64 * VEC;
     const int lane = threadIdx.x & 63;
     const T k = (T)(0.5 * g_), g = (T)g_;
-    const T lx = (T)(0.5 * dt / dx), ly = (T)(0.5 * dt / dy);
-    const T mx = (T)(dt / dx), my = (T)(dt / dy);
+    // set from dt once the tile's first rows are in flight (dt_of waits for
+    // the CFL ring slot and divides: wave-wide, called in uniform control flow)
+    T lx, ly, mx, my, elx;
     const int nx = t.nx, ny = t.ny, s = t.s, rb = t.rb, rows = t.rows;
     const int64_t pitch = t.pitch;
     {
@@ -187,7 +188,6 @@ __device__ __forceinline__ void fused_tile(const TileArgs &t, double dt, double 
         // that the compiler can count the loads in flight exactly and keep
         // the prefetched rows outstanding while it computes.
         const unsigned cl = in_row ? c : (unsigned)c0;
-        const T elx = lane == 0 ? lx : -lx;                  // lane 0 needs L of its edge, lane 63 needs R
         const bool tile_at_wall = s == 0 || c0 + W >= nx || j0 == 0 || j1 >= ny;
         T *O[3] = {(T *)t.out[0], (T *)t.out[1], (T *)t.out[2]};
         // Descriptors of this tile: they start at cell (-1, j0 - 1) and span
@@ -331,6 +331,18 @@ __device__ __forceinline__ void fused_tile(const TileArgs &t, double dt, double 
         T rh[PD + 1][VEC], rp[PD + 1][VEC], rq[PD + 1][VEC], re[PD + 1][3];
         load_row(j0 - 1, rh[0], rp[0], rq[0], re[0]);
         load_row(j0, rh[1 % (PD + 1)], rp[1 % (PD + 1)], rq[1 % (PD + 1)], re[1 % (PD + 1)]);
+        // keep the scheduler from hoisting the dt arithmetic (and its wait for
+        // the ring slot) above these loads: both latencies then overlap
+        __builtin_amdgcn_sched_barrier(0);
+        {
+            const double dt = dt_of();
+            dt_out = dt;
+            lx = (T)(0.5 * dt / dx);
+            ly = (T)(0.5 * dt / dy);
+            mx = (T)(dt / dx);
+            my = (T)(dt / dy);
+            elx = lane == 0 ? lx : -lx;                      // lane 0 needs L of its edge, lane 63 needs R
+        }
         row_pass(bconst<false>{}, bconst<false>{}, rh[0], rp[0], rq[0], re[0], false, 0);
         row_pass(bconst<true>{}, bconst<false>{}, rh[1 % (PD + 1)], rp[1 % (PD + 1)], rq[1 % (PD + 1)],
                  re[1 % (PD + 1)], true, 0);
