@@ -109,6 +109,18 @@ def test_tunings_bitwise_identical():
             assert ref[-1] == out[-1]
 
 
+def test_batch_tile_span_limit():
+    """The batch's fused tiles reach their rows through 32-bit buffer
+    offsets as the single-grid kernel's do: with a grid 2^21 cells wide in
+    FP64 in the batch, 40 rows per tile fit and 41 are refused when the shape
+    is chosen (the other grid is small)."""
+    b = sw.Batch([(2 ** 21, 1), (64, 64)], dtype="f64")
+    b.set_tuning(variant=2, rows=40, vec=1)
+    with pytest.raises(sw.SwError) as e:
+        b.set_tuning(variant=2, rows=41, vec=1)
+    assert e.value.status == sw.EINVAL
+
+
 def test_per_grid_sticky_flag_and_dt():
     shapes = [(64, 64), (64, 64), (128, 64)]
     sts = states(shapes, 900, False)
