@@ -17,7 +17,10 @@ nothing with the HIP path.  Written from the definition of the network:
   ``dW_l[co, tap, ci] = sum_p dZ_l[p, co] A_{l-1}[p + tap, ci]``,
   ``db_l = sum_p dZ_l``, ``G_{l-1}[q, ci] = sum_{tap, co} dZ_l[q - tap, co] W_l[co, tap, ci]``
   plus ``G_l`` when layer l is a residual block (``G_l = dL/dA_l``),
-  ``dZ_{l-1} = G_{l-1} * (Z_{l-1} > 0)``.
+  ``dZ_{l-1} = G_{l-1} * (Z_{l-1} > 0)``;
+* the training update: Adam (Kingma and Ba 2015, Algorithm 1) on the FP64
+  parameter vector, with the moment decays 0.9 / 0.999 and eps = 1e-8 the
+  network's trainer uses.
 
 ``bf16=True`` rounds the tensors the GPU stores in BF16 (input, weights,
 hidden activations, gradient seeds and hidden-layer gradients ``G``, ``dZ``)
@@ -123,43 +126,84 @@ def forward(params, u, offset, scale, bc_x=0, bc_y=0, bf16_mode=True, masks=None
         acts.append(a)
 
 
-def loss_and_grad(params, u, u8, offset, scale, out_scale, bc_x=0, bc_y=0, bf16_mode=True):
-    """MSE loss and the gradient (flat, master layout) of one pair."""
-    q = bf16 if bf16_mode else (lambda a: np.asarray(a, dtype=np.float64))
-    layers = [(q(w), b) for w, b in unpack(params)]
-    masks = []
-    acts, delta = forward(params, u, offset, scale, bc_x, bc_y, bf16_mode, masks)
+def target_of(u, u8, out_scale):
+    """Normalised 8-step increment ``(u8 - u) / out_scale`` as [B][H][W][3]."""
     u = np.asarray(u, dtype=np.float32)
     u8 = np.asarray(u8, dtype=np.float32)
-    tgt = np.stack([(u8[:, c] - u[:, c]) / np.float32(out_scale[c]) for c in range(3)], axis=-1).astype(np.float64)
+    return np.stack([(u8[:, c] - u[:, c]) / np.float32(out_scale[c]) for c in range(3)], axis=-1).astype(np.float64)
+
+
+def weight_grad(dz, a_in):
+    """dW[co, tap, ci] = sum_p dZ[p, co] A[p + tap, ci] and db[co] = sum_p dZ[p, co]
+    (dz: [B][H][W][co], a_in: the layer input with halo)."""
+    H, W = dz.shape[1], dz.shape[2]
+    gw = np.zeros((dz.shape[3], 9, a_in.shape[3]))
+    for tap in range(9):
+        dy, dx = tap // 3, tap % 3
+        gw[:, tap, :] = np.tensordot(dz, a_in[:, dy:dy + H, dx:dx + W, :], axes=([0, 1, 2], [0, 1, 2]))
+    return gw, dz.sum(axis=(0, 1, 2))
+
+
+def input_grad(dz, w):
+    """dL/dA_in[q, ci] = sum_{tap, co} dZ[q - off(tap), co] W[co, tap, ci]: the
+    correlation of the zero-padded dZ with the flipped, transposed kernel."""
+    wflip = w[:, ::-1, :].transpose(2, 1, 0)          # [ci][tap'][co], tap' = 8 - tap
+    return conv3x3(pad(dz), wflip)
+
+
+def backward(params, acts, masks, delta, tgt, bf16_mode=True, abs_sums=False):
+    """Loss and flat gradient from a forward pass's activations (with halo,
+    ``acts[l]`` = input of layer l), the hidden layers' masks ``Z_l > 0``, the
+    output ``delta`` and the target.  With ``abs_sums`` also returns, per
+    gradient entry, the sum of the absolute values of the terms it adds up
+    (``sum_p |dZ| |A|`` for a weight, ``sum_p |dZ|`` for a bias): the scale a
+    rounding bound for that sum is stated against."""
+    q = bf16 if bf16_mode else (lambda a: np.asarray(a, dtype=np.float64))
+    layers = [(q(w), b) for w, b in unpack(params)]
     n = delta.shape[0] * delta.shape[1] * delta.shape[2] * 3
     d = delta - tgt
     loss = float(np.sum(d * d) / n)
     dz = q(2.0 * d / n)
     g_out = None                     # dL/d(output of layer l), needed where layer l is residual
-    grads = [None] * len(layers)
+    grads, sums = [None] * len(layers), [None] * len(layers)
     for l in range(len(layers) - 1, -1, -1):
-        w, _ = layers[l]
-        a_in = acts[l]
-        H, W = dz.shape[1], dz.shape[2]
-        gw = np.zeros_like(w)
-        for tap in range(9):
-            dy, dx = tap // 3, tap % 3
-            gw[:, tap, :] = np.tensordot(dz, a_in[:, dy:dy + H, dx:dx + W, :], axes=([0, 1, 2], [0, 1, 2]))
-        gb = dz.sum(axis=(0, 1, 2))
-        grads[l] = (gw, gb)
+        grads[l] = weight_grad(dz, acts[l])
+        if abs_sums:
+            sums[l] = weight_grad(np.abs(dz), np.abs(acts[l]))
         if l == 0:
             break
-        # dL/dA_in[q] = sum_tap dZ[q - off(tap)] W[tap]: correlation of the padded dZ with the flipped kernel
-        wflip = w[:, ::-1, :].transpose(2, 1, 0)          # [ci][tap'][co], tap' = 8 - tap
-        g = conv3x3(pad(dz), wflip)
+        g = input_grad(dz, layers[l][0])
         if residual(l):
             g = g + g_out
         g = q(g)
         dz = g * masks[l - 1]
         g_out = g
     flat = np.concatenate([np.concatenate([gw.ravel(), gb]) for gw, gb in grads])
-    return loss, flat
+    if not abs_sums:
+        return loss, flat
+    return loss, flat, np.concatenate([np.concatenate([sw.ravel(), sb]) for sw, sb in sums])
+
+
+def loss_and_grad(params, u, u8, offset, scale, out_scale, bc_x=0, bc_y=0, bf16_mode=True, abs_sums=False):
+    """MSE loss and the gradient (flat, master layout) of one pair."""
+    masks = []
+    acts, delta = forward(params, u, offset, scale, bc_x, bc_y, bf16_mode, masks)
+    return backward(params, acts, masks, delta, target_of(u, u8, out_scale), bf16_mode, abs_sums)
+
+
+def adam_step(theta, m, v, g, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba 2015, "Adam: a method for stochastic
+    optimization", Algorithm 1) of step number ``t`` (1-based): exponential
+    moving averages of the gradient and of its square, each divided by its
+    bias correction ``1 - beta^t``, and the step ``lr * m_hat / (sqrt(v_hat) + eps)``
+    against the gradient.  Returns the new ``(theta, m, v)`` in FP64."""
+    g = np.asarray(g, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    theta = np.asarray(theta, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return theta, m, v
 
 
 def init_params(seed: int, out_gain: float = 0.1):

@@ -109,3 +109,93 @@ def test_loss_of_the_zero_network_is_the_mean_squared_target():
 
 def test_param_count():
     assert no.nparams() == 38755
+
+
+# ---- the Adam update (Kingma and Ba 2015, Algorithm 1) ----------------------
+# Closed forms of the two moment recurrences m_t = b1 m_{t-1} + (1 - b1) g_t,
+# v_t = b2 v_{t-1} + (1 - b2) g_t^2 from m_0 = v_0 = 0, pinned below without
+# running the recurrence:
+#  * first step: m_1 / (1 - b1) = g and v_1 / (1 - b2) = g^2, so the update
+#    is -lr g / (|g| + eps) whatever b1, b2 are;
+#  * a constant g for t steps: m_t = g (1 - b1^t), v_t = g^2 (1 - b2^t), so
+#    every bias-corrected step is again -lr g / (|g| + eps);
+#  * g_k = (-1)^k g: m_t = (1 - b1) g (-1)^t (1 - (-b1)^t) / (1 + b1) (a
+#    geometric sum) while v_t = g^2 (1 - b2^t), which separates b1 from b2
+#    and pins the bias correction of the first moment;
+#  * g, then 0: the second step is -lr (b1 / (1 + b1)) g / (|g| sqrt(b2 / (1 + b2)) + eps).
+B1, B2, EPS = 0.9, 0.999, 1e-8
+
+
+def _adam_run(grads, lr, theta0):
+    th = np.array(theta0, dtype=np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    out = []
+    for t, g in enumerate(grads, start=1):
+        th, m, v = no.adam_step(th, m, v, g, t, lr)
+        out.append(th.copy())
+    return out, m, v
+
+
+def _grads():
+    rng = np.random.default_rng(21)
+    return np.concatenate([rng.standard_normal(200) * 10.0 ** rng.integers(-6, 3, 200),
+                           [1e-8, -3e-9, 2.5e-8, 0.0]])      # |g| near eps pins where eps enters
+
+
+def test_adam_first_step_closed_form():
+    g = _grads()
+    theta0 = np.linspace(-1.0, 1.0, g.size)
+    (th,), m, v = _adam_run([g], 1e-3, theta0)
+    np.testing.assert_allclose(th - theta0, -1e-3 * g / (np.abs(g) + EPS), rtol=1e-12, atol=1e-19)
+    np.testing.assert_allclose(m, (1 - B1) * g, rtol=1e-15)
+    np.testing.assert_allclose(v, (1 - B2) * g * g, rtol=1e-15)
+
+
+def test_adam_constant_gradient_closed_form():
+    g = _grads()
+    theta0 = np.zeros(g.size)
+    ths, m, v = _adam_run([g] * 25, 2e-3, theta0)
+    for t, th in enumerate(ths, start=1):
+        np.testing.assert_allclose(th, -t * 2e-3 * g / (np.abs(g) + EPS), rtol=1e-11, atol=1e-18)
+    np.testing.assert_allclose(m, g * (1 - B1 ** 25), rtol=1e-12)
+    np.testing.assert_allclose(v, g * g * (1 - B2 ** 25), rtol=1e-12)
+
+
+def test_adam_alternating_gradient_closed_form():
+    g = np.array([0.7, -1.3e-3, 4.0e2, 2.0e-7])
+    lr = 1e-2
+    T = 12
+    ths, _, _ = _adam_run([(-1.0) ** k * g for k in range(1, T + 1)], lr, np.zeros(g.size))
+    prev = np.zeros(g.size)
+    for t, th in enumerate(ths, start=1):
+        m_t = (1 - B1) * g * (-1.0) ** t * (1 - (-B1) ** t) / (1 + B1)
+        v_t = g * g * (1 - B2 ** t)
+        step = -lr * (m_t / (1 - B1 ** t)) / (np.sqrt(v_t / (1 - B2 ** t)) + EPS)
+        np.testing.assert_allclose(th - prev, step, rtol=1e-10, atol=1e-18)
+        prev = th
+
+
+def test_adam_decay_after_a_zero_gradient_closed_form():
+    g = _grads()
+    ths, _, _ = _adam_run([g, np.zeros(g.size)], 1e-3, np.zeros(g.size))
+    want = -1e-3 * (B1 / (1 + B1)) * g / (np.abs(g) * np.sqrt(B2 / (1 + B2)) + EPS)
+    np.testing.assert_allclose(ths[1] - ths[0], want, rtol=1e-10, atol=1e-19)
+
+
+def test_abs_sums_bound_the_gradient_and_equal_it_for_positive_terms():
+    """The per-entry sum of |terms| is >= |gradient| everywhere, and equals it
+    where every term is non-negative (all inputs and weights made positive,
+    periodic ghosts, target below the prediction, hidden masks all on)."""
+    rng = np.random.default_rng(8)
+    h, hu, hv = (a.numpy() for a in ics.random_state(8, 6, seed=11, amp_h=0.3, amp_m=0.1))
+    u = np.stack([h, hu, hv])[None]
+    u8 = u + 0.01 * rng.standard_normal(u.shape)
+    p = no.init_params(4, out_gain=1.0)
+    _, g, s = no.loss_and_grad(p, u, u8, OFF, SCALE, (0.02, 0.02, 0.02), bf16_mode=False, abs_sums=True)
+    assert np.all(s >= np.abs(g) * (1 - 1e-12))
+    pos = np.abs(p)
+    u_pos = np.stack([h * 0 + 2.0, np.abs(hu) + 0.1, np.abs(hv) + 0.1])[None]
+    _, g, s = no.loss_and_grad(pos, u_pos, u_pos - 1.0, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (1.0, 1.0, 1.0),
+                               bc_x=1, bc_y=1, bf16_mode=False, abs_sums=True)
+    np.testing.assert_allclose(np.abs(g), s, rtol=1e-12)

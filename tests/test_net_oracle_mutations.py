@@ -34,6 +34,13 @@ MUTATIONS = [
      "n = delta.shape[0] * delta.shape[1] * delta.shape[2]"),
     ("target sign", "(u8[:, c] - u[:, c])", "(u[:, c] - u8[:, c])"),
     ("weight gradient of the wrong tap", "gw[:, tap, :] = np.tensordot", "gw[:, 8 - tap, :] = np.tensordot"),
+    ("Adam: first moment not bias-corrected", "m_hat = m / (1.0 - beta1 ** t)", "m_hat = m"),
+    ("Adam: second moment not bias-corrected", "v_hat = v / (1.0 - beta2 ** t)", "v_hat = v"),
+    ("Adam: decays swapped", "m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g",
+     "m = beta2 * np.asarray(m, dtype=np.float64) + (1.0 - beta2) * g"),
+    ("Adam: eps inside the root", "(np.sqrt(v_hat) + eps)", "np.sqrt(v_hat + eps)"),
+    ("Adam: step along the gradient", "theta = np.asarray(theta, dtype=np.float64) - lr", "theta = np.asarray(theta, dtype=np.float64) + lr"),
+    ("Adam: gradient not squared", "(1.0 - beta2) * g * g", "(1.0 - beta2) * np.abs(g)"),
 ]
 
 
@@ -114,8 +121,23 @@ def battery(no) -> list[str]:
         return abs(loss - want) <= 1e-12 * want and np.allclose(
             g[-3:], [-2.0 * float(np.mean(tc, dtype=np.float64)) / 3 for tc in t], rtol=1e-12)
 
+    def adam():
+        # first step, then a zero gradient, then a constant one (closed forms
+        # of the moment recurrences; see test_net_oracle.py)
+        b1, b2, eps, lr = 0.9, 0.999, 1e-8, 1e-3
+        g = np.concatenate([rng.standard_normal(50) * 10.0 ** rng.integers(-6, 3, 50), [1e-8, -2e-8]])
+        th, m, v = no.adam_step(np.zeros(g.size), np.zeros(g.size), np.zeros(g.size), g, 1, lr)
+        ok = np.allclose(th, -lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-19)
+        th2, _, _ = no.adam_step(th, m, v, np.zeros(g.size), 2, lr)
+        want = -lr * (b1 / (1 + b1)) * g / (np.abs(g) * np.sqrt(b2 / (1 + b2)) + eps)
+        ok = ok and np.allclose(th2 - th, want, rtol=1e-10, atol=1e-19)
+        th, m, v = np.zeros(g.size), np.zeros(g.size), np.zeros(g.size)
+        for t in range(1, 6):
+            th, m, v = no.adam_step(th, m, v, g, t, lr)
+        return ok and np.allclose(th, -5 * lr * g / (np.abs(g) + eps), rtol=1e-11, atol=1e-18)
+
     for name, fn in (("conv", conv), ("bf16", rounding), ("ghosts", ghosts), ("central differences", fd),
-                     ("residual closed form", residual_form), ("zero network", zero_net)):
+                     ("residual closed form", residual_form), ("zero network", zero_net), ("adam", adam)):
         check(name, fn)
     return bad
 
