@@ -30,6 +30,8 @@ The language, one statement per line (``#`` starts a comment)::
     out oH, oU, oV                 # output arrays, same shape
     elemental f(a, b) = EXPR       # inline function of scalars
     west = [0, 1, 1, 1]            # a halo vector (may be reassigned)
+    stencil s(A, B) = EXPR         # an expression over regions of array parameters,
+                                   # expanded where it is applied: s(H, U)
     Hx = EXPR                      # an array temporary; its extent is the expression's
     pH = region_ptr(oH, interior)  # a writable view of an output array
     pH = EXPR                      # stores into the view
@@ -122,8 +124,9 @@ def tokenize(text: str, line: int):
 
 
 class _Parser:
-    def __init__(self, toks, line, prog):
+    def __init__(self, toks, line, prog, array_params=()):
         self.toks, self.i, self.line, self.prog = toks, 0, line, prog
+        self.array_params = tuple(array_params)     # names standing for arrays in a stencil's body
 
     def peek(self):
         return self.toks[self.i] if self.i < len(self.toks) else (None, None)
@@ -178,6 +181,10 @@ class _Parser:
         name = self.take("name")
         if name == "region_cpy":
             arr, halo = self.region_args()
+            if arr in self.array_params:
+                if halo not in self.prog.halos:
+                    raise RegionError(f"line {self.line}: unknown halo {halo!r}")
+                return Region(arr, self.prog.halos[halo])
             if arr not in self.prog.arrays:
                 raise RegionError(f"line {self.line}: region_cpy of unknown array {arr!r}")
             if arr in self.prog.outputs:
@@ -187,6 +194,8 @@ class _Parser:
             return Region(arr, self.prog.halos[halo])
         if name == "region_ptr":
             raise RegionError(f"line {self.line}: region_ptr may only start a view assignment")
+        if name in self.prog.stencils and self.peek() == ("op", "("):
+            return self.stencil_call(name)
         if self.peek() == ("op", "("):
             self.take()
             args = [self.expr(params)]
@@ -205,6 +214,27 @@ class _Parser:
             raise RegionError(f"line {self.line}: array {name!r} used without region_cpy")
         raise RegionError(f"line {self.line}: unknown name {name!r}")
 
+    def stencil_call(self, name):
+        """A stencil applied to arrays: its body with each array parameter
+        replaced by the array passed for it."""
+        st = self.prog.stencils[name]
+        self.take("op", "(")
+        args = [self.take("name")]
+        while self.peek() == ("op", ","):
+            self.take()
+            args.append(self.take("name"))
+        self.take("op", ")")
+        if len(args) != len(st.params):
+            raise RegionError(f"line {self.line}: {name} takes {len(st.params)} arrays")
+        for a in args:
+            if a not in self.prog.arrays and a not in self.array_params:
+                raise RegionError(f"line {self.line}: {name} of unknown array {a!r}")
+            if a in self.prog.outputs:
+                raise RegionError(f"line {self.line}: {name} reads output array {a!r}")
+        bind = dict(zip(st.params, args))
+        return _rewrite(st.body, lambda x: Region(bind[x.array], x.halo)
+                        if isinstance(x, Region) and x.array in bind else None)
+
     def region_args(self):
         """(ARRAY, HALO) of region_cpy / region_ptr: both plain names."""
         self.take("op", "(")
@@ -222,12 +252,19 @@ class Elemental:
 
 
 @dataclass
+class Stencil:
+    params: tuple      # array parameters
+    body: object       # expression over region_cpy(param, halo), scalars and elemental calls
+
+
+@dataclass
 class Program:
     name: str = ""
     scalars: list = field(default_factory=list)
     inputs: list = field(default_factory=list)
     outputs: list = field(default_factory=list)
     elementals: dict = field(default_factory=dict)
+    stencils: dict = field(default_factory=dict)    # name -> Stencil (expanded where called)
     arrays: dict = field(default_factory=dict)      # name -> extent (a, b): (nx + a, ny + b)
     temps: list = field(default_factory=list)       # [(name, expr)] in order
     views: dict = field(default_factory=dict)       # view -> (output array, halo)
@@ -291,6 +328,21 @@ def parse(text: str) -> Program:
                 (prog.inputs if head[0] == "in" else prog.outputs).extend(names)
                 for n in names:
                     prog.arrays[n] = (2, 2)          # a one-element halo on every side
+            continue
+        if head[0] == "stencil":
+            m = re.fullmatch(r"stencil\s+([A-Za-z_]\w*)\s*\(([^)]*)\)\s*=\s*(.+)", line)
+            if not m:
+                raise RegionError(f"line {ln}: bad stencil definition")
+            fn, params = m.group(1), tuple(x.strip() for x in m.group(2).split(","))
+            if fn in prog.elementals or fn in prog.stencils:
+                raise RegionError(f"line {ln}: {fn!r} defined twice")
+            for x in params:
+                if not re.fullmatch(r"[A-Za-z_]\w*", x) or x in prog.arrays or x in prog.scalars:
+                    raise RegionError(f"line {ln}: bad stencil parameter {x!r}")
+            p = _Parser(tokenize(m.group(3), ln), ln, prog, params)
+            body = p.expr()
+            p.done()
+            prog.stencils[fn] = Stencil(params, body)
             continue
         if head[0] == "elemental":
             m = re.fullmatch(r"elemental\s+([A-Za-z_]\w*)\s*\(([^)]*)\)\s*=\s*(.+)", line)
@@ -438,8 +490,9 @@ def hoist(prog: Program) -> Program:
     hoisted = {k: f"{k[0]}__{'_'.join(k[1])}" for k, halos in uses.items() if len(halos) > 1}
     if not hoisted:
         return prog
-    out = Program(prog.name, list(prog.scalars), list(prog.inputs), list(prog.outputs), dict(prog.elementals),
-                  dict(prog.arrays), [], dict(prog.views), [], dict(prog.halos))
+    out = Program(name=prog.name, scalars=list(prog.scalars), inputs=list(prog.inputs), outputs=list(prog.outputs),
+                  elementals=dict(prog.elementals), stencils=dict(prog.stencils), arrays=dict(prog.arrays), temps=[],
+                  views=dict(prog.views), stores=[], halos=dict(prog.halos))
     defined = set(prog.inputs)
 
     def sub(x):

@@ -24,9 +24,13 @@ def test_extents_of_the_shipped_program():
         assert p.arrays[t] == (1, 0)          # (nx + 1) x ny x faces
     for t in ("Hy", "Uy", "Vy"):
         assert p.arrays[t] == (0, 1)          # nx x (ny + 1) y faces
-    assert [v for v, _ in p.stores] == ["pH", "pU", "pV"]
-    assert p.views["pH"] == ("oH", (1, 1, 1, 1))
-    assert set(p.elementals) == {"fu", "fv", "gv", "half"}
+    for t in ("FU", "FV", "GV"):
+        assert p.arrays[t] == (2, 2)          # flux parts on the whole array, halo included
+    assert p.arrays["FUx"] == p.arrays["FVx"] == (1, 0) and p.arrays["GUy"] == p.arrays["GVy"] == (0, 1)
+    assert [v for v, _ in p.stores] == ["newH", "newU", "newV"]
+    assert p.views["newH"] == ("oH", (1, 1, 1, 1))
+    assert set(p.elementals) == {"fu", "fv", "gv", "half", "advance"}
+    assert set(p.stencils) == {"xface", "yface", "step2"}
 
 
 def test_generated_kernel_is_up_to_date():
@@ -125,19 +129,46 @@ def test_rejected_store_extent_and_missing_store():
 def test_elemental_scalars_become_arguments():
     src = regions.generate(regions.load())
     assert "rgn_fu(T h, T u, T g)" in src and "rgn_half(T a, T b, T fa, T fb, T c)" in src
-    assert "__syncthreads();" in src and "__shared__ T s_Hx[520];" in src
-    assert "s_fu__H_U" in src and "s_fu__H_U" not in regions.generate(regions.load(), optimize=False)
+    assert "rgn_advance(T u, T fx1, T fx0, T fy1, T fy0, T dt, T dx, T dy)" in src
+    assert "__syncthreads();" in src and "__shared__ T s_Hx[520];" in src and "s_FU" in src
+
+
+# A program written without flux temporaries: the flux parts are evaluated
+# inside the face and update expressions, once per shifted region.
+UNHOISTED = """kernel k
+scalar dt, dx, dy, g
+in H, U, V
+out oH, oU, oV
+elemental fu(h, u) = u**2/h + 0.5*g*h**2
+elemental fv(h, u, v) = u*v/h
+elemental half(a, b, fa, fb, c) = 0.5*(a + b) - c*(fb - fa)
+interior = [1, 1, 1, 1]
+e = [1, 0, 1, 1]
+w = [0, 1, 1, 1]
+l = [0, 1, 0, 0]
+r = [1, 0, 0, 0]
+Ux = half(region_cpy(U, w), region_cpy(U, e), fu(region_cpy(H, w), region_cpy(U, w)), fu(region_cpy(H, e), region_cpy(U, e)), dt)
+Vx = half(region_cpy(V, w), region_cpy(V, e), fv(region_cpy(H, w), region_cpy(U, w), region_cpy(V, w)), fv(region_cpy(H, e), region_cpy(U, e), region_cpy(V, e)), dt)
+Hx = half(region_cpy(H, w), region_cpy(H, e), region_cpy(U, w), region_cpy(U, e), dt)
+a = region_ptr(oH, interior)
+b = region_ptr(oU, interior)
+c = region_ptr(oV, interior)
+a = region_cpy(H, interior) - dt*(region_cpy(Ux, r) - region_cpy(Ux, l))
+b = region_cpy(U, interior) - dt*(fu(region_cpy(Hx, r), region_cpy(Ux, r)) - fu(region_cpy(Hx, l), region_cpy(Ux, l)))
+c = region_cpy(V, interior) - dt*(fv(region_cpy(Hx, r), region_cpy(Ux, r), region_cpy(Vx, r)) - fv(region_cpy(Hx, l), region_cpy(Ux, l), region_cpy(Vx, l)))
+"""
 
 
 def test_hoisting_keeps_every_bit():
     """Elemental calls repeated on shifted regions are hoisted into
-    temporaries (three cell fluxes on the inputs, four on the face states);
-    the hoisted program computes bitwise the same outputs."""
-    p = regions.load()
+    temporaries (two cell fluxes on the inputs, two on the face states);
+    the hoisted program computes bitwise the same outputs.  The shipped
+    program evaluates its flux parts once per cell already: nothing to hoist."""
+    assert regions.hoist(regions.load()).temps == regions.load().temps
+    p = regions.parse(UNHOISTED)
     hp = regions.hoist(p)
     new = [n for n, _ in hp.temps if n not in p.arrays]
-    assert sorted(new) == ["fu__H_U", "fu__Hx_Ux", "fv__H_U_V", "fv__Hx_Ux_Vx", "fv__Hy_Uy_Vy", "gv__H_V",
-                           "gv__Hy_Vy"]
+    assert sorted(new) == ["fu__H_U", "fu__Hx_Ux", "fv__H_U_V", "fv__Hx_Ux_Vx"]
     assert hp.arrays["fu__H_U"] == (2, 2) and hp.arrays["fu__Hx_Ux"] == (1, 0)
     nx, ny = 29, 19
     h, hu, hv = ics.random_state(nx, ny, seed=12, amp_h=0.2, amp_m=0.05)
@@ -157,11 +188,41 @@ def test_hoisting_keeps_every_bit():
     assert regions.hoist(q).temps == q.temps
 
 
-def test_tile_ranges_of_hoisted_temporaries():
-    boxes, _ = regions.tile_ranges(regions.hoist(regions.load()), 64, 8)
-    assert boxes["fu__H_U"] == (0, 66, 1, 9)      # read at the x faces only: the tile's rows
-    assert boxes["gv__H_V"] == (1, 65, 0, 10)     # read at the y faces only: the tile's columns
-    assert boxes["fu__Hx_Ux"] == (0, 65, 0, 8)
+def test_tile_ranges_of_flux_temporaries():
+    boxes, _ = regions.tile_ranges(regions.load(), 64, 8)
+    assert boxes["FU"] == (0, 66, 1, 9)      # read at the x faces only: the tile's rows
+    assert boxes["GV"] == (1, 65, 0, 10)     # read at the y faces only: the tile's columns
+    assert boxes["FV"] == (0, 66, 0, 10)     # both
+    assert boxes["FUx"] == (0, 65, 0, 8)
+
+
+def test_stencil_expansion_equals_the_written_out_expression():
+    """A stencil applied to arrays is its body with the arrays put in: the
+    shipped program interprets bitwise as the same program with every
+    stencil written out by hand."""
+    text = program_text()
+    expanded = regions.load()
+    manual = regions.parse(UNHOISTED)
+    assert manual.stencils == {}
+    # write xface(U, FU) out by hand in a copy of the shipped program
+    hand = "half(region_cpy(U, west), region_cpy(U, east), region_cpy(FU, west), region_cpy(FU, east), 0.5*dt/dx)"
+    written = text.replace("Ux = xface(U, FU)", "Ux = " + hand)
+    assert written != text
+    w = regions.parse(written)
+    assert dict(w.temps)["Ux"] == dict(expanded.temps)["Ux"]
+
+
+@pytest.mark.parametrize("line,msg", [
+    ("Hx = sx(Q)\n", "unknown array"),
+    ("Hx = sx(oH)\n", "output array"),
+    ("Hx = sx(H, U)\n", "takes 1 arrays"),
+    ("stencil sx(A) = region_cpy(A, lo)\n", "defined twice"),
+    ("stencil sy(A) = region_cpy(A, nowhere)\n", "unknown halo"),
+    ("Hx = sx(H) + region_cpy(H, interior)\n", "extents differ"),
+])
+def test_rejected_stencils(line, msg):
+    with pytest.raises(regions.RegionError, match=msg):
+        regions.parse(HEAD + "stencil sx(A) = region_cpy(A, lo)\n" + line + TAIL)
 
 
 def test_march_plan_of_the_shipped_program():
@@ -174,9 +235,9 @@ def test_march_plan_of_the_shipped_program():
     m = regions.march_plan(regions.hoist(regions.load()))
     for a in ("H", "U", "V"):
         assert (m.lo[a], m.hi[a], m.valid[a]) == (-1, 1, (0, 63))
-    for a in ("Hx", "Ux", "Vx"):
+    for a in ("Hx", "Ux", "Vx", "FUx", "FVx"):
         assert (m.lo[a], m.hi[a], m.valid[a]) == (0, 0, (0, 62))
-    for a in ("Hy", "Uy", "Vy"):
+    for a in ("Hy", "Uy", "Vy", "GUy", "GVy"):
         assert (m.lo[a], m.hi[a]) == (-1, 0)       # the y faces below and above a stored row
     assert m.out_lanes == (1, 62) and m.warmup == 2
     assert m.order[:3] == ["H", "U", "V"]          # inputs first, then temporaries in program order
