@@ -163,7 +163,7 @@ sw_status sw_reset_time(sw_ctx *ctx, void *stream);
 
 /* Kernel variant used by sw_step: 0 = auto (fastest known), 1 = one thread
  * per cell reading neighbours from global memory (baseline), 2 = fused
- * row-marching kernel (paper scheme only), 3 = temporal blocking: K steps of
+ * row-marching kernel (both schemes; the default for both), 3 = temporal blocking: K steps of
  * a tile and its K-cell halo per launch in LDS (paper scheme with a fixed dt
  * only; a CFL dt depends on every cell after each step; nsteps % K remaining
  * steps use the fused kernel), 4 = unfused: the first half-step writes the
@@ -213,6 +213,7 @@ typedef struct {
 sw_status sw_set_tuning(sw_ctx *ctx, const sw_tuning *tuning);
 /* The tuning sw_step will use, with defaults resolved. */
 sw_status sw_get_tuning(const sw_ctx *ctx, sw_tuning *out);
+
 /* 1 (default): sw_step replays one hipGraph per (nsteps, current buffer,
  * state planes, launch shape), captured on the first such call (kept up to 8
  * per context); 0: eager launches.  Results are identical either way. */
@@ -233,7 +234,7 @@ sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per_trial, con
 
 /* ---------------------------------------------------------------------------
  * Batched mode: n independent grids of possibly different sizes (same g, dx,
- * options and scheme, paper scheme only), all advanced together.  Each grid
+ * options and scheme, either scheme), all advanced together.  Each grid
  * keeps its own CFL dt, simulated time and sticky flag; a grid advanced in a
  * batch is bitwise identical to the same grid advanced alone with the same
  * launch shape.  One kernel launch per time step covers every grid (a tile
@@ -244,8 +245,8 @@ sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per_trial, con
 typedef struct sw_batch sw_batch;
 
 /* Validates every grid like sw_create (no HIP call until then), then
- * allocates the per-grid scalars.  Errors: SW_EINVAL, SW_ENOTSUP (halo,
- * transverse scheme), SW_ENOMEM, SW_EHIP. */
+ * allocates the per-grid scalars.  Errors: SW_EINVAL, SW_ENOTSUP (halo),
+ * SW_ENOMEM, SW_EHIP. */
 sw_status sw_batch_create(int32_t n, const sw_grid *grids, sw_halo halo, double g, double dx, const sw_opts *opts,
                           sw_batch **out);
 sw_status sw_batch_destroy(sw_batch *batch);
@@ -274,7 +275,8 @@ sw_status sw_batch_reset_time(sw_batch *batch, void *stream);
 sw_status sw_batch_export(sw_batch *batch, void *dense, void *stream);
 sw_status sw_batch_import(sw_batch *batch, const void *dense, void *stream);
 /* Launch shape for every grid (variant must be 0 or 2; order: 0 = LPT
- * tile table, largest grids first; 1 = round-robin over grids). */
+ * tile table, largest grids first; 1 = round-robin over grids).  Every
+ * shape gives bitwise the same states. */
 sw_status sw_batch_set_tuning(sw_batch *batch, const sw_tuning *tuning);
 sw_status sw_batch_get_tuning(const sw_batch *batch, sw_tuning *out);
 /* 1 (default): one hipGraph launch per sw_batch_step call; 0: eager launches. */
@@ -345,7 +347,9 @@ sw_status sw_surrogate_set_norm(sw_net *net, const float in_offset[3], const flo
 sw_status sw_surrogate_forward(sw_net *net, const float *u, int32_t B, float *delta, void *stream);
 /* Device pointer to the last forward pass's activations: layer 0 = network
  * input (BF16 NHWC, 8 channels, with halo), 1..5 = hidden layers (BF16 NHWC,
- * 32 channels, with halo), 6 = delta (FP32 [B][H][W][4]). */
+ * 32 channels, with halo), 6 = delta (FP32 [B][H][W][4]).  A rollout's
+ * first layer reads the batch's planes directly and leaves layer 0 as the
+ * last sw_surrogate_forward / grad / train_step wrote it. */
 sw_status sw_surrogate_activation(sw_net *net, int32_t layer, const void **ptr, int64_t *bytes);
 /* Async.  Loss (device float, may be NULL) and gradient (device, nparams
  * floats, may be NULL) of the pair (u -> u8), without updating. */
@@ -374,6 +378,14 @@ sw_status sw_surrogate_advance(sw_net *net, sw_batch *solver, int32_t nsteps, co
 /* 1 (default): unjudged rollouts replay captured graphs; 0: eager launches.
  * Results are identical either way.  Errors: SW_EINVAL for a NULL network. */
 sw_status sw_surrogate_set_graph(sw_net *net, int32_t enable);
+/* Upper bound on the workgroups of the persistent convolution and
+ * weight-gradient kernels (each walks a contiguous run of tiles); 0 (the
+ * default) launches one workgroup per slot the device holds at once.  A
+ * smaller cap only changes how the tiles are split among workgroups: the
+ * convolution outputs are bitwise unchanged, the weight gradient's FP32 block
+ * partials (summed in FP64) split differently.  Drops captured rollouts.
+ * Errors: SW_EINVAL for a NULL network or a cap outside [0, 1024]. */
+sw_status sw_surrogate_set_block_cap(sw_net *net, int32_t max_blocks);
 
 const char *sw_strerror(sw_status status);
 const char *sw_last_error_detail(void);

@@ -379,9 +379,9 @@ constexpr int kRgnDefaultPrefetch = 1;   // generated row march: input rows load
 sw_status resolve_tuning(const sw_ctx *ctx, const sw_tuning &in, SwTuning *out) {
     int variant = in.variant;
     if (variant < 0 || variant > 6) return fail(SW_EINVAL, "tuning: unknown variant %d", variant);
-    if (variant == 0) variant = ctx->opts.scheme == SW_SCHEME_PAPER ? 2 : 1;
-    if (variant >= 2 && ctx->opts.scheme != SW_SCHEME_PAPER)
-        return fail(SW_ENOTSUP, "tuning: the fused, blocked, unfused, AoS and generated kernels implement the paper scheme only");
+    if (variant == 0) variant = 2;
+    if (variant >= 3 && ctx->opts.scheme != SW_SCHEME_PAPER)
+        return fail(SW_ENOTSUP, "tuning: the blocked, unfused, AoS and generated kernels implement the paper scheme only");
     if (variant == 4) {
         *out = SwTuning{4, 0, 0, 0, 0, 0};
         return SW_OK;
@@ -432,7 +432,7 @@ sw_status resolve_tuning(const sw_ctx *ctx, const sw_tuning &in, SwTuning *out) 
     out->order = in.order;
     if (in.order < 0 || in.order > 2) return fail(SW_EINVAL, "tuning: order = %d", in.order);
     if (in.rows < 0) return fail(SW_EINVAL, "tuning: rows = %d", in.rows);
-    if (variant == 2 && !sw_fused_supported((int)ctx->opts.dtype, out->vec, out->minw, out->pd))
+    if (variant == 2 && !sw_fused_supported((int)ctx->opts.dtype, (int)ctx->opts.scheme, out->vec, out->minw, out->pd))
         return fail(SW_EINVAL, "tuning: vec %d / occupancy %d / prefetch %d not available for this dtype", out->vec,
                     out->minw, out->pd);
     // the fused kernel reaches a tile's rows through 32-bit buffer offsets

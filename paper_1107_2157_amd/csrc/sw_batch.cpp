@@ -83,7 +83,7 @@ sw_status resolve(const sw_batch *b, const sw_tuning &t, Resolved *r) {
     r->order = t.order;
     if (t.rows < 0) return sw_fail(SW_EINVAL, "batch tuning: rows = %d", t.rows);
     if (r->order < 0 || r->order > 1) return sw_fail(SW_EINVAL, "batch tuning: order %d (0 LPT, 1 round-robin)", r->order);
-    if (!sw_fused_supported((int)b->opts.dtype, r->vec, r->minw, r->pd))
+    if (!sw_fused_supported((int)b->opts.dtype, (int)b->opts.scheme, r->vec, r->minw, r->pd))
         return sw_fail(SW_EINVAL, "batch tuning: vec %d / occupancy %d / prefetch %d not available", r->vec, r->minw,
                        r->pd);
     for (int i = 0; i < b->n; ++i)   // the fused kernel reaches a tile's rows through 32-bit buffer offsets
@@ -160,6 +160,7 @@ SwBatchLaunch launch_of(const sw_batch *b, const Resolved &r, int cur, int step)
     a.bc_x = (int)b->opts.bc_x;
     a.bc_y = (int)b->opts.bc_y;
     a.dtype = (int)b->opts.dtype;
+    a.scheme = (int)b->opts.scheme;
     return a;
 }
 
@@ -219,14 +220,17 @@ int sw_batch_internal_prepare(sw_batch *b) {
     return build_tiles(b, r);
 }
 
-int sw_batch_internal_step_masked(sw_batch *b, int nsteps, const int32_t *active, hipStream_t s) {
+int sw_batch_internal_fallback(sw_batch *b, int nsteps, const int32_t *active, hipStream_t s) {
     sw_status st = check_bound(b);
     if (st != SW_OK) return st;
     if (nsteps < 0 || (nsteps & 1)) return sw_fail(SW_EINVAL, "batch: masked steps must be even (%d)", nsteps);
+    if (!active || b->opts.dtype != SW_F32) return sw_fail(SW_EINVAL, "batch: the fallback runs FP32 batches");
     Resolved r;
     if ((st = resolve(b, b->tuning, &r)) != SW_OK) return st;
-    if ((st = build_tiles(b, r)) != SW_OK) return st;
-    return enqueue(b, r, nsteps, b->cur, s, active);
+    SwBatchLaunch a = launch_of(b, r, b->cur, 0);
+    a.active = active;
+    BHIP(sw_batch_launch_fallback(a, b->n, nsteps, s));
+    return SW_OK;
 }
 
 int sw_batch_internal_set_cur(sw_batch *b, int cur) {
@@ -292,7 +296,6 @@ sw_status sw_batch_create(int32_t n, const sw_grid *grids, sw_halo halo, double 
         sw_status st = sw_validate_opts(grids[i], halo, g, dx, opts, &o, &lay[i]);
         if (st != SW_OK) return st;
     }
-    if (o.scheme != SW_SCHEME_PAPER) return sw_fail(SW_ENOTSUP, "batch_create: the batch runs the paper scheme only");
     auto *b = new (std::nothrow) sw_batch();
     if (!b) return sw_fail(SW_ENOMEM, "batch_create: host allocation");
     b->n = n;
@@ -382,10 +385,15 @@ sw_status sw_batch_view(const sw_batch *b, int32_t i, sw_state *view, sw_layout 
 
 sw_status sw_batch_set_tuning(sw_batch *b, const sw_tuning *t) {
     if (!b || !t) return sw_fail(SW_EINVAL, "batch_set_tuning: NULL argument");
-    Resolved r;
+    Resolved r, prev;
     sw_status st = resolve(b, *t, &r);
     if (st != SW_OK) return st;
+    const bool had = resolve(b, b->tuning, &prev) == SW_OK;
     b->tuning = *t;
+    // any change of the launch shape renews the generation, so rollouts
+    // captured by a surrogate with the old shape are captured anew (the tile
+    // table below renews it too when rows, vec or order change)
+    if (!had || std::memcmp(&prev, &r, sizeof r) != 0) b->gen = g_next_gen.fetch_add(1);
     if (b->arena) {
         int dev = -1;
         BHIP(hipGetDevice(&dev));
@@ -549,8 +557,8 @@ sw_status sw_batch_autotune(sw_batch *b, int32_t steps_per_trial, const char *ca
     for (int vi = 0; vi < nv; ++vi)
         for (int occ : {0, 3, 4})
             for (int pd = 1; pd <= 3; ++pd)
-                if (sw_fused_supported((int)b->opts.dtype, vecs[vi], occ, pd))
-                    for (int rows : {8, 16, 32})
+                if (sw_fused_supported((int)b->opts.dtype, (int)b->opts.scheme, vecs[vi], occ, pd))
+                    for (int rows : {2, 4, 8, 16, 32})
                         for (int order = 0; order <= 1; ++order) cands.push_back(sw_tuning{2, rows, vecs[vi], occ, pd, order});
     const bool graph0 = b->use_graph;
     const sw_tuning prev = b->tuning;

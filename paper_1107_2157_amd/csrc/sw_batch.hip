@@ -6,7 +6,7 @@
 // the same grid advanced alone.  Each grid keeps its own CFL ring slots,
 // time and sticky flag.
 #include "sw_batch_internal.h"
-#include "sw_tile.h"
+#include "sw_tile_tr.h"
 
 using namespace sw;
 using namespace sw::tile;
@@ -45,7 +45,7 @@ __device__ __forceinline__ void batch_reduce(const SwBatchLaunch &a, int grid, i
     }
 }
 
-template <typename T, int VEC, int MINW, int PD>
+template <typename T, int VEC, int MINW, int PD, bool TR>
 __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_batch_step(SwBatchLaunch a) {
     const int tile = batch_tile_index();
     if (tile >= a.ntiles) return;                 // whole wave leaves: no barriers are used
@@ -70,7 +70,10 @@ __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_batch_step(SwBat
     T smax = T(0);
     bool bad = false;
     double dt = 0.0;
-    fused_tile<T, VEC, PD>(t, [&] { return batch_dt_finish(a, stripe); }, a.g, a.dx, a.dy, smax, bad, dt);
+    if constexpr (TR)
+        fused_tile_tr<T, VEC, PD>(t, [&] { return batch_dt_finish(a, stripe); }, a.g, a.dx, a.dy, smax, bad, dt);
+    else
+        fused_tile<T, VEC, PD>(t, [&] { return batch_dt_finish(a, stripe); }, a.g, a.dx, a.dy, smax, bad, dt);
     batch_reduce(a, tt.grid, (a.step + 1) % 3, tile, (double)smax, bad);
     if (tt.s == 0 && tt.rb == 0) {               // the grid's first tile keeps its books
         const int lane = threadIdx.x & 63;
@@ -112,6 +115,113 @@ __global__ __launch_bounds__(256) void k_batch_prologue(SwBatchLaunch a, int til
     batch_reduce(a, tt.grid, 0, tile, smax, bad);
 }
 
+// The masked fallback of the surrogate's rollout in one launch: one
+// workgroup per grid, all of that grid's steps.  A grid whose active entry is
+// 0 leaves at once, so a jump the gate accepts everywhere costs one launch.
+// A rejected grid takes the prologue (ghosts and max signal speed of buffer
+// cur) and then nsteps steps of the fused tile body, the workgroup's waves
+// walking its tiles; each step's max speed is reduced in LDS, and its writes
+// reach the next step's loads through an agent-scope release before the
+// barrier and an acquire after it (the acquire drops the CU's vector cache,
+// which may hold lines of the buffer from two steps earlier).  Every cell is
+// computed as in k_batch_step and every dt from the same max, so the grid
+// ends bitwise where a prologue and nsteps launches of k_batch_step leave
+// it, with the same time and step count.
+constexpr int kFbWaves = 8;
+
+template <typename T, int VEC, int PD, bool TR>
+__global__ __launch_bounds__(64 * kFbWaves) void k_batch_fallback(SwBatchLaunch a, int nsteps) {
+    const int gi = blockIdx.x;
+    if (!a.active[gi]) return;                  // uniform: the whole workgroup leaves
+    const SwBatchGrid &gd = a.grids[gi];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    __shared__ double s_max[kFbWaves];
+    __shared__ unsigned s_bad[kFbWaves];
+    __shared__ double s_dt;
+    const T g = (T)a.g;
+    const int nx = gd.nx, ny = gd.ny;
+    int cur = a.cur;
+
+    // the grid's max speed over the workgroup; thread 0 turns it into the
+    // next dt and raises the flag; every thread sees s_dt after the barrier
+    auto finish = [&](double smax, bool bad) {
+        smax = wave_max(smax);
+        const unsigned long long anybad = __ballot(bad);
+        if (lane == 0) {
+            s_max[wave] = smax;
+            s_bad[wave] = anybad != 0ull;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double m = 0.0;
+            unsigned b = 0u;
+            for (int w = 0; w < kFbWaves; ++w) {
+                m = fmax(m, s_max[w]);
+                b |= s_bad[w];
+            }
+            if (b) atomicOr(&a.sc[gi].unstable, 1u);
+            s_dt = a.dt_fixed > 0 ? a.dt_fixed : a.cfl * fmin(a.dx, a.dy) / m;
+        }
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    };
+
+    {   // prologue: ghosts of U^cur and its max speed
+        T *P[3] = {(T *)gd.plane[cur][0], (T *)gd.plane[cur][1], (T *)gd.plane[cur][2]};
+        double smax = 0.0;
+        bool bad = false;
+        const int64_t n = (int64_t)nx * ny;
+        for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
+            const int j = (int)(c / nx), i = (int)(c - (int64_t)j * nx);
+            const int64_t off = (int64_t)j * gd.pitch + i;
+            U3<T> u = {P[0][off], P[1][off], P[2][off]};
+            T sp = signal_speed(u, g);
+            bad |= !(sp <= finite_max<T>());
+            smax = fmax(smax, (double)sp);
+            if (i == 0 || i == nx - 1 || j == 0 || j == ny - 1)
+                write_ghosts(P, gd.pitch, nx, ny, a.bc_x, a.bc_y, i, j, u);
+        }
+        finish(smax, bad);
+    }
+    constexpr int W = 64 * VEC;
+    const int nstrips = (nx + W - 1) / W, nrb = (ny + a.rows - 1) / a.rows;
+    for (int k = 0; k < nsteps; ++k) {
+        const double dt = s_dt;
+        TileArgs t;
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+            t.in[kk] = gd.plane[cur][kk];
+            t.out[kk] = const_cast<void *>(gd.plane[cur ^ 1][kk]);
+        }
+        t.pitch = gd.pitch;
+        t.nx = nx;
+        t.ny = ny;
+        t.bc_x = a.bc_x;
+        t.bc_y = a.bc_y;
+        t.rows = a.rows;
+        T smax = T(0);
+        bool bad = false;
+        for (int tile = wave; tile < nstrips * nrb; tile += kFbWaves) {
+            t.s = tile % nstrips;
+            t.rb = tile / nstrips;
+            double dt_used = 0.0;
+            if constexpr (TR)
+                fused_tile_tr<T, VEC, PD>(t, [&] { return dt; }, a.g, a.dx, a.dy, smax, bad, dt_used);
+            else
+                fused_tile<T, VEC, PD>(t, [&] { return dt; }, a.g, a.dx, a.dy, smax, bad, dt_used);
+        }
+        if (threadIdx.x == 0) {
+            a.sc[gi].t += dt;
+            a.sc[gi].last_dt = dt;
+            a.sc[gi].steps += 1;
+        }
+        finish((double)smax, bad);
+        cur ^= 1;
+    }
+}
+
 __global__ void k_batch_reset(SwBatchScalars *sc, int n, int clear_time) {
     const int gi = blockIdx.x;
     if (gi >= n) return;
@@ -147,9 +257,9 @@ unsigned batch_blocks(int ntiles) {
     return (unsigned)((blocks + 7) / 8 * 8);
 }
 
-template <typename T, int VEC, int MINW, int PD>
+template <typename T, int VEC, int MINW, int PD, bool TR>
 hipError_t launch_batch_t(const SwBatchLaunch &a, hipStream_t s) {
-    k_batch_step<T, VEC, MINW, PD><<<batch_blocks(a.ntiles), 256, 0, s>>>(a);
+    k_batch_step<T, VEC, MINW, PD, TR><<<batch_blocks(a.ntiles), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -182,11 +292,28 @@ hipError_t sw_batch_launch_prologue(const SwBatchLaunch &a, int vec, hipStream_t
     return hipGetLastError();
 }
 
+hipError_t sw_batch_launch_fallback(const SwBatchLaunch &a, int ngrids, int nsteps, hipStream_t s) {
+    if (ngrids <= 0 || nsteps <= 0) return hipSuccess;
+    if (a.dtype != 0 || !a.active || a.rows < 1) return hipErrorInvalidValue;
+    if (a.scheme == 0) k_batch_fallback<float, 2, 1, false><<<ngrids, 64 * kFbWaves, 0, s>>>(a, nsteps);
+    else k_batch_fallback<float, 2, 1, true><<<ngrids, 64 * kFbWaves, 0, s>>>(a, nsteps);
+    return hipGetLastError();
+}
+
 hipError_t sw_batch_launch_step(const SwBatchLaunch &a, int vec, int minw, int pd, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
 #define SW_BATCH_CASE(T, V, M, P) \
-    if ((a.dtype == 1) == (sizeof(T) == 8) && vec == V && minw == M && pd == P) return launch_batch_t<T, V, M, P>(a, s);
-    SW_FUSED_SHAPES(SW_BATCH_CASE)
+    if ((a.dtype == 1) == (sizeof(T) == 8) && vec == V && minw == M && pd == P) \
+        return launch_batch_t<T, V, M, P, false>(a, s);
+#define SW_BATCH_TR_CASE(T, V, M, P) \
+    if ((a.dtype == 1) == (sizeof(T) == 8) && vec == V && minw == M && pd == P) \
+        return launch_batch_t<T, V, M, P, true>(a, s);
+    if (a.scheme == 0) {
+        SW_FUSED_SHAPES(SW_BATCH_CASE)
+    } else if (a.scheme == 1) {
+        SW_FUSED_TR_SHAPES(SW_BATCH_TR_CASE)
+    }
 #undef SW_BATCH_CASE
+#undef SW_BATCH_TR_CASE
     return hipErrorInvalidValue;
 }

@@ -41,13 +41,20 @@ struct SwBatchLaunch {
     int32_t step;     // ring position
     int32_t rows;     // rows per tile
     double g, dx, dy, cfl, dt_fixed;
-    int32_t bc_x, bc_y, dtype, pad;
+    int32_t bc_x, bc_y, dtype, scheme;   // scheme: 0 paper, 1 transverse
     const int32_t *active;   // optional per-grid mask: grids with 0 are skipped entirely
 };
 
 hipError_t sw_batch_launch_reset(SwBatchScalars *sc, int n, int clear_time, hipStream_t s);
 hipError_t sw_batch_launch_prologue(const SwBatchLaunch &a, int vec, hipStream_t s);
+// persistent: resident blocks only, each wave looping over tiles of its
+// XCD's run of the table (same cells, dt and bookkeeping).
 hipError_t sw_batch_launch_step(const SwBatchLaunch &a, int vec, int minw, int pd, hipStream_t s);
+// FP32 only: prologue and nsteps steps of every grid g < ngrids with
+// a.active[g] != 0, one workgroup per grid, one launch (the other grids
+// return at once).  Bitwise the same as reset-free prologue + nsteps step
+// launches of those grids.
+hipError_t sw_batch_launch_fallback(const SwBatchLaunch &a, int ngrids, int nsteps, hipStream_t s);
 hipError_t sw_batch_launch_copy(const SwBatchGrid *grids, int cur, int n, int nx, int ny, int dtype, void *dense,
                                 int to_dense, hipStream_t s);
 
@@ -64,10 +71,11 @@ int sw_batch_internal_info(const sw_batch *b, SwBatchInfo *info);   // returns s
 // Resolve the tuning and build the tile table now (it allocates and copies
 // synchronously), so that later enqueues only launch kernels.
 int sw_batch_internal_prepare(sw_batch *b);
-// Eager: reset, prologue and nsteps steps for the grids with active[g] != 0
-// (device array), starting from the current buffer.  Does not flip the
-// batch's current buffer (nsteps must be even).
-int sw_batch_internal_step_masked(sw_batch *b, int nsteps, const int32_t *active, hipStream_t s);
+// Eager, one launch: prologue and nsteps steps for the grids with
+// active[g] != 0 (device array), starting from the current buffer; the other
+// grids are left alone.  FP32 batches.  Does not flip the batch's current
+// buffer (nsteps must be even).
+int sw_batch_internal_fallback(sw_batch *b, int nsteps, const int32_t *active, hipStream_t s);
 // A batch with the same grids, options and tuning as src, bound to an arena
 // it allocates (*arena; the caller frees it after sw_batch_destroy).
 int sw_batch_internal_clone(const sw_batch *src, sw_batch **out, void **arena);

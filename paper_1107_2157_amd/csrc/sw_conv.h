@@ -5,14 +5,26 @@
 
 #include "sw_batch_internal.h"
 
-enum { SW_CONV_RELU_BF16 = 0, SW_CONV_RESID_BF16 = 1, SW_CONV_F32 = 2, SW_CONV_DGRAD = 3 };
+enum { SW_CONV_RELU_BF16 = 0, SW_CONV_RESID_BF16 = 1, SW_CONV_F32 = 2, SW_CONV_DGRAD = 3, SW_CONV_RELU_PLANES = 4 };
+
+// Per-channel affine normalisation of the state: x = (u - offset) / scale.
+struct SwNorm {
+    float in_off[3], in_scale[3], out_scale[3];
+};
+struct SwGateStats;
 
 // One 3x3 convolution launch (see sw_conv.hip for layouts).  Modes:
 //   RELU:  y = relu(conv(x) + b)                                (first layer)
 //   RESID: y = x + relu(conv(x) + b), y2 = relu(conv(x) + b)     (residual blocks)
 //   F32:   yf = conv(x) + b in FP32                              (output layer)
 //   DGRAD: G = conv(x) + add, y = G, y2 = G where mask > 0       (input gradient)
+//   RELU_PLANES: RELU with the input read from the FP32 planes of a batch of
+//          grids (buffer cur, ghosts materialised) and normalised on the fly
+//          (the rollout's first layer); the tile at a grid's origin also
+//          clears that grid's gate statistics (clear_stats).
 // Every BF16 output may be null except y in RELU / RESID and y2 in DGRAD.
+// F32 with dh_part set also writes, per grid and output row, the sum of the
+// row's channel-0 outputs (FP64, fixed order) at dh_part[b * H + y].
 struct SwConvArgs {
     const void *x;       // BF16 NHWC input with halo, CIN channels
     const void *w;       // BF16 [COUT padded to 16][K padded to 32] implicit-GEMM weights
@@ -23,26 +35,22 @@ struct SwConvArgs {
     const void *add;     // BF16 NHWC with halo, COUT channels, added before rounding (DGRAD)
     const void *mask;    // BF16 NHWC with halo, COUT channels: y2 kept where mask > 0 (DGRAD)
     int B, H, W;
+    int max_blocks;      // cap on the persistent grid (0: one block per resident slot)
+    const SwBatchGrid *grids;   // RELU_PLANES: the batch's grids (all H x W)
+    int cur;                    // RELU_PLANES: buffer holding the state
+    SwNorm nrm;                 // RELU_PLANES: input normalisation
+    SwGateStats *clear_stats;   // RELU_PLANES: gate statistics to clear (may be null)
+    double *dh_part;            // F32: per-row sums of channel 0 (may be null)
 };
 hipError_t sw_conv3x3(const SwConvArgs &a, int cin, int cout, int mode, hipStream_t s);
 // Compute units of the current device (for persistent grids).
 int sw_device_cus();
-
-// Per-channel affine normalisation of the state: x = (u - offset) / scale.
-struct SwNorm {
-    float in_off[3], in_scale[3], out_scale[3];
-};
 
 // Dense FP32 frames [B][3][H][W] -> network input X0 (BF16 NHWC, 8 channels,
 // halo = reflective / periodic ghost values) and, if u8 != nullptr, the
 // target (u8 - u) / out_scale as FP32 [B][H][W][4].
 hipError_t sw_sur_prep_dense(const float *u, const float *u8, int B, int H, int W, int bc_x, int bc_y, SwNorm nrm,
                              void *x0, float *target, hipStream_t s);
-// Batch planes (current buffer, halo filled) of grids [0, B) -> X0; clears
-// the gate statistics st[0, B) of the jump (struct SwGateStats below).
-struct SwGateStats;
-hipError_t sw_sur_prep_planes(const SwBatchGrid *grids, int cur, int B, int H, int W, SwNorm nrm, void *x0,
-                              SwGateStats *st, hipStream_t s);
 // MSE loss over the three channels: per-block partial sums into partial[nblocks],
 // and dZ = 2 (pred - target) / (3 B H W) as BF16 NHWC with halo, 8 channels.
 hipError_t sw_sur_loss(const float *pred, const float *target, int B, int H, int W, float *partial, int nblocks,
@@ -76,15 +84,16 @@ hipError_t sw_sur_relayout(const float *master, const SwLayerDesc *layers, int n
 // update U' = U + denorm(delta) (- mean dh if projecting) written into the
 // other buffer, and the gate's mass / min-h / finiteness statistics.
 struct SwGateStats {
-    double mass_old, mass_new, dh_sum;
+    double mass_old, mass_new;
     float hmin;
     unsigned int nonfinite;
     int fallback;
     int pad;
 };
-hipError_t sw_sur_delta_sum(const float *delta, int B, int H, int W, SwGateStats *st, hipStream_t s);
-hipError_t sw_sur_apply(const float *delta, const SwBatchGrid *grids, int cur, int B, int H, int W, SwNorm nrm,
-                        int project, int bcx, int bcy, SwGateStats *st, hipStream_t s);
+// dh_part: the output layer's per-row sums of the normalised dh (B * H
+// doubles), summed per grid in a fixed order for the mass projection.
+hipError_t sw_sur_apply(const float *delta, const double *dh_part, const SwBatchGrid *grids, int cur, int B, int H,
+                        int W, SwNorm nrm, int project, int bcx, int bcy, SwGateStats *st, hipStream_t s);
 // The gate's verdict per grid (active[b] = 1 and fallbacks[b] += 1 for a
 // rejected jump); rejected grids get U^n (buffer cur, halos included) copied
 // over the prediction in buffer cur ^ 1, where the solver then takes the jump.

@@ -81,9 +81,24 @@ __global__ __launch_bounds__(64 * ROWS) void k_conv3x3(SwConvArgs a, int tiles_y
             const int row = c / (kStageCols * CIN / 8), rem = c - row * (kStageCols * CIN / 8);
             const int yy = ty * ROWS + row;                        // halo row of the input
             stg[k] = bf16x8{};
-            if (c < CHUNKS && yy < a.H + 2)
-                stg[k] = *reinterpret_cast<const bf16x8 *>(
-                    X + (((int64_t)b * (a.H + 2) + yy) * Wp + tx * kTileCols) * CIN + rem * 8);
+            if (c < CHUNKS && yy < a.H + 2) {
+                if constexpr (MODE == SW_CONV_RELU_PLANES) {
+                    // CIN = 8: one chunk is one pixel (h, hu, hv, 0 ...) of grid b's
+                    // buffer cur, normalised as the dense input preparation does
+                    const SwBatchGrid &gd = a.grids[b];
+                    const int64_t off = (int64_t)(yy - 1) * gd.pitch + (tx * kTileCols + rem - 1);
+                    const float h = ((const float *)gd.plane[a.cur][0])[off];
+                    const float hu = ((const float *)gd.plane[a.cur][1])[off];
+                    const float hv = ((const float *)gd.plane[a.cur][2])[off];
+                    stg[k] = bf16x8{(__bf16)((h - a.nrm.in_off[0]) / a.nrm.in_scale[0]),
+                                    (__bf16)((hu - a.nrm.in_off[1]) / a.nrm.in_scale[1]),
+                                    (__bf16)((hv - a.nrm.in_off[2]) / a.nrm.in_scale[2]),
+                                    (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
+                } else {
+                    stg[k] = *reinterpret_cast<const bf16x8 *>(
+                        X + (((int64_t)b * (a.H + 2) + yy) * Wp + tx * kTileCols) * CIN + rem * 8);
+                }
+            }
         }
     };
     auto store_tile = [&](int buf) {
@@ -106,6 +121,15 @@ __global__ __launch_bounds__(64 * ROWS) void k_conv3x3(SwConvArgs a, int tiles_y
         const int y = ty * ROWS + w;                               // output row of this wave
         const int x0 = tx * kTileCols;
         const __bf16 *T = tile[buf];
+        if constexpr (MODE == SW_CONV_RELU_PLANES) {                // a grid's first tile clears its statistics
+            if (a.clear_stats && ty == 0 && tx == 0 && threadIdx.x == 0) {
+                SwGateStats &st = a.clear_stats[b];
+                st.mass_old = 0.0;
+                st.mass_new = 0.0;
+                st.hmin = 3.0e38f;
+                st.nonfinite = 0u;
+            }
+        }
 
         f32x4 acc[MB][NPB];
 #pragma unroll
@@ -131,6 +155,7 @@ __global__ __launch_bounds__(64 * ROWS) void k_conv3x3(SwConvArgs a, int tiles_y
         // epilogue: lane holds channels co = mb*16 + 4g .. +3 of pixel x0 + pb*16 + n
         if (y < a.H) {
             if (MODE == SW_CONV_F32) {   // channels 0..3 (COUT <= 4) with bias, FP32, no halo
+                double dh = 0.0;         // this lane's channel-0 outputs, for the row sums
 #pragma unroll
                 for (int pb = 0; pb < NPB; ++pb) {
                     if (g != 0) continue;
@@ -139,6 +164,12 @@ __global__ __launch_bounds__(64 * ROWS) void k_conv3x3(SwConvArgs a, int tiles_y
 #pragma unroll
                     for (int q = 0; q < 4; ++q) v[q] = q < COUT ? v[q] + a.bias[q] : 0.f;
                     *reinterpret_cast<f32x4 *>(Y) = v;
+                    dh += (double)v[0];
+                }
+                if (a.dh_part) {         // fixed-order sum of the wave's 64 pixels (one tile row)
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) dh += __shfl_xor(dh, o);
+                    if (lane == 0) a.dh_part[((int64_t)b * a.H + y) * tiles_x + tx] = dh;
                 }
             } else {
                 // The wave's 64 output pixels x COUT channels are one contiguous run of the
@@ -167,7 +198,7 @@ __global__ __launch_bounds__(64 * ROWS) void k_conv3x3(SwConvArgs a, int tiles_y
                     for (int q = 0; q < 4; ++q) v[q] = fmaxf(v[q] + a.bias[mb * 16 + 4 * g + q], 0.f);
                     return v;
                 };
-                if (MODE == SW_CONV_RELU_BF16 || MODE == SW_CONV_RESID_BF16) {
+                if (MODE == SW_CONV_RELU_BF16 || MODE == SW_CONV_RELU_PLANES || MODE == SW_CONV_RESID_BF16) {
 #pragma unroll
                     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -256,7 +287,8 @@ hipError_t launch(const SwConvArgs &a, hipStream_t s) {
                    ? r
                    : 1;
     }();
-    const int64_t blocks = std::min<int64_t>(ntiles, (int64_t)sw_device_cus() * resident);
+    int64_t blocks = std::min<int64_t>(ntiles, (int64_t)sw_device_cus() * resident);
+    if (a.max_blocks > 0) blocks = std::min<int64_t>(blocks, a.max_blocks);
     k_conv3x3<CIN, COUT, MODE, ROWS><<<(unsigned)blocks, 64 * ROWS, 0, s>>>(a, tiles_y, tiles_x, (int)ntiles);
     return hipGetLastError();
 }
@@ -270,10 +302,14 @@ constexpr int kFwdRows = 4;
 }  // namespace
 
 hipError_t sw_conv3x3(const SwConvArgs &a, int cin, int cout, int mode, hipStream_t s) {
-    if (a.B < 1 || a.H < 1 || a.W < 1 || !a.x || !a.w) return hipErrorInvalidValue;
+    if (a.B < 1 || a.H < 1 || a.W < 1 || (!a.x && mode != SW_CONV_RELU_PLANES) || !a.w) return hipErrorInvalidValue;
     if (mode == SW_CONV_F32 ? !a.yf || !a.bias : mode == SW_CONV_DGRAD ? !a.y2 || !a.mask : !a.y || !a.bias)
         return hipErrorInvalidValue;
     if (cin == 8 && cout == 32 && mode == SW_CONV_RELU_BF16) return launch<8, 32, SW_CONV_RELU_BF16, kFwdRows>(a, s);
+    if (cin == 8 && cout == 32 && mode == SW_CONV_RELU_PLANES) {
+        if (!a.grids || a.cur < 0 || a.cur > 1) return hipErrorInvalidValue;
+        return launch<8, 32, SW_CONV_RELU_PLANES, kFwdRows>(a, s);
+    }
     if (cin == 32 && cout == 32 && mode == SW_CONV_RESID_BF16)
         return launch<32, 32, SW_CONV_RESID_BF16, kFwdRows>(a, s);
     if (cin == 32 && cout == 3 && mode == SW_CONV_F32) return launch<32, 3, SW_CONV_F32, kFwdRows>(a, s);

@@ -1,5 +1,6 @@
-// Single-grid fused step kernel for gfx950 (per-tile body in sw_tile.h).
-#include "sw_tile.h"
+// Single-grid fused step kernel for gfx950 (per-tile body in sw_tile.h; with
+// the transverse term in sw_tile_tr.h).
+#include "sw_tile_tr.h"
 
 using namespace sw;
 using namespace sw::tile;
@@ -8,7 +9,8 @@ namespace {
 
 // MINW: register budget expressed as waves per SIMD (0 = compiler's choice).
 // PD: rows loaded ahead of the row being processed (software pipeline depth).
-template <typename T, int VEC, int MINW, int PD>
+// TR: the transverse scheme.
+template <typename T, int VEC, int MINW, int PD, bool TR>
 __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_step_fused(SwLaunch a, int rows, int nstrips, int nrb,
                                                                            int order) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -40,7 +42,10 @@ __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_step_fused(SwLau
         t.pitch = a.pitch;
         t.nx = a.nx; t.ny = a.ny; t.bc_x = a.bc_x; t.bc_y = a.bc_y;
         t.s = s; t.rb = rb; t.rows = rows;
-        fused_tile<T, VEC, PD>(t, [&] { return step_dt_finish(a, stripe); }, a.g, a.dx, a.dy, smax, bad, dt);
+        if constexpr (TR)
+            fused_tile_tr<T, VEC, PD>(t, [&] { return step_dt_finish(a, stripe); }, a.g, a.dx, a.dy, smax, bad, dt);
+        else
+            fused_tile<T, VEC, PD>(t, [&] { return step_dt_finish(a, stripe); }, a.g, a.dx, a.dy, smax, bad, dt);
     } else {
         dt = step_dt_finish(a, stripe);
     }
@@ -48,7 +53,7 @@ __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_step_fused(SwLau
     step_epilogue(a, (double)smax, bad, dt, blockIdx.x == 0 && wave == 0, (int)blockIdx.x * 4 + wave);
 }
 
-template <typename T, int VEC, int MINW, int PD>
+template <typename T, int VEC, int MINW, int PD, bool TR>
 hipError_t launch_fused_t(const SwLaunch &a, int rows, int order, hipStream_t s) {
     constexpr int W = 64 * VEC;
     const int nstrips = (a.nx + W - 1) / W;
@@ -58,7 +63,7 @@ hipError_t launch_fused_t(const SwLaunch &a, int rows, int order, hipStream_t s)
     int64_t blocks = (ntiles + 3) / 4;
     blocks = (blocks + 7) / 8 * 8;
     if (blocks > 0x3fffffff) return hipErrorInvalidValue;
-    k_step_fused<T, VEC, MINW, PD><<<(unsigned)blocks, 256, 0, s>>>(a, rows, nstrips, nrb, order);
+    k_step_fused<T, VEC, MINW, PD, TR><<<(unsigned)blocks, 256, 0, s>>>(a, rows, nstrips, nrb, order);
     return hipGetLastError();
 }
 
@@ -87,20 +92,32 @@ bool sw_fused_tile_fits(int rows, int64_t pitch, int elem_bytes) {
     return rows >= 1 && ((int64_t)rows + 2) * pitch * (int64_t)elem_bytes <= 0x7fffffff;
 }
 
-bool sw_fused_supported(int dtype, int vec, int minw, int pd) {
+bool sw_fused_supported(int dtype, int scheme, int vec, int minw, int pd) {
 #define SW_FUSED_SUP(T, V, M, P) \
     if ((dtype == 1) == (sizeof(T) == 8) && vec == V && minw == M && pd == P) return true;
-    SW_FUSED_SHAPES(SW_FUSED_SUP)
+    if (scheme == 0) {
+        SW_FUSED_SHAPES(SW_FUSED_SUP)
+    } else if (scheme == 1) {
+        SW_FUSED_TR_SHAPES(SW_FUSED_SUP)
+    }
 #undef SW_FUSED_SUP
     return false;
 }
 
 hipError_t sw_launch_fused_cfg(const SwLaunch &a, int rows, int vec, int minw, int pd, int order, hipStream_t s) {
-    if (a.scheme != 0 || rows < 1 || order < 0 || order > 2) return hipErrorInvalidValue;
+    if (a.scheme < 0 || a.scheme > 1 || rows < 1 || order < 0 || order > 2) return hipErrorInvalidValue;
 #define SW_FUSED_CASE(T, V, M, P) \
     if ((a.dtype == 1) == (sizeof(T) == 8) && vec == V && minw == M && pd == P) \
-        return launch_fused_t<T, V, M, P>(a, rows, order, s);
-    SW_FUSED_SHAPES(SW_FUSED_CASE)
+        return launch_fused_t<T, V, M, P, false>(a, rows, order, s);
+#define SW_FUSED_TR_CASE(T, V, M, P) \
+    if ((a.dtype == 1) == (sizeof(T) == 8) && vec == V && minw == M && pd == P) \
+        return launch_fused_t<T, V, M, P, true>(a, rows, order, s);
+    if (a.scheme == 0) {
+        SW_FUSED_SHAPES(SW_FUSED_CASE)
+    } else {
+        SW_FUSED_TR_SHAPES(SW_FUSED_TR_CASE)
+    }
 #undef SW_FUSED_CASE
+#undef SW_FUSED_TR_CASE
     return hipErrorInvalidValue;
 }

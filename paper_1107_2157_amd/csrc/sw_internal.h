@@ -68,7 +68,7 @@ int sw_tb_tile_rows(int dtype, int k);   // output rows per blocked tile (one gr
 // waves per block: 4, 8, 12 or 16 (the tile is the same; each wave marches one chunk of its rows).
 hipError_t sw_launch_tb(const SwLaunch &a, int k, int waves, hipStream_t s);
 int sw_fused_default_vec(int dtype, int nx);
-bool sw_fused_supported(int dtype, int vec, int minw, int pd);
+bool sw_fused_supported(int dtype, int scheme, int vec, int minw, int pd);
 // A fused tile of `rows` rows (plus its two halo rows) of `pitch`-element rows
 // fits the kernel's 32-bit buffer offsets.
 bool sw_fused_tile_fits(int rows, int64_t pitch, int elem_bytes);
@@ -110,3 +110,8 @@ hipError_t sw_launch_rgn(const SwLaunch &a, int design, int rows, int prefetch, 
     X(double, 1, 3, 2) X(double, 1, 3, 3) X(double, 1, 4, 1) X(double, 1, 4, 2)                 \
     X(double, 1, 4, 3) X(double, 2, 0, 1) X(double, 2, 0, 2) X(double, 2, 0, 3)                 \
     X(double, 2, 3, 1) X(double, 2, 3, 2)
+// The instantiated launch shapes of the transverse scheme (fused and batched
+// kernels): default register budget, prefetch depth 1 or 2.
+#define SW_FUSED_TR_SHAPES(X)                                                                   \
+    X(float, 1, 0, 1) X(float, 1, 0, 2) X(float, 2, 0, 1) X(float, 2, 0, 2) X(float, 4, 0, 1)   \
+    X(float, 4, 0, 2) X(double, 1, 0, 1) X(double, 1, 0, 2) X(double, 2, 0, 1) X(double, 2, 0, 2)

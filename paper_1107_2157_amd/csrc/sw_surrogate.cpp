@@ -42,6 +42,7 @@ struct sw_net {
     // NHWC BF16 tensors with halo; relu[k] = relu(Z) of residual block k + 1 (its mask)
     void *x0 = nullptr, *act[kLayers - 1] = {}, *relu[kLayers - 2] = {}, *g[2] = {}, *dz[2] = {}, *dz6 = nullptr;
     float *delta = nullptr, *target = nullptr;
+    double *dh_part = nullptr;   // rollout: the output layer's per-row sums of dh ([B][H][W / 64])
     SwGateStats *stats = nullptr;
     int32_t *active = nullptr;
     // judge mode: a clone of the advanced batch that runs the plain solver
@@ -50,6 +51,7 @@ struct sw_net {
     SwJudge *judge = nullptr;
     int32_t *reject = nullptr;
     SwNorm nrm{};
+    int block_cap = 0;   // cap on the persistent conv / weight-gradient grids (0: resident slots)
     int64_t adam_t = 0;
     std::vector<void *> allocs;
     // unjudged rollouts replay one hipGraph per (batch and its generation,
@@ -100,19 +102,37 @@ SwConvArgs conv_args(const sw_net *n, int B, const void *x) {
     a.B = B;
     a.H = n->H;
     a.W = n->W;
+    a.max_blocks = n->block_cap;
     return a;
 }
 
-// X0 -> act[0..4] -> delta; with train, also the ReLU parts (backward masks)
-sw_status forward(const sw_net *n, int B, bool train, hipStream_t s) {
+// X0 -> act[0..4] -> delta; with train, also the ReLU parts (backward masks).
+// With `planes` (a rollout) the first layer reads the batch's buffer directly
+// (normalising it and clearing the jump's gate statistics) instead of X0, and
+// the output layer also writes the per-row sums of dh when `dh_part` is set.
+struct RolloutInput {
+    const SwBatchGrid *grids;
+    int cur;
+    bool dh_sums;
+};
+sw_status forward(const sw_net *n, int B, bool train, hipStream_t s, const RolloutInput *planes = nullptr) {
     for (int l = 0; l < kLayers; ++l) {
         const SwLayerDesc &L = n->L[l];
         SwConvArgs a = conv_args(n, B, l == 0 ? n->x0 : n->act[l - 1]);
         a.w = L.wk;
         a.bias = n->master + L.b_off;
         int mode = SW_CONV_RELU_BF16;
+        if (l == 0 && planes) {
+            mode = SW_CONV_RELU_PLANES;
+            a.x = nullptr;
+            a.grids = planes->grids;
+            a.cur = planes->cur;
+            a.nrm = n->nrm;
+            a.clear_stats = n->stats;
+        }
         if (l == kLayers - 1) {
             a.yf = n->delta;
+            if (planes && planes->dh_sums) a.dh_part = n->dh_part;
             mode = SW_CONV_F32;
         } else {
             a.y = n->act[l];
@@ -137,7 +157,8 @@ sw_status backward(sw_net *n, int B, float *loss_out, hipStream_t s) {
     for (int l = kLayers - 1; l >= 0; --l) {
         const SwLayerDesc &L = n->L[l];
         SHIP(sw_sur_wgrad(dz, dzc, L.cout, l == 0 ? n->x0 : n->act[l - 1], L.cinp, L.cin, B, n->H, n->W,
-                          n->wpartial, kWgradBlocks, n->grad + L.w_off, n->grad + L.b_off, s));
+                          n->wpartial, n->block_cap > 0 ? n->block_cap : kWgradBlocks, n->grad + L.w_off,
+                          n->grad + L.b_off, s));
         if (l == 0) break;
         SwConvArgs a = conv_args(n, B, dz);
         a.w = L.wd;
@@ -235,6 +256,7 @@ sw_status sw_surrogate_create(const sw_net_cfg *cfg, int32_t H, int32_t W, int32
     if (st == SW_OK) st = dalloc(n, (void **)&n->delta, (size_t)max_batch * H * W * 16);
     if (st == SW_OK) st = dalloc(n, (void **)&n->target, (size_t)max_batch * H * W * 16);
     if (st == SW_OK) st = dalloc(n, (void **)&n->stats, (size_t)max_batch * sizeof(SwGateStats));
+    if (st == SW_OK) st = dalloc(n, (void **)&n->dh_part, (size_t)max_batch * H * (W / 64) * sizeof(double));
     if (st == SW_OK) st = dalloc(n, (void **)&n->active, (size_t)max_batch * 4);
     if (st == SW_OK) st = dalloc(n, (void **)&n->judge, (size_t)max_batch * sizeof(SwJudge));
     if (st == SW_OK) st = dalloc(n, (void **)&n->reject, (size_t)max_batch * 4);
@@ -304,6 +326,15 @@ sw_status sw_surrogate_set_graph(sw_net *n, int32_t enable) {
     if (!n) return sw_fail(SW_EINVAL, "surrogate_set_graph: NULL network");
     n->use_graph = enable != 0;
     if (!n->use_graph) drop_graphs(n);
+    return SW_OK;
+}
+
+sw_status sw_surrogate_set_block_cap(sw_net *n, int32_t max_blocks) {
+    if (!n) return sw_fail(SW_EINVAL, "surrogate_set_block_cap: NULL network");
+    if (max_blocks < 0 || max_blocks > kWgradBlocks)
+        return sw_fail(SW_EINVAL, "surrogate_set_block_cap: %d outside [0, %d]", max_blocks, kWgradBlocks);
+    n->block_cap = max_blocks;
+    drop_graphs(n);   // captured rollouts hold the old launch shapes
     return SW_OK;
 }
 
@@ -378,18 +409,17 @@ sw_status enqueue_rollout(sw_net *n, sw_batch *solver, const SwBatchInfo &bi, in
     if ((st = sw_batch_fill_halo(solver, s)) != SW_OK) return st;
     for (int j = 0; j < nsteps / n->cfg.jump; ++j) {
         // U^n in buffer cur; every grid's U^{n+jump} ends in buffer cur ^ 1
-        SHIP(sw_sur_prep_planes(bi.d_grids, cur, B, n->H, n->W, n->nrm, n->x0, n->stats, s));
-        if ((st = forward(n, B, false, s)) != SW_OK) return st;
-        if (gate->project_mass) SHIP(sw_sur_delta_sum(n->delta, B, n->H, n->W, n->stats, s));
-        SHIP(sw_sur_apply(n->delta, bi.d_grids, cur, B, n->H, n->W, n->nrm, gate->project_mass, bi.bc_x, bi.bc_y,
-                          n->stats, s));
+        const RolloutInput in{bi.d_grids, cur, gate->project_mass != 0};
+        if ((st = forward(n, B, false, s, &in)) != SW_OK) return st;
+        SHIP(sw_sur_apply(n->delta, n->dh_part, bi.d_grids, cur, B, n->H, n->W, n->nrm, gate->project_mass, bi.bc_x,
+                          bi.bc_y, n->stats, s));
         // the gate; rejected grids: U^n over the prediction, then the plain solver takes the jump (an
         // even number of steps, so it ends where it started); accepted grids keep the prediction
         SHIP(sw_sur_gate_restore(bi.d_grids, cur, B, n->H, n->W, n->stats, gate->mass_rel_tol, gate->hmin, n->active,
                                  fallbacks, s));
         cur ^= 1;
         if ((st = (sw_status)sw_batch_internal_set_cur(solver, cur)) != SW_OK) return st;
-        if ((st = (sw_status)sw_batch_internal_step_masked(solver, n->cfg.jump, n->active, s)) != SW_OK) return st;
+        if ((st = (sw_status)sw_batch_internal_fallback(solver, n->cfg.jump, n->active, s)) != SW_OK) return st;
     }
     return SW_OK;
 }

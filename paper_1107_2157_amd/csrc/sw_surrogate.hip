@@ -74,35 +74,6 @@ __global__ __launch_bounds__(256) void k_prep_dense(const float *u, const float 
     }
 }
 
-// Network input of a jump from every grid's buffer cur; also clears the
-// jump's gate statistics (st, one entry per grid) for the kernels after the
-// network.
-__global__ __launch_bounds__(256) void k_prep_planes(const SwBatchGrid *grids, int cur, int B, int H, int W, SwNorm nrm,
-                                                     __bf16 *x0, SwGateStats *st) {
-    const int Wp = W + 2, Hp = H + 2;
-    const int64_t n = (int64_t)B * Hp * Wp;
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid < B) {
-        st[gid].mass_old = 0.0;
-        st[gid].mass_new = 0.0;
-        st[gid].dh_sum = 0.0;
-        st[gid].hmin = 3.0e38f;
-        st[gid].nonfinite = 0u;
-    }
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
-        const int b = (int)(idx / ((int64_t)Hp * Wp));
-        const int r = (int)(idx - (int64_t)b * Hp * Wp);
-        const int yy = r / Wp, xx = r - yy * Wp;
-        const SwBatchGrid &g = grids[b];
-        const int64_t off = (int64_t)(yy - 1) * g.pitch + (xx - 1);   // halo cells are materialised
-        const float h = ((const float *)g.plane[cur][0])[off];
-        const float hu = ((const float *)g.plane[cur][1])[off];
-        const float hv = ((const float *)g.plane[cur][2])[off];
-        store_x0(x0 + idx * 8, (h - nrm.in_off[0]) / nrm.in_scale[0], (hu - nrm.in_off[1]) / nrm.in_scale[1],
-                 (hv - nrm.in_off[2]) / nrm.in_scale[2]);
-    }
-}
-
 __global__ __launch_bounds__(256) void k_loss(const float *pred, const float *target, int B, int H, int W,
                                               float *partial, __bf16 *dz) {
     const int64_t n = (int64_t)B * H * W;
@@ -360,27 +331,29 @@ __global__ void k_relayout(const float *master, const SwLayerDesc *layers, int n
     if (L.wd) reinterpret_cast<__bf16 *>(L.wd)[(int64_t)ci * L.kpd + (8 - tap) * L.cdp + co] = (__bf16)w;
 }
 
-// Per grid (blockIdx.y): sum of the normalised dh over its pixels (one
-// atomic per block: the four waves' sums are added in LDS first).
-__global__ __launch_bounds__(256) void k_delta_sum(const float *delta, int H, int W, SwGateStats *st) {
-    __shared__ double s_acc[4];
-    const int b = blockIdx.y;
-    const int64_t n = (int64_t)H * W;
-    double acc = 0.0;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
-        acc += delta[((int64_t)b * n + p) * 4];
-    acc = wave_sum_d(acc);
-    if ((threadIdx.x & 63) == 0) s_acc[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(&st[b].dh_sum, (s_acc[0] + s_acc[1]) + (s_acc[2] + s_acc[3]));
-}
-
-__global__ __launch_bounds__(256) void k_apply(const float *delta, const SwBatchGrid *grids, int cur, int H, int W,
-                                               SwNorm nrm, int project, int bcx, int bcy, SwGateStats *st) {
+// Per grid (blockIdx.y): U' = U + denorm(delta) (less the mean dh when
+// projecting) into buffer cur ^ 1 with its ghosts, and the gate statistics.
+// The mean dh comes from the output layer's per-row sums, added by every
+// block in the same fixed order (so every block, and every run, gets the
+// same value).
+__global__ __launch_bounds__(256) void k_apply(const float *delta, const double *dh_part, const SwBatchGrid *grids,
+                                               int cur, int H, int W, SwNorm nrm, int project, int bcx, int bcy,
+                                               SwGateStats *st) {
     const int b = blockIdx.y;
     const SwBatchGrid &g = grids[b];
     const int64_t n = (int64_t)H * W;
-    const float dh_mean = project ? (float)(st[b].dh_sum / (double)n) : 0.f;
+    float dh_mean = 0.f;
+    if (project) {
+        __shared__ double s_part[4];
+        const int nparts = H * (W / 64);
+        const double *part = dh_part + (int64_t)b * nparts;
+        double acc = 0.0;
+        for (int k = threadIdx.x; k < nparts; k += blockDim.x) acc += part[k];
+        acc = wave_sum_d(acc);
+        if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        dh_mean = (float)(((s_part[0] + s_part[1]) + (s_part[2] + s_part[3])) / (double)n);
+    }
     const float *U[3] = {(const float *)g.plane[cur][0], (const float *)g.plane[cur][1], (const float *)g.plane[cur][2]};
     float *O[3] = {(float *)g.plane[cur ^ 1][0], (float *)g.plane[cur ^ 1][1], (float *)g.plane[cur ^ 1][2]};
     double mo = 0.0, mn = 0.0;
@@ -534,12 +507,6 @@ hipError_t sw_sur_prep_dense(const float *u, const float *u8, int B, int H, int 
     return hipGetLastError();
 }
 
-hipError_t sw_sur_prep_planes(const SwBatchGrid *grids, int cur, int B, int H, int W, SwNorm nrm, void *x0,
-                              SwGateStats *st, hipStream_t s) {
-    // every grid's statistics entry needs a thread: the grid covers B threads at least
-    k_prep_planes<<<grid_for((int64_t)B * (H + 2) * (W + 2)), 256, 0, s>>>(grids, cur, B, H, W, nrm, (__bf16 *)x0, st);
-    return hipGetLastError();
-}
 
 hipError_t sw_sur_loss(const float *pred, const float *target, int B, int H, int W, float *partial, int nblocks,
                        void *dz, hipStream_t s) {
@@ -611,16 +578,12 @@ unsigned per_grid_blocks(int64_t n, int B) {
     return grid_for(n, cap);
 }
 
-hipError_t sw_sur_delta_sum(const float *delta, int B, int H, int W, SwGateStats *st, hipStream_t s) {
-    dim3 grid(per_grid_blocks((int64_t)H * W, B), B);
-    k_delta_sum<<<grid, 256, 0, s>>>(delta, H, W, st);
-    return hipGetLastError();
-}
 
-hipError_t sw_sur_apply(const float *delta, const SwBatchGrid *grids, int cur, int B, int H, int W, SwNorm nrm,
-                        int project, int bcx, int bcy, SwGateStats *st, hipStream_t s) {
+hipError_t sw_sur_apply(const float *delta, const double *dh_part, const SwBatchGrid *grids, int cur, int B, int H,
+                        int W, SwNorm nrm, int project, int bcx, int bcy, SwGateStats *st, hipStream_t s) {
+    if (project && (!dh_part || W % 64 != 0)) return hipErrorInvalidValue;
     dim3 grid(per_grid_blocks((int64_t)H * W, B), B);
-    k_apply<<<grid, 256, 0, s>>>(delta, grids, cur, H, W, nrm, project, bcx, bcy, st);
+    k_apply<<<grid, 256, 0, s>>>(delta, dh_part, grids, cur, H, W, nrm, project, bcx, bcy, st);
     return hipGetLastError();
 }
 

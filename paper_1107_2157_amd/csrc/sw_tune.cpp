@@ -100,9 +100,7 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
     }
 
     std::vector<sw_tuning> cands;
-    if (opts.scheme != SW_SCHEME_PAPER) {
-        cands.push_back(sw_tuning{1, 0, 0, 0, 0, 0});
-    } else {
+    {
         const int vecs_f32[] = {1, 2, 4}, vecs_f64[] = {1, 2};
         const int *vecs = opts.dtype == SW_F64 ? vecs_f64 : vecs_f32;
         const int nvec = opts.dtype == SW_F64 ? 2 : 3;
@@ -111,11 +109,11 @@ extern "C" sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per
         for (int vi = 0; vi < nvec; ++vi)
             for (int occ : occs)
                 for (int pd = 1; pd <= 3; ++pd)
-                    if (sw_fused_supported((int)opts.dtype, vecs[vi], occ, pd))
+                    if (sw_fused_supported((int)opts.dtype, (int)opts.scheme, vecs[vi], occ, pd))
                         for (int rows : rows_list)
                             for (int order = 0; order <= 1; ++order)
                                 cands.push_back(sw_tuning{2, rows, vecs[vi], occ, pd, order});
-        if (opts.dt_fixed > 0)   // temporal blocking: K steps per launch
+        if (opts.dt_fixed > 0 && opts.scheme == SW_SCHEME_PAPER)   // temporal blocking: K steps per launch
             for (int k : {3, 5, 7})
                 for (int waves : {8, 12, 16})
                     if (sw_tb_supported((int)opts.dtype, k)) cands.push_back(sw_tuning{3, k, waves, 0, 0, 0});

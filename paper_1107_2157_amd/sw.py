@@ -137,6 +137,7 @@ SIGNATURES = {
     "sw_surrogate_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                                ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p]),
     "sw_surrogate_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "sw_surrogate_set_block_cap": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "sw_surrogate_advance": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Gate),
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sw_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -290,14 +291,15 @@ class Batch:
     whole call replayed as one hipGraph."""
 
     def __init__(self, sides, g: float = 9.8, dx: float = 1.0, dtype="f32", bc_x: int = REFLECT,
-                 bc_y: int = REFLECT, dy: float = 0.0, cfl: float = 0.5, dt_fixed: float = 0.0, device="cuda"):
+                 bc_y: int = REFLECT, dy: float = 0.0, cfl: float = 0.5, dt_fixed: float = 0.0, device="cuda",
+                 scheme: int = SCHEME_PAPER):
         shapes = [(s, s) if isinstance(s, int) else tuple(s) for s in sides]
         self.n = len(shapes)
         self.shapes = shapes
         self.dtype = _DT[dtype]
         self.torch_dtype = _TORCH_DT[self.dtype]
         grids = (Grid * self.n)(*[Grid(nx, ny) for nx, ny in shapes])
-        opts = Opts(self.dtype, bc_x, bc_y, SCHEME_PAPER, dy, cfl, dt_fixed)
+        opts = Opts(self.dtype, bc_x, bc_y, scheme, dy, cfl, dt_fixed)
         h = ctypes.c_void_p()
         check(lib().sw_batch_create(self.n, grids, Halo(1, 1, 1, 1), g, dx, ctypes.byref(opts), ctypes.byref(h)),
               "sw_batch_create")
@@ -484,6 +486,10 @@ class Surrogate:
     def set_graph(self, enable: bool):
         """Unjudged rollouts replay captured graphs (True, the default) or launch eagerly."""
         check(lib().sw_surrogate_set_graph(self.handle, 1 if enable else 0), "sw_surrogate_set_graph")
+
+    def set_block_cap(self, max_blocks: int):
+        """Cap the persistent convolution / weight-gradient grids (0: one block per resident slot)."""
+        check(lib().sw_surrogate_set_block_cap(self.handle, max_blocks), "sw_surrogate_set_block_cap")
 
     def forward(self, u: torch.Tensor) -> torch.Tensor:
         """u: [B][3][H][W] FP32 on the GPU -> normalised delta [B][H][W][4]."""

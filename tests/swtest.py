@@ -27,15 +27,3 @@ def gpu_available():
 def announce(msg: str):
     """Print (and flush) what a GPU step is about to run."""
     print(f"[gpu-case] {msg}", flush=True)
-
-
-def assert_fused_refuses_transverse(dtype):
-    """The fused step kernel implements the paper's scheme only: asking it for
-    the transverse scheme fails with SW_ENOTSUP (at the variant choice or at
-    the first step) instead of computing something else."""
-    import pytest
-    from paper_1107_2157_amd import sw
-    with pytest.raises(sw.SwError) as e:
-        s = sw.Solver(16, 8, dtype=dtype, scheme=sw.SCHEME_TRANSVERSE, variant=sw.VARIANT_FUSED)
-        s.step(1)
-    assert e.value.status == sw.ENOTSUP

@@ -106,7 +106,7 @@ def batch_create(grids, **kw):
 
 @pytest.mark.parametrize("grids,kw,status", [
     ([], {}, sw.EINVAL), ([(8, 8), (0, 8)], {}, sw.EINVAL), ([(8, 8)], dict(cfl=0.0), sw.EINVAL),
-    ([(8, 8)], dict(scheme=1), sw.ENOTSUP), ([(8, 8)], dict(bc_y=7), sw.EINVAL),
+    ([(8, 8)], dict(scheme=7), sw.EINVAL), ([(8, 8)], dict(bc_y=7), sw.EINVAL),
 ])
 def test_batch_create_validates_before_any_hip_call(grids, kw, status):
     st, detail = batch_create(grids, **kw)
@@ -166,3 +166,4 @@ def test_binding_checks_tensors_before_the_abi():
         sw._device_tensor(torch.zeros(2, 3, 4, 4), (2, 3, 4, 4), torch.float32, "u")
     with pytest.raises(ValueError, match="shape"):
         sw._device_tensor([1.0, 2.0], (2,), torch.float32, "u")
+

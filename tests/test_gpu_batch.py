@@ -35,16 +35,17 @@ def make_batch(shapes, sts, dtype, bc, tuning, graph=True, **kw):
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 @pytest.mark.parametrize("bc", [sw.REFLECT, sw.PERIODIC])
 @pytest.mark.parametrize("graph", [True, False])
-def test_batch_equals_each_grid_alone(dtype, bc, graph):
+@pytest.mark.parametrize("scheme", [sw.SCHEME_PAPER, sw.SCHEME_TRANSVERSE])
+def test_batch_equals_each_grid_alone(dtype, bc, graph, scheme):
     tun = dict(variant=2, rows=16, vec=2, occupancy=0, prefetch=2, order=0)
     sts = states(SHAPES, 100, bc == sw.PERIODIC)
-    announce(f"batch {dtype} bc{bc} graph{graph}")
-    b = make_batch(SHAPES, sts, dtype, bc, tun, graph)
+    announce(f"batch {dtype} bc{bc} graph{graph} scheme{scheme}")
+    b = make_batch(SHAPES, sts, dtype, bc, tun, graph, scheme=scheme)
     b.step(7)
     b.step(4)
     t_b, n_b, _ = b.sync_status()
     for i, (nx, ny) in enumerate(SHAPES):
-        s = sw.Solver(nx, ny, dtype=dtype, bc_x=bc, bc_y=bc)
+        s = sw.Solver(nx, ny, dtype=dtype, bc_x=bc, bc_y=bc, scheme=scheme)
         s.set_tuning(**tun)
         s.set_state(*sts[i])
         s.step(7)
@@ -58,15 +59,16 @@ def test_batch_equals_each_grid_alone(dtype, bc, graph):
 
 
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
-def test_batch_matches_oracle(dtype, tol):
-    shapes = [(96, 80), (33, 150), (128, 128)]
+@pytest.mark.parametrize("scheme", [sw.SCHEME_PAPER, sw.SCHEME_TRANSVERSE])
+def test_batch_matches_oracle(dtype, tol, scheme):
+    shapes = [(96, 80), (33, 150), (128, 128), (1, 9)]
     sts = states(shapes, 300, False)
-    b = make_batch(shapes, sts, dtype, sw.REFLECT, dict(variant=2))
+    b = make_batch(shapes, sts, dtype, sw.REFLECT, dict(variant=2), scheme=scheme)
     b.step(60)
     b.sync_status()
     for i, st in enumerate(sts):
         st = [a.to(torch.float32).to(torch.float64) if dtype == "f32" else a for a in st]
-        H, U, V, _ = oracle.run(*(a.numpy() for a in st), 60, g=G)
+        H, U, V, _ = oracle.run(*(a.numpy() for a in st), 60, g=G, scheme=scheme)
         err = rel_maxnorm(b.get_state(i), (H[1:-1, 1:-1], U[1:-1, 1:-1], V[1:-1, 1:-1]))
         assert err <= tol, (i, err)
 
@@ -91,13 +93,20 @@ def test_graph_replays_equal_eager():
         assert bg.sync_status() == be.sync_status()
 
 
-def test_tunings_bitwise_identical():
+TUNINGS = {sw.SCHEME_PAPER: (dict(rows=8, vec=1, order=0), dict(rows=16, vec=2, order=1, occupancy=4, prefetch=2),
+                             dict(rows=32, vec=4, order=0, prefetch=3), dict(rows=5, vec=2, order=1, prefetch=1)),
+           sw.SCHEME_TRANSVERSE: (dict(rows=8, vec=1, order=0, prefetch=1), dict(rows=16, vec=2, order=1, prefetch=2),
+                                  dict(rows=32, vec=4, order=0, prefetch=2), dict(rows=5, vec=2, order=1, prefetch=1),
+                                  dict(rows=2, vec=1, order=0, prefetch=2))}
+
+
+@pytest.mark.parametrize("scheme", [sw.SCHEME_PAPER, sw.SCHEME_TRANSVERSE])
+def test_tunings_bitwise_identical(scheme):
     shapes = [(200, 130), (64, 64), (513, 70)]
     sts = states(shapes, 700, False)
     ref = None
-    for tun in (dict(rows=8, vec=1, order=0), dict(rows=16, vec=2, order=1, occupancy=4, prefetch=2),
-                dict(rows=32, vec=4, order=0, prefetch=3), dict(rows=5, vec=2, order=1, prefetch=1)):
-        b = make_batch(shapes, sts, "f32", sw.REFLECT, dict(variant=2, **tun))
+    for tun in TUNINGS[scheme]:
+        b = make_batch(shapes, sts, "f32", sw.REFLECT, dict(variant=2, **tun), scheme=scheme)
         b.step(13)
         out = [[a.numpy() for a in b.get_state(i, halo=True)] for i in range(len(shapes))] + [b.sync_status()]
         if ref is None:

@@ -12,7 +12,7 @@ import torch
 
 import oracle
 from paper_1107_2157_amd import ics, sw
-from swtest import assert_fused_refuses_transverse, G, announce, rel_maxnorm
+from swtest import G, announce, rel_maxnorm
 
 pytestmark = pytest.mark.gpu
 
@@ -29,7 +29,6 @@ def rounded(a, dtype):
 
 def run_both(state, nsteps, dtype, variant, bc_x=sw.REFLECT, bc_y=sw.REFLECT, scheme=sw.SCHEME_PAPER,
              dx=1.0, dy=1.0, cfl=0.5, dt_fixed=0.0):
-    assert not (variant == sw.VARIANT_FUSED and scheme == sw.SCHEME_TRANSVERSE), "unsupported pair"
     h, hu, hv = (rounded(a, dtype) for a in state)
     ny, nx = h.shape
     announce(f"{dtype} variant={variant} {nx}x{ny} steps={nsteps} bc=({bc_x},{bc_y}) scheme={scheme}")
@@ -63,10 +62,7 @@ def test_dam_break_128(variant, dtype):
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_bumps_ragged(variant, dtype, bc, scheme):
     """Gaussian bumps plus moving water on a ragged grid spanning several
-    tiles in both directions."""
-    if variant == sw.VARIANT_FUSED and scheme == sw.SCHEME_TRANSVERSE:
-        assert_fused_refuses_transverse(dtype)
-        return
+    tiles in both directions, both schemes."""
     nx, ny = 301, 203
     h, _, _ = ics.bumps_state(nx, ny, seed=7, periodic=bc == sw.PERIODIC, count=4)
     _, hu, hv = ics.random_state(nx, ny, seed=9, amp_h=0.0, amp_m=0.02)
@@ -79,14 +75,16 @@ def test_bumps_ragged(variant, dtype, bc, scheme):
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("shape", [(1, 1), (1, 37), (37, 1), (2, 3), (63, 5), (64, 64), (65, 130), (257, 9)])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_edge_shapes(variant, shape, dtype):
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_edge_shapes(variant, shape, dtype, scheme):
     """Degenerate and ragged grids (single rows/columns, one cell, exact and
-    off-by-one tile multiples), mixed boundary conditions, random moving
-    state."""
+    off-by-one tile multiples), mixed boundary conditions (the transverse
+    scheme reads the corner ghosts), random moving state."""
     nx, ny = shape
     st = ics.random_state(nx, ny, seed=nx * 1000 + ny, amp_h=0.2, amp_m=0.05)
-    for bc_x, bc_y in ((sw.REFLECT, sw.PERIODIC), (sw.PERIODIC, sw.REFLECT)):
-        got, ref, _, _, _ = run_both(st, 40, dtype, variant, bc_x=bc_x, bc_y=bc_y, dx=1.0, dy=0.7)
+    for bc_x, bc_y in ((sw.REFLECT, sw.PERIODIC), (sw.PERIODIC, sw.REFLECT), (sw.REFLECT, sw.REFLECT),
+                       (sw.PERIODIC, sw.PERIODIC)):
+        got, ref, _, _, _ = run_both(st, 40, dtype, variant, bc_x=bc_x, bc_y=bc_y, dx=1.0, dy=0.7, scheme=scheme)
         assert rel_maxnorm(got, ref) <= TOL[dtype], (shape, bc_x, bc_y)
 
 
