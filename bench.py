@@ -39,7 +39,18 @@ WORKLOADS = {
                             "4096x4096 FP64, reflective walls, 8 Gaussian bumps (seed 2), CFL 0.5"),
     "dam128-f64": (128, "f64", "reflect", None, 100,
                    "128x128 FP64 dam break, reflective walls, CFL 0.5"),
+    "swe4096-f32-reflect-transverse": (4096, "f32", "reflect", 2, 1000,
+                                       "4096x4096 FP32, reflective walls, 8 Gaussian bumps (seed 2), CFL 0.5, "
+                                       "transverse scheme"),
+    "swe4096-f64-reflect-transverse": (4096, "f64", "reflect", 2, 1000,
+                                       "4096x4096 FP64, reflective walls, 8 Gaussian bumps (seed 2), CFL 0.5, "
+                                       "transverse scheme"),
 }
+GOLDEN_4096 = os.path.join(ROOT, "tests", "golden", "swe4096_1000steps.json")
+
+
+def scheme_of(name):
+    return "transverse" if name.endswith("-transverse") else "paper"
 
 
 def source_hash(paths) -> str:
@@ -53,7 +64,8 @@ def source_hash(paths) -> str:
 def make_solver(name, sw, ics, torch):
     n, dtype, bc, seed, _, _ = WORKLOADS[name]
     bcv = sw.PERIODIC if bc == "periodic" else sw.REFLECT
-    s = sw.Solver(n, n, dtype=dtype, bc_x=bcv, bc_y=bcv)
+    scheme = sw.SCHEME_TRANSVERSE if scheme_of(name) == "transverse" else sw.SCHEME_PAPER
+    s = sw.Solver(n, n, dtype=dtype, bc_x=bcv, bc_y=bcv, scheme=scheme)
     if seed is None:
         st = ics.dam_break_state(n, device="cuda")
     else:
@@ -114,12 +126,51 @@ def run_workload(name, steps, warmup, sw, ics, torch, tune_cache, fixed=None):
     elem = 4 if dtype == "f32" else 8
     out = {
         "workload": name, "description": desc, "nx": n, "ny": n, "steps": steps, "dtype": dtype,
-        "seconds": t, "gcells_per_s": cells * steps / t / 1e9, "ms_per_step": 1e3 * t / steps,
-        "kernel_us": per_step * 1e6, "alg_bytes_per_launch": 6 * elem * cells,
+        "scheme": scheme_of(name), "seconds": t, "gcells_per_s": cells * steps / t / 1e9,
+        "ms_per_step": 1e3 * t / steps, "kernel_us": per_step * 1e6, "alg_bytes_per_launch": 6 * elem * cells,
         "tuning": tuning, "finite": finite,
     }
+    vs = versus_oracle_1000(name, s, steps, torch)
+    if vs is not None:
+        out["vs_oracle_1000"] = vs
     del s
     torch.cuda.empty_cache()
+    return out
+
+
+def versus_oracle_1000(name, s, steps, torch):
+    """The GPU state after the timed run (`steps` steps from the initial
+    state) against the CPU oracle's stored 1000-step state of the same
+    4096^2 workload (tests/golden, written by a script that calls only the
+    oracle): reported, not gated.  Differences at a 16 x 16 lattice of cells,
+    relative to the max-norm scales of h and of the momenta, and relative
+    differences of the per-field sums and 2-norms; FP32 runs are compared
+    with the oracle run started from the FP32-rounded state."""
+    import math
+    import numpy as np
+    n, dtype = WORKLOADS[name][0], WORKLOADS[name][1]
+    if n != 4096 or steps != 1000 or not os.path.exists(GOLDEN_4096):
+        return None
+    with open(GOLDEN_4096) as f:
+        gold = json.load(f)
+    run = [r for r in gold["runs"] if r["scheme"] == scheme_of(name) and r["start"] == dtype]
+    if not run:
+        return None
+    run = run[0]
+    lat = gold["lattice"]
+    t_gpu, _, _ = s.sync_status() if run["finite"] else (float("nan"), 0, 0)
+    got = {k: s.interior(i).to("cpu", dtype=torch.float64).numpy() for i, k in enumerate(("h", "hu", "hv"))}
+    sh = run["fields"]["h"]["max_abs"]
+    sm = sh * math.sqrt(9.8 * sh)
+    out = {"scheme": run["scheme"], "oracle_finite": run["finite"], "t_gpu": t_gpu, "t_oracle": run["t"]}
+    for k in ("h", "hu", "hv"):
+        g = got[k]
+        ref = np.array(run["fields"][k]["lattice"])
+        samp = g[np.ix_(lat, lat)]
+        scale = sh if k == "h" else sm
+        out[f"{k}_lattice_rel_max"] = float(np.max(np.abs(samp - ref)) / scale)
+        out[f"{k}_sum_rel"] = float(abs(math.fsum(g.ravel()) - run["fields"][k]["sum"]) / max(abs(run["fields"][k]["sum"]), scale))
+        out[f"{k}_l2_rel"] = float(abs(float(np.sqrt(np.sum(g * g))) - run["fields"][k]["l2"]) / run["fields"][k]["l2"])
     return out
 
 
@@ -223,8 +274,19 @@ def run_comparison(steps, fused_tuning, sw, ics, torch):
 
 # Table 1 of the paper: ms per time step of its generated OpenCL kernel (work-group 16 x 8) on a
 # Tesla C2050, FP32, mean over 100 iterations of the time loop.  Context only (other hardware).
-PAPER_TABLE1_GPU_MS = {16: 0.017, 32: 0.02, 64: 0.02, 128: 0.036, 256: 0.092, 512: 0.32, 1024: 1.22,
-                       1280: 1.89, 2048: 4.82, 4096: 19.29}
+TABLE1 = os.path.join(ROOT, "tests", "golden", "table1_times.csv")
+
+
+def paper_table1_gpu_ms():
+    """width -> the paper's GPU ms per step (Table 1), from the stored copy of the table."""
+    out = {}
+    with open(TABLE1) as f:
+        for line in f:
+            if line.startswith("#") or line.startswith("width"):
+                continue
+            w, _, gpu_ms, _ = line.strip().split(",")
+            out[int(w)] = float(gpu_ms)
+    return out
 
 
 def run_table1(sw, ics, torch, steps=100):
@@ -234,7 +296,7 @@ def run_table1(sw, ics, torch, steps=100):
     paper averaged 100 iterations of its time loop; the fused kernel in its
     default launch shape."""
     rows = []
-    for n, paper_ms in PAPER_TABLE1_GPU_MS.items():
+    for n, paper_ms in paper_table1_gpu_ms().items():
         s = sw.Solver(n, n, dtype="f32")
         st = ics.bumps_state(n, n, seed=ics.SEED_BUMPS_4096, periodic=False, count=8, device="cuda")
         for _ in range(2):                         # graph capture for both buffers, warm
@@ -276,6 +338,11 @@ def run_batch(steps, sw, ics, torch, tune_cache, per_grid_steps):
         finite = False
     del b
     torch.cuda.empty_cache()
+    rate = cells * steps / t / 1e9
+    if per_grid_steps <= 0:
+        return {"workload": "batch512-f32-reflect", "grids": 512, "cells_per_step": cells, "steps": steps,
+                "seconds": t, "gcells_per_s": rate, "ms_per_step": 1e3 * t / steps, "tuning": tuning,
+                "finite": finite, "hbm_frac": rate * 24 / HBM_PEAK_GBS}
     # per-grid launches: every grid its own context and planes, `per_grid_steps` steps
     solvers = []
     for k, n in enumerate(sides):
@@ -360,6 +427,26 @@ def run_surrogate(sw, ics, torch, n=256, size=256, nsteps=64):
             "weights_recipe": meta.get("recipe"), "weights_eval": meta.get("eval")}
 
 
+def surrogate_kernels(sw, ics, torch, n=256, size=256, reps=3):
+    """The surrogate's forward pass and Adam step alone, reps times each, on
+    n seeded bump states (and their states 8 solver steps later)."""
+    from paper_1107_2157_amd import surrogate
+    u0 = surrogate.initial_states(n, size, size, ics.SEED_SURR_EVAL0)
+    b = sw.Batch([(size, size)] * n, dtype="f32")
+    b.load(u0)
+    b.step(8)
+    u8 = b.export()
+    del b
+    net = sw.Surrogate(size, size, n, jump=8, seed=1)
+    t_fwd = [timed(torch, lambda: net.forward(u0)) for _ in range(reps)]
+    t_train = [timed(torch, lambda: net.train_step(u0, u8, 1e-5)) for _ in range(reps)]
+    pixels = n * size * size
+    return {"workload": f"surrogate{size}-b{n}-kernels", "forward_ms": [1e3 * t for t in t_fwd],
+            "train_step_ms": [1e3 * t for t in t_train],
+            "forward_tflops": SUR_FLOP_PER_PIXEL_FWD * pixels / min(t_fwd) / 1e12,
+            "train_tflops": SUR_FLOP_PER_PIXEL_TRAIN * pixels / min(t_train) / 1e12}
+
+
 def copy_bandwidth(torch, nbytes):
     """Device copy of nbytes (read + write) with torch: attainable streaming BW."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -438,6 +525,13 @@ def main():
                     help="run only the fixed-dt comparison (fused single step against temporal blocking)")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="run only the learned-surrogate workload and print its record")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched 512-grid workload and print its record")
+    ap.add_argument("--no-per-grid", action="store_true",
+                    help="with --batch-only: skip the per-grid-launch comparison (for counter profiles)")
+    ap.add_argument("--surrogate-kernels", action="store_true",
+                    help="run only the surrogate's forward pass and training step at 256 grids of 256^2 (three "
+                         "each, for kernel profiles) and print their times")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1107_2157_amd", "tune_cache_gfx950.txt"),
                     help="autotuner cache (launch shapes found by sw_autotune on MI355X; missing keys are tuned "
                          "and appended)")
@@ -465,6 +559,13 @@ def main():
     sw.lib()    # fails loudly if the HIP library is not built
     if args.surrogate_only:
         print(json.dumps(run_surrogate(sw, ics, torch)), flush=True)
+        return
+    if args.surrogate_kernels:
+        print(json.dumps(surrogate_kernels(sw, ics, torch)), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps(run_batch(args.steps or 500, sw, ics, torch, args.tune_cache,
+                                   per_grid_steps=0 if args.no_per_grid else 50)), flush=True)
         return
 
     if args.comparison_only:
@@ -499,10 +600,11 @@ def main():
 
     also = []
     if not args.no_also and args.workload == "swe16384-f32-periodic":
-        for name in ("swe4096-f32-reflect", "swe4096-f64-reflect", "dam128-f64"):
+        for name in ("swe4096-f32-reflect", "swe4096-f64-reflect", "swe4096-f32-reflect-transverse",
+                     "swe4096-f64-reflect-transverse", "dam128-f64"):
             r = run_workload(name, WORKLOADS[name][4], args.warmup, sw, ics, torch, args.tune_cache)
-            also.append({k: r[k] for k in ("workload", "dtype", "steps", "gcells_per_s", "ms_per_step",
-                                            "kernel_us", "finite", "tuning")} |
+            also.append({k: r[k] for k in ("workload", "dtype", "scheme", "steps", "gcells_per_s", "ms_per_step",
+                                            "kernel_us", "finite", "tuning") + (("vs_oracle_1000",) if "vs_oracle_1000" in r else ())} |
                         {"hbm_frac": r["alg_bytes_per_launch"] / (r["kernel_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS})
 
     if not args.no_also and args.workload == "swe16384-f32-periodic":
