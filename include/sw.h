@@ -161,6 +161,28 @@ sw_status sw_diagnostics(sw_ctx *ctx, const sw_state *state, void *stream, doubl
 /* Async.  Zero the simulated time and step counter and clear the sticky flag. */
 sw_status sw_reset_time(sw_ctx *ctx, void *stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  sw_step
+ * without a context: validates (grid, halo, g, dx, opts) as sw_create does,
+ * then advances buf[cur] of `state` by nsteps (>= 0) steps with the fused
+ * kernel in sw_step's default launch shape, launched eagerly on the stream
+ * (no graph), and sets state->cur ^= (nsteps & 1).  The results are bitwise
+ * those of sw_create + sw_step with the default tuning.  The device scalars
+ * of the step sequence (CFL ring, time, step count, sticky flag; 2 KiB,
+ * whatever the grid size) live in a static array of the library, one per
+ * device, held until the process ends; each call clears them first with a
+ * kernel (no memset), so the time and step count cover this call only.
+ * Every call on a device shares that array: calls that overlap on one device
+ * (other streams, other threads) race and give wrong dt and status.
+ * status: device pointer to 4 doubles (8-byte aligned) or NULL; receives
+ * (simulated time, last dt, steps, 1 if a step produced h <= 0 or a
+ * non-finite value else 0) of this call.  Calls no hipMalloc / hipFree.
+ * Errors (synchronous, before any launch): SW_EINVAL (as sw_create and
+ * sw_step, NULL / misaligned / shared planes, nsteps < 0, misaligned status),
+ * SW_ENOTSUP (halo other than [1,1,1,1]; current device index >= 64), SW_EHIP. */
+sw_status sw_step_noalloc(sw_grid grid, sw_halo halo, double g, double dx, const sw_opts *opts, sw_state *state,
+                          int32_t nsteps, double *status, void *stream);
+
 /* Kernel variant used by sw_step: 0 = auto (fastest known), 1 = one thread
  * per cell reading neighbours from global memory (baseline), 2 = fused
  * row-marching kernel (both schemes; the default for both), 3 = temporal blocking: K steps of

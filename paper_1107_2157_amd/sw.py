@@ -140,6 +140,8 @@ SIGNATURES = {
     "sw_surrogate_set_block_cap": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "sw_surrogate_advance": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Gate),
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sw_step_noalloc": (ctypes.c_int, [Grid, Halo, ctypes.c_double, ctypes.c_double, ctypes.POINTER(Opts),
+                                       ctypes.POINTER(State), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "sw_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sw_last_error_detail": (ctypes.c_char_p, []),
 }
@@ -189,6 +191,7 @@ class Solver:
         self.dtype = _DT[dtype]
         self.torch_dtype = _TORCH_DT[self.dtype]
         opts = Opts(self.dtype, bc_x, bc_y, scheme, dy, cfl, dt_fixed)
+        self.opts, self.g, self.dx = opts, g, dx
         ctx = ctypes.c_void_p()
         check(lib().sw_create(Grid(nx, ny), Halo(1, 1, 1, 1), g, dx, ctypes.byref(opts), ctypes.byref(ctx)),
               "sw_create")
@@ -261,6 +264,19 @@ class Solver:
 
     def step(self, nsteps: int, stream=None):
         check(lib().sw_step(self.ctx, ctypes.byref(self.state), nsteps, _stream_handle(stream)), "sw_step")
+
+    def step_noalloc(self, nsteps: int, status: torch.Tensor | None = None, stream=None):
+        """sw_step_noalloc on this solver's planes: default launch shape, eager
+        launches, the library's static per-device scalars instead of the
+        context's.  status: optional float64 device tensor of 4 entries that
+        receives (t, last dt, steps, unstable) of this call."""
+        if status is not None and (not status.is_cuda or status.dtype != torch.float64 or status.numel() < 4
+                                   or not status.is_contiguous()):
+            raise ValueError("status: expected a contiguous float64 device tensor of at least 4 entries")
+        ptr = ctypes.c_void_p(status.data_ptr()) if status is not None else None
+        check(lib().sw_step_noalloc(Grid(self.nx, self.ny), Halo(1, 1, 1, 1), self.g, self.dx,
+                                    ctypes.byref(self.opts), ctypes.byref(self.state), nsteps, ptr,
+                                    _stream_handle(stream)), "sw_step_noalloc")
 
     def sync_status(self, stream=None):
         """(t, last_dt, steps); raises Unstable if the sticky flag is set."""
