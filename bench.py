@@ -370,13 +370,17 @@ SUR_FLOP_PER_PIXEL_TRAIN = SUR_FLOP_PER_PIXEL_FWD * 2 + 2 * 9 * (4 * 32 * 32 + 3
 BF16_PEAK_TFLOPS = 2500.0
 
 
-def run_surrogate(sw, ics, torch, n=256, size=256, nsteps=64):
+def run_surrogate(sw, ics, torch, n=256, size=256, nsteps=64, kernels=True):
     """Surrogate workload: n held-out size x size grids (seeds SEED_SURR_EVAL0 + k,
     1-8 bumps, reflective walls, FP32), advanced nsteps = nsteps / 8 jumps of the
     trained network (committed weights) under the gate (mass drift 1e-4 with
     projection, h > 0, finite), against the plain batched solver (one graph
-    launch) from the same states; plus the judged rollout, the forward pass
-    alone and one training step at batch n."""
+    launch) from the same states.  The rollout is timed in the library's
+    default form (the network as one fused launch or as per-layer launches,
+    whichever the batch size favours) and in both forms; the judged rollout
+    (the solver's state replaces any grid above relative L2(h) 1e-2) is timed
+    too, and its final L2 checked.  With kernels, also the per-layer forward
+    pass alone and one training step at batch n."""
     from paper_1107_2157_amd import surrogate
     name = f"surrogate{size}-b{n}-{nsteps}steps"
     if os.path.exists(surrogate.WEIGHTS_256):
@@ -388,61 +392,86 @@ def run_surrogate(sw, ics, torch, n=256, size=256, nsteps=64):
     gate = dict(mass_rel_tol=1e-4, project_mass=True)
     b = sw.Batch([(size, size)] * n, dtype="f32")
     fbs = torch.zeros(n, dtype=torch.int32, device="cuda")
-    surrogate.rollout(net, u0, nsteps, gate, batch=b, fallbacks=fbs)        # warm: captures the rollout's graph
-    got, fb, t_sur = surrogate.rollout(net, u0, nsteps, gate, batch=b, fallbacks=fbs)
+
+    def best_rollout(g, **kw):
+        surrogate.rollout(net, u0, nsteps, g, batch=b, fallbacks=fbs, **kw)       # warm: captures the graph
+        runs = [surrogate.rollout(net, u0, nsteps, g, batch=b, fallbacks=fbs, **kw) for _ in range(3)]
+        return min(runs, key=lambda r: r[2])
+
+    forms = {}
+    for form, mode in (("fused", 1), ("per_layer", 0), ("default", None)):
+        net.set_fused(surrogate.DEFAULT_FORM if mode is None else mode)
+        got, fb, t_sur = best_rollout(gate)
+        forms[form] = {"seconds": t_sur, "speedup_vs_solver": t_solver / t_sur}
     e, e_strict = surrogate.rel_l2_h(got[:, 0], ref[:, 0])
     p, _ = surrogate.rel_l2_h(u0[:, 0], ref[:, 0])
     l2 = torch.zeros(n, dtype=torch.float64, device="cuda")
     jg = dict(gate, judge=True, l2_tol=1e-2)
-    surrogate.rollout(net, u0, nsteps, jg, l2=l2, batch=b)                  # warm (allocates the solver copy)
-    _, fbj, t_judge = surrogate.rollout(net, u0, nsteps, jg, l2=l2, batch=b)
+    judged, fbj, t_judge = best_rollout(jg, l2=l2)
+    ej, _ = surrogate.rel_l2_h(judged[:, 0], ref[:, 0])
     judged_out = int((l2 > 1e-2).sum())
     del b
-    net.forward(u0)
-    t_fwd = timed(torch, lambda: net.forward(u0))
-    pixels = n * size * size
-    fwd_tflops = SUR_FLOP_PER_PIXEL_FWD * pixels / t_fwd / 1e12
-    # one Adam step on (U^0, U^8) pairs of the same grids, on a separate network
-    bt = sw.Batch([(size, size)] * n, dtype="f32")
-    bt.load(u0)
-    bt.step(8)
-    u8 = bt.export()
-    del bt
-    tnet = sw.Surrogate(size, size, n, jump=8, seed=1)
-    tnet.train_step(u0, u8, 1e-5)
-    t_train = timed(torch, lambda: tnet.train_step(u0, u8, 1e-5))
-    del tnet, net
+    out = {"workload": name, "grids": n, "size": size, "steps": nsteps, "jump": 8,
+           "solver_seconds": t_solver, "rollout_seconds": forms["default"]["seconds"],
+           "speedup_vs_solver": forms["default"]["speedup_vs_solver"], "forms": forms,
+           "rel_l2_h_mean": float(e.mean()), "rel_l2_h_max": float(e.max()),
+           "rel_l2_h_strict_mean": float(e_strict.mean()), "persistence_rel_l2_h_mean": float(p.mean()),
+           "fallback_jumps": int(fb.sum()), "jumps": n * nsteps // 8,
+           "judged": {"seconds": t_judge, "speedup_vs_solver": t_solver / t_judge, "rejected_grids": judged_out,
+                      "rel_l2_h_max": float(ej.max()), "within_1e-2": bool(ej.max() <= 1e-2)},
+           "weights": "untrained" if meta.get("untrained") else "trained",
+           "weights_recipe": meta.get("recipe"), "weights_eval": meta.get("eval")}
+    if kernels:
+        net.forward(u0)
+        t_fwd = timed(torch, lambda: net.forward(u0))
+        pixels = n * size * size
+        fwd_tflops = SUR_FLOP_PER_PIXEL_FWD * pixels / t_fwd / 1e12
+        # one Adam step on (U^0, U^8) pairs of the same grids, on a separate network
+        bt = sw.Batch([(size, size)] * n, dtype="f32")
+        bt.load(u0)
+        bt.step(8)
+        u8 = bt.export()
+        del bt
+        tnet = sw.Surrogate(size, size, n, jump=8, seed=1)
+        tnet.train_step(u0, u8, 1e-5)
+        t_train = timed(torch, lambda: tnet.train_step(u0, u8, 1e-5))
+        del tnet
+        out.update({"forward_ms": 1e3 * t_fwd, "forward_tflops": fwd_tflops,
+                    "forward_frac_bf16_peak": fwd_tflops / BF16_PEAK_TFLOPS, "train_step_ms": 1e3 * t_train,
+                    "train_tflops": SUR_FLOP_PER_PIXEL_TRAIN * pixels / t_train / 1e12})
+    del net
     torch.cuda.empty_cache()
-    return {"workload": name, "grids": n, "size": size, "steps": nsteps, "jump": 8,
-            "solver_seconds": t_solver, "rollout_seconds": t_sur, "speedup_vs_solver": t_solver / t_sur,
-            "rel_l2_h_mean": float(e.mean()), "rel_l2_h_max": float(e.max()),
-            "rel_l2_h_strict_mean": float(e_strict.mean()), "persistence_rel_l2_h_mean": float(p.mean()),
-            "fallback_jumps": int(fb.sum()), "jumps": n * nsteps // 8,
-            "judged_rollout_seconds": t_judge, "judge_rejected_grids": judged_out,
-            "forward_ms": 1e3 * t_fwd, "forward_tflops": fwd_tflops,
-            "forward_frac_bf16_peak": fwd_tflops / BF16_PEAK_TFLOPS,
-            "train_step_ms": 1e3 * t_train,
-            "train_tflops": SUR_FLOP_PER_PIXEL_TRAIN * pixels / t_train / 1e12,
-            "weights": "untrained" if meta.get("untrained") else "trained",
-            "weights_recipe": meta.get("recipe"), "weights_eval": meta.get("eval")}
+    return out
 
 
 def surrogate_kernels(sw, ics, torch, n=256, size=256, reps=3):
-    """The surrogate's forward pass and Adam step alone, reps times each, on
-    n seeded bump states (and their states 8 solver steps later)."""
+    """The surrogate's kernels alone, reps times each, on n seeded bump states
+    (and their states 8 solver steps later): the per-layer forward pass, the
+    Adam step, and one rollout jump with the fused network launch and with
+    the per-layer kernels (eager launches, gate wide open, so that every
+    jump is the network's)."""
     from paper_1107_2157_amd import surrogate
-    u0 = surrogate.initial_states(n, size, size, ics.SEED_SURR_EVAL0)
+    # inputs built on the host and copied in: the process launches only the
+    # library's kernels (and the runtime's copies), which keeps it profilable
+    u0 = surrogate.initial_states(n, size, size, ics.SEED_SURR_EVAL0, device="cpu").cuda()
     b = sw.Batch([(size, size)] * n, dtype="f32")
     b.load(u0)
     b.step(8)
     u8 = b.export()
-    del b
     net = sw.Surrogate(size, size, n, jump=8, seed=1)
     t_fwd = [timed(torch, lambda: net.forward(u0)) for _ in range(reps)]
     t_train = [timed(torch, lambda: net.train_step(u0, u8, 1e-5)) for _ in range(reps)]
+    net.set_graph(False)
+    jumps = {}
+    for fused in (True, False):
+        net.set_fused(fused)
+        b.load(u0)
+        ts = [timed(torch, lambda: net.advance(b, 8, mass_rel_tol=10.0, hmin=-1e30)) for _ in range(reps)]
+        jumps["fused" if fused else "per_layer"] = [1e3 * t for t in ts]
+    del b
     pixels = n * size * size
     return {"workload": f"surrogate{size}-b{n}-kernels", "forward_ms": [1e3 * t for t in t_fwd],
-            "train_step_ms": [1e3 * t for t in t_train],
+            "train_step_ms": [1e3 * t for t in t_train], "rollout_jump_ms": jumps,
             "forward_tflops": SUR_FLOP_PER_PIXEL_FWD * pixels / min(t_fwd) / 1e12,
             "train_tflops": SUR_FLOP_PER_PIXEL_TRAIN * pixels / min(t_train) / 1e12}
 
@@ -621,7 +650,8 @@ def main():
 
     if not args.no_also and not args.no_surrogate and args.workload == "swe16384-f32-periodic":
         also.append(run_surrogate(sw, ics, torch))
-        also.append(run_surrogate(sw, ics, torch, n=1))      # batch 1: the launch-bound end
+        also.append(run_surrogate(sw, ics, torch, n=16, kernels=False))
+        also.append(run_surrogate(sw, ics, torch, n=1, kernels=False))      # batch 1: the launch-bound end
 
     line = {
         "metric": METRIC,

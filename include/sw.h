@@ -297,8 +297,10 @@ sw_status sw_batch_reset_time(sw_batch *batch, void *stream);
 sw_status sw_batch_export(sw_batch *batch, void *dense, void *stream);
 sw_status sw_batch_import(sw_batch *batch, const void *dense, void *stream);
 /* Launch shape for every grid (variant must be 0 or 2; order: 0 = LPT
- * tile table, largest grids first; 1 = round-robin over grids).  Every
- * shape gives bitwise the same states. */
+ * tile table, largest grids first, one wave per tile; 1 = round-robin over
+ * grids, one wave per tile; 2 = the LPT table walked by persistent waves,
+ * only the workgroups the device holds at once, each wave taking a
+ * contiguous run of tiles).  Every shape gives bitwise the same states. */
 sw_status sw_batch_set_tuning(sw_batch *batch, const sw_tuning *tuning);
 sw_status sw_batch_get_tuning(const sw_batch *batch, sw_tuning *out);
 /* 1 (default): one hipGraph launch per sw_batch_step call; 0: eager launches. */
@@ -408,6 +410,21 @@ sw_status sw_surrogate_set_graph(sw_net *net, int32_t enable);
  * partials (summed in FP64) split differently.  Drops captured rollouts.
  * Errors: SW_EINVAL for a NULL network or a cap outside [0, 1024]. */
 sw_status sw_surrogate_set_block_cap(sw_net *net, int32_t max_blocks);
+
+/* Form of the rollout's network pass.  1: one launch runs all six layers
+ * per output tile with the activations on chip (the state with a 6-pixel
+ * border in, the prediction out), and the gate's verdict and the rejected
+ * grids' solver steps share one launch: three launches per jump.  0: one
+ * launch per layer through activation tensors in device memory, then
+ * separate gate and fallback launches.  2 (default): 1 while the batch has
+ * at most 16 output tiles of 16 x 32 pixels per compute unit, else 0 (the
+ * fused form recomputes each tile's border and wins where launches and HBM
+ * traffic dominate, i.e. at small batches).  The predictions are bitwise
+ * equal; with project_mass the mean of the predicted dh is summed in a
+ * different fixed order (per tile instead of per row segment), so h may
+ * differ in the last bits.  Drops captured rollouts.
+ * Errors: SW_EINVAL for a NULL network or a mode outside 0..2. */
+sw_status sw_surrogate_set_fused(sw_net *net, int32_t mode);
 
 const char *sw_strerror(sw_status status);
 const char *sw_last_error_detail(void);

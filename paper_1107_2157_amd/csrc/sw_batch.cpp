@@ -82,7 +82,9 @@ sw_status resolve(const sw_batch *b, const sw_tuning &t, Resolved *r) {
     r->pd = t.prefetch ? t.prefetch : 2;
     r->order = t.order;
     if (t.rows < 0) return sw_fail(SW_EINVAL, "batch tuning: rows = %d", t.rows);
-    if (r->order < 0 || r->order > 1) return sw_fail(SW_EINVAL, "batch tuning: order %d (0 LPT, 1 round-robin)", r->order);
+    if (r->order < 0 || r->order > 2)
+        return sw_fail(SW_EINVAL, "batch tuning: order %d (0 LPT, 1 round-robin, 2 LPT walked by persistent waves)",
+                       r->order);
     if (!sw_fused_supported((int)b->opts.dtype, (int)b->opts.scheme, r->vec, r->minw, r->pd))
         return sw_fail(SW_EINVAL, "batch tuning: vec %d / occupancy %d / prefetch %d not available", r->vec, r->minw,
                        r->pd);
@@ -98,8 +100,9 @@ void drop_graphs(sw_batch *b) {
     b->graphs.clear();
 }
 
-// Tile table: order 0 = LPT (grids by cell count, largest first, each grid's
-// tiles row-block-major); order 1 = round-robin over the grids.
+// Tile table: order 0 and 2 = LPT (grids by cell count, largest first, each
+// grid's tiles row-block-major; order 2 launches persistent waves over it);
+// order 1 = round-robin over the grids.
 sw_status build_tiles(sw_batch *b, const Resolved &r) {
     if (b->table_rows == r.rows && b->table_vec == r.vec && b->table_order == r.order && b->d_tiles) return SW_OK;
     const int W = 64 * r.vec;
@@ -119,7 +122,7 @@ sw_status build_tiles(sw_batch *b, const Resolved &r) {
     if (total > 0x3fffffff) return sw_fail(SW_EINVAL, "batch: %zu tiles", total);
     std::vector<SwBatchTile> tiles;
     tiles.reserve(total);
-    if (r.order == 0) {
+    if (r.order != 1) {
         for (int gi : idx) tiles.insert(tiles.end(), per[gi].begin(), per[gi].end());
     } else {
         std::vector<size_t> pos(b->n, 0);
@@ -175,7 +178,7 @@ sw_status enqueue(const sw_batch *b, const Resolved &r, int nsteps, int cur, hip
     for (int k = 0; k < nsteps; ++k) {
         SwBatchLaunch a = launch_of(b, r, cur, k);
         a.active = active;
-        BHIP(sw_batch_launch_step(a, r.vec, r.minw, r.pd, s));
+        BHIP(sw_batch_launch_step(a, r.vec, r.minw, r.pd, r.order == 2, s));
         cur ^= 1;
     }
     return SW_OK;
@@ -230,6 +233,18 @@ int sw_batch_internal_fallback(sw_batch *b, int nsteps, const int32_t *active, h
     SwBatchLaunch a = launch_of(b, r, b->cur, 0);
     a.active = active;
     BHIP(sw_batch_launch_fallback(a, b->n, nsteps, s));
+    return SW_OK;
+}
+
+int sw_batch_internal_gated_fallback(sw_batch *b, int nsteps, const SwFallbackGate &gate, hipStream_t s) {
+    sw_status st = check_bound(b);
+    if (st != SW_OK) return st;
+    if (nsteps < 2 || (nsteps & 1)) return sw_fail(SW_EINVAL, "batch: masked steps must be even and > 0 (%d)", nsteps);
+    if (!gate.stats || b->opts.dtype != SW_F32) return sw_fail(SW_EINVAL, "batch: the fallback runs FP32 batches");
+    Resolved r;
+    if ((st = resolve(b, b->tuning, &r)) != SW_OK) return st;
+    SwBatchLaunch a = launch_of(b, r, b->cur, 0);
+    BHIP(sw_batch_launch_gated_fallback(a, gate, b->n, nsteps, s));
     return SW_OK;
 }
 
@@ -514,7 +529,7 @@ sw_status sw_batch_autotune(sw_batch *b, int32_t steps_per_trial, const char *ca
     if (st != SW_OK) return st;
     if (steps_per_trial < 1) return sw_fail(SW_EINVAL, "batch_autotune: steps_per_trial = %d", steps_per_trial);
     hipStream_t s = (hipStream_t)stream;
-    // cache key: arch, CUs, dtype, number of grids and total cells
+    // cache key: arch, CUs, dtype, scheme, number of grids and total cells
     std::string key;
     {
         hipDeviceProp_t prop;
@@ -528,7 +543,8 @@ sw_status sw_batch_autotune(sw_batch *b, int32_t steps_per_trial, const char *ca
         int64_t cells = 0;
         for (auto &g : b->grids) cells += (int64_t)g.nx * g.ny;
         std::ostringstream k;
-        k << arch << ":" << cus << ":" << (b->opts.dtype == SW_F64 ? "f64" : "f32") << ":batch" << b->n << ":" << cells;
+        k << arch << ":" << cus << ":" << (b->opts.dtype == SW_F64 ? "f64" : "f32") << ":" << (int)b->opts.scheme
+          << ":batch" << b->n << ":" << cells;
         key = k.str();
     }
     if (cache_path && *cache_path) {
@@ -559,7 +575,7 @@ sw_status sw_batch_autotune(sw_batch *b, int32_t steps_per_trial, const char *ca
             for (int pd = 1; pd <= 3; ++pd)
                 if (sw_fused_supported((int)b->opts.dtype, (int)b->opts.scheme, vecs[vi], occ, pd))
                     for (int rows : {2, 4, 8, 16, 32})
-                        for (int order = 0; order <= 1; ++order) cands.push_back(sw_tuning{2, rows, vecs[vi], occ, pd, order});
+                        for (int order = 0; order <= 2; ++order) cands.push_back(sw_tuning{2, rows, vecs[vi], occ, pd, order});
     const bool graph0 = b->use_graph;
     const sw_tuning prev = b->tuning;
     const int cur0 = b->cur;

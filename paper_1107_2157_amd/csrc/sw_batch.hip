@@ -5,6 +5,8 @@
 // kernel (sw_tile.h), so a grid advanced in a batch is bitwise identical to
 // the same grid advanced alone.  Each grid keeps its own CFL ring slots,
 // time and sticky flag.
+#include <algorithm>
+
 #include "sw_batch_internal.h"
 #include "sw_tile_tr.h"
 
@@ -86,6 +88,70 @@ __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_batch_step(SwBat
     }
 }
 
+// Persistent form of the step: only resident workgroups are launched and
+// each wave walks a contiguous run of the tile table (tiles_per_wave
+// entries; the runs of one XCD's waves are contiguous, so a grid's
+// neighbouring tiles meet in that XCD's L2).  The next tile's table entry is
+// loaded while the current tile runs, the grid's dt is kept while the run
+// stays on one grid, and the signal-speed max of consecutive tiles of one
+// grid is flushed once per grid.  Every cell, dt and book entry is the one
+// k_batch_step computes.
+template <typename T, int VEC, int MINW, int PD, bool TR>
+__global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_batch_step_pers(SwBatchLaunch a, int tiles_per_wave) {
+    const int w = batch_tile_index();            // this wave's position among all waves, XCD-aware
+    const int t0 = w * tiles_per_wave;
+    const int t1 = min(a.ntiles, t0 + tiles_per_wave);
+    if (t0 >= t1) return;                         // whole wave leaves: no barriers are used
+    SwBatchTile nxt = a.tiles[t0];
+    int cur_grid = -1;
+    double dt_grid = 0.0;
+    T smax = T(0);
+    bool bad = false;
+    for (int t = t0; t < t1; ++t) {
+        const SwBatchTile tt = nxt;
+        if (t + 1 < t1) nxt = a.tiles[t + 1];     // in flight during this tile
+        if (tt.grid != cur_grid) {                 // a new grid: flush the previous one's max, take this one's dt
+            if (cur_grid >= 0) batch_reduce(a, cur_grid, (a.step + 1) % 3, w, (double)smax, bad);
+            smax = T(0);
+            bad = false;
+            cur_grid = tt.grid;
+            dt_grid = batch_dt_finish(a, batch_dt_stripe(a, cur_grid));
+        }
+        if (a.active && !a.active[tt.grid]) continue;
+        const SwBatchGrid &gd = a.grids[tt.grid];
+        TileArgs ta;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            ta.in[k] = gd.plane[a.cur][k];
+            ta.out[k] = const_cast<void *>(gd.plane[a.cur ^ 1][k]);
+        }
+        ta.pitch = gd.pitch;
+        ta.nx = gd.nx;
+        ta.ny = gd.ny;
+        ta.bc_x = a.bc_x;
+        ta.bc_y = a.bc_y;
+        ta.s = tt.s;
+        ta.rb = tt.rb;
+        ta.rows = a.rows;
+        double dt = 0.0;
+        const double dtg = dt_grid;
+        if constexpr (TR)
+            fused_tile_tr<T, VEC, PD>(ta, [&] { return dtg; }, a.g, a.dx, a.dy, smax, bad, dt);
+        else
+            fused_tile<T, VEC, PD>(ta, [&] { return dtg; }, a.g, a.dx, a.dy, smax, bad, dt);
+        if (tt.s == 0 && tt.rb == 0) {           // the grid's first tile keeps its books
+            const int lane = threadIdx.x & 63;
+            if (lane < kBatchStripes) atomicExch(&a.sc[tt.grid].smax[(a.step + 2) % 3][lane], 0ull);
+            if (lane == 0) {
+                a.sc[tt.grid].t += dt;
+                a.sc[tt.grid].last_dt = dt;
+                a.sc[tt.grid].steps += 1;
+            }
+        }
+    }
+    if (cur_grid >= 0) batch_reduce(a, cur_grid, (a.step + 1) % 3, w, (double)smax, bad);
+}
+
 // Once per call: ghosts of U^cur for every grid and the max signal speed
 // into ring slot 0.  One wave per tile, lanes across the tile's columns.
 template <typename T>
@@ -129,11 +195,38 @@ __global__ __launch_bounds__(256) void k_batch_prologue(SwBatchLaunch a, int til
 // it, with the same time and step count.
 constexpr int kFbWaves = 8;
 
-template <typename T, int VEC, int PD, bool TR>
-__global__ __launch_bounds__(64 * kFbWaves) void k_batch_fallback(SwBatchLaunch a, int nsteps) {
+// GATED: the surrogate gate's verdict is taken here instead of from a mask:
+// from the jump's statistics (the same rule and expression as the
+// gate-and-restore pass), recorded by thread 0; a rejected grid first copies
+// U^n from buffer cur ^ 1 over the prediction in buffer cur (the whole halo'd
+// rectangle) and makes the copy visible to the workgroup as above.
+template <typename T, int VEC, int PD, bool TR, bool GATED>
+__global__ __launch_bounds__(64 * kFbWaves) void k_batch_fallback(SwBatchLaunch a, SwFallbackGate gate, int nsteps) {
     const int gi = blockIdx.x;
-    if (!a.active[gi]) return;                  // uniform: the whole workgroup leaves
     const SwBatchGrid &gd = a.grids[gi];
+    if constexpr (GATED) {
+        const SwGateStats &sg = gate.stats[gi];
+        const double drift = fabs(sg.mass_new - sg.mass_old) / fabs(sg.mass_old);
+        const int reject = !(drift <= gate.mass_tol) || !((double)sg.hmin > gate.hmin) || sg.nonfinite != 0u;
+        __syncthreads();                        // every thread has read the statistics before thread 0 writes
+        if (threadIdx.x == 0) {
+            gate.stats[gi].fallback = reject;
+            if (gate.fallbacks) gate.fallbacks[gi] += reject;
+        }
+        if (!reject) return;                    // uniform: the whole workgroup leaves
+        const int64_t n = (int64_t)(gd.ny + 2) * (gd.nx + 2);
+        for (int64_t p = threadIdx.x; p < n; p += blockDim.x) {
+            const int yy = (int)(p / (gd.nx + 2)), xx = (int)(p - (int64_t)yy * (gd.nx + 2));
+            const int64_t off = (int64_t)(yy - 1) * gd.pitch + (xx - 1);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) ((T *)gd.plane[a.cur][k])[off] = ((const T *)gd.plane[a.cur ^ 1][k])[off];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    } else {
+        if (!a.active[gi]) return;              // uniform: the whole workgroup leaves
+    }
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     __shared__ double s_max[kFbWaves];
@@ -258,8 +351,27 @@ unsigned batch_blocks(int ntiles) {
 }
 
 template <typename T, int VEC, int MINW, int PD, bool TR>
-hipError_t launch_batch_t(const SwBatchLaunch &a, hipStream_t s) {
-    k_batch_step<T, VEC, MINW, PD, TR><<<batch_blocks(a.ntiles), 256, 0, s>>>(a);
+hipError_t launch_batch_t(const SwBatchLaunch &a, int persistent, hipStream_t s) {
+    if (!persistent) {
+        k_batch_step<T, VEC, MINW, PD, TR><<<batch_blocks(a.ntiles), 256, 0, s>>>(a);
+        return hipGetLastError();
+    }
+    static const int resident = [] {   // workgroups of this instance that fit on one CU at once
+        int r = 0;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, k_batch_step_pers<T, VEC, MINW, PD, TR>, 256, 0) ==
+                               hipSuccess &&
+                       r > 0
+                   ? r
+                   : 1;
+    }();
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int64_t blocks = (int64_t)cus * resident;
+    blocks = std::min<int64_t>(blocks, ((int64_t)a.ntiles + 3) / 4);
+    blocks = (blocks + 7) / 8 * 8;
+    const int64_t waves = blocks * 4;
+    const int per_wave = (int)((a.ntiles + waves - 1) / waves);
+    k_batch_step_pers<T, VEC, MINW, PD, TR><<<(unsigned)blocks, 256, 0, s>>>(a, per_wave);
     return hipGetLastError();
 }
 
@@ -295,19 +407,29 @@ hipError_t sw_batch_launch_prologue(const SwBatchLaunch &a, int vec, hipStream_t
 hipError_t sw_batch_launch_fallback(const SwBatchLaunch &a, int ngrids, int nsteps, hipStream_t s) {
     if (ngrids <= 0 || nsteps <= 0) return hipSuccess;
     if (a.dtype != 0 || !a.active || a.rows < 1) return hipErrorInvalidValue;
-    if (a.scheme == 0) k_batch_fallback<float, 2, 1, false><<<ngrids, 64 * kFbWaves, 0, s>>>(a, nsteps);
-    else k_batch_fallback<float, 2, 1, true><<<ngrids, 64 * kFbWaves, 0, s>>>(a, nsteps);
+    const SwFallbackGate none{};
+    if (a.scheme == 0) k_batch_fallback<float, 2, 1, false, false><<<ngrids, 64 * kFbWaves, 0, s>>>(a, none, nsteps);
+    else k_batch_fallback<float, 2, 1, true, false><<<ngrids, 64 * kFbWaves, 0, s>>>(a, none, nsteps);
     return hipGetLastError();
 }
 
-hipError_t sw_batch_launch_step(const SwBatchLaunch &a, int vec, int minw, int pd, hipStream_t s) {
+hipError_t sw_batch_launch_gated_fallback(const SwBatchLaunch &a, const SwFallbackGate &gate, int ngrids, int nsteps,
+                                          hipStream_t s) {
+    if (ngrids <= 0) return hipSuccess;
+    if (a.dtype != 0 || !gate.stats || a.rows < 1 || nsteps <= 0) return hipErrorInvalidValue;
+    if (a.scheme == 0) k_batch_fallback<float, 2, 1, false, true><<<ngrids, 64 * kFbWaves, 0, s>>>(a, gate, nsteps);
+    else k_batch_fallback<float, 2, 1, true, true><<<ngrids, 64 * kFbWaves, 0, s>>>(a, gate, nsteps);
+    return hipGetLastError();
+}
+
+hipError_t sw_batch_launch_step(const SwBatchLaunch &a, int vec, int minw, int pd, int persistent, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
 #define SW_BATCH_CASE(T, V, M, P) \
     if ((a.dtype == 1) == (sizeof(T) == 8) && vec == V && minw == M && pd == P) \
-        return launch_batch_t<T, V, M, P, false>(a, s);
+        return launch_batch_t<T, V, M, P, false>(a, persistent, s);
 #define SW_BATCH_TR_CASE(T, V, M, P) \
     if ((a.dtype == 1) == (sizeof(T) == 8) && vec == V && minw == M && pd == P) \
-        return launch_batch_t<T, V, M, P, true>(a, s);
+        return launch_batch_t<T, V, M, P, true>(a, persistent, s);
     if (a.scheme == 0) {
         SW_FUSED_SHAPES(SW_BATCH_CASE)
     } else if (a.scheme == 1) {

@@ -45,16 +45,42 @@ struct SwBatchLaunch {
     const int32_t *active;   // optional per-grid mask: grids with 0 are skipped entirely
 };
 
+// Gate statistics of a surrogate jump, per grid: mass before and after, the
+// least depth, whether any value is non-finite, and the verdict.
+struct SwGateStats {
+    double mass_old, mass_new;
+    float hmin;
+    unsigned int nonfinite;
+    int fallback;
+    int pad;
+};
+// The gate's rule: reject a jump on mass drift above mass_tol, a depth at or
+// below hmin, or a non-finite value.
+struct SwFallbackGate {
+    SwGateStats *stats;
+    double mass_tol, hmin;
+    int32_t *fallbacks;   // per-grid count of rejected jumps (may be null)
+};
+
 hipError_t sw_batch_launch_reset(SwBatchScalars *sc, int n, int clear_time, hipStream_t s);
 hipError_t sw_batch_launch_prologue(const SwBatchLaunch &a, int vec, hipStream_t s);
-// persistent: resident blocks only, each wave looping over tiles of its
-// XCD's run of the table (same cells, dt and bookkeeping).
-hipError_t sw_batch_launch_step(const SwBatchLaunch &a, int vec, int minw, int pd, hipStream_t s);
+// persistent = 0: one wave per tile of the table.  persistent = 1: resident
+// workgroups only, each wave walking a contiguous run of the table (runs of
+// one XCD contiguous); the same cells, dt and bookkeeping.
+hipError_t sw_batch_launch_step(const SwBatchLaunch &a, int vec, int minw, int pd, int persistent, hipStream_t s);
 // FP32 only: prologue and nsteps steps of every grid g < ngrids with
 // a.active[g] != 0, one workgroup per grid, one launch (the other grids
 // return at once).  Bitwise the same as reset-free prologue + nsteps step
 // launches of those grids.
 hipError_t sw_batch_launch_fallback(const SwBatchLaunch &a, int ngrids, int nsteps, hipStream_t s);
+// The same with the gate folded in: each grid's workgroup takes the verdict
+// from the jump's statistics (recording it in stats[g].fallback and
+// fallbacks[g]); an accepted grid returns at once, a rejected one copies
+// U^n (buffer cur ^ 1, halos included) over the prediction in buffer cur and
+// takes its nsteps steps from there.  Bitwise the gate-and-restore pass
+// followed by sw_batch_launch_fallback with the verdicts as the mask.
+hipError_t sw_batch_launch_gated_fallback(const SwBatchLaunch &a, const SwFallbackGate &gate, int ngrids, int nsteps,
+                                          hipStream_t s);
 hipError_t sw_batch_launch_copy(const SwBatchGrid *grids, int cur, int n, int nx, int ny, int dtype, void *dense,
                                 int to_dense, hipStream_t s);
 
@@ -76,6 +102,9 @@ int sw_batch_internal_prepare(sw_batch *b);
 // grids are left alone.  FP32 batches.  Does not flip the batch's current
 // buffer (nsteps must be even).
 int sw_batch_internal_fallback(sw_batch *b, int nsteps, const int32_t *active, hipStream_t s);
+// The gated form (sw_batch_launch_gated_fallback) on the batch's current
+// buffer, which holds the prediction; U^n is in the other one.
+int sw_batch_internal_gated_fallback(sw_batch *b, int nsteps, const SwFallbackGate &gate, hipStream_t s);
 // A batch with the same grids, options and tuning as src, bound to an arena
 // it allocates (*arena; the caller frees it after sw_batch_destroy).
 int sw_batch_internal_clone(const sw_batch *src, sw_batch **out, void **arena);

@@ -11,7 +11,6 @@ enum { SW_CONV_RELU_BF16 = 0, SW_CONV_RESID_BF16 = 1, SW_CONV_F32 = 2, SW_CONV_D
 struct SwNorm {
     float in_off[3], in_scale[3], out_scale[3];
 };
-struct SwGateStats;
 
 // One 3x3 convolution launch (see sw_conv.hip for layouts).  Modes:
 //   RELU:  y = relu(conv(x) + b)                                (first layer)
@@ -43,6 +42,27 @@ struct SwConvArgs {
     double *dh_part;            // F32: per-row sums of channel 0 (may be null)
 };
 hipError_t sw_conv3x3(const SwConvArgs &a, int cin, int cout, int mode, hipStream_t s);
+
+// The rollout's whole network in one launch (sw_netfused.hip): from the
+// batch's FP32 planes (buffer cur, ghosts materialised) to the FP32
+// prediction [B][H][W][4], bitwise the per-layer forward pass, plus each
+// output tile's sum of the predicted dh (FP64, fixed order) at
+// dh_tile[b * tiles_per_grid + tile] (tiles row-major; sw_net_fused_tile
+// gives the tile shape).  W a multiple of 64.
+struct SwNetFusedArgs {
+    const SwBatchGrid *grids;
+    int cur;
+    int B, H, W;
+    SwNorm nrm;
+    const void *wk[6];          // forward weight layouts of the six layers
+    const float *bias[6];       // FP32 biases
+    float *delta;               // [B][H][W][4]
+    double *dh_tile;            // may be null
+    SwGateStats *clear_stats;   // the jump's gate statistics, cleared per grid (may be null)
+    int max_blocks;             // cap on the persistent grid (0: one workgroup per CU)
+};
+hipError_t sw_net_fused(const SwNetFusedArgs &a, hipStream_t s);
+void sw_net_fused_tile(int B, int H, int W, int *th, int *tw);
 // Compute units of the current device (for persistent grids).
 int sw_device_cus();
 
@@ -82,18 +102,14 @@ hipError_t sw_sur_relayout(const float *master, const SwLayerDesc *layers, int n
 
 // Rollout: per grid, sum of predicted dh (for the mass projection), the
 // update U' = U + denorm(delta) (- mean dh if projecting) written into the
-// other buffer, and the gate's mass / min-h / finiteness statistics.
-struct SwGateStats {
-    double mass_old, mass_new;
-    float hmin;
-    unsigned int nonfinite;
-    int fallback;
-    int pad;
-};
-// dh_part: the output layer's per-row sums of the normalised dh (B * H
-// doubles), summed per grid in a fixed order for the mass projection.
-hipError_t sw_sur_apply(const float *delta, const double *dh_part, const SwBatchGrid *grids, int cur, int B, int H,
-                        int W, SwNorm nrm, int project, int bcx, int bcy, SwGateStats *st, hipStream_t s);
+// other buffer, and the gate's mass / min-h / finiteness statistics
+// (SwGateStats, sw_batch_internal.h).
+// dh_part: partial sums of the normalised dh, nparts per grid ([B][nparts]:
+// the per-layer output layer's per-row-segment sums, or the fused network's
+// per-tile sums), summed per grid in a fixed order for the mass projection.
+hipError_t sw_sur_apply(const float *delta, const double *dh_part, int nparts, const SwBatchGrid *grids, int cur,
+                        int B, int H, int W, SwNorm nrm, int project, int bcx, int bcy, SwGateStats *st,
+                        hipStream_t s);
 // The gate's verdict per grid (active[b] = 1 and fallbacks[b] += 1 for a
 // rejected jump); rejected grids get U^n (buffer cur, halos included) copied
 // over the prediction in buffer cur ^ 1, where the solver then takes the jump.

@@ -30,6 +30,15 @@ template <int CIN> constexpr int ksteps() { return CIN == 32 ? 9 : 3; }
 constexpr int kTileCols = 64;               // output pixels per tile row (4 MFMA N blocks)
 constexpr int kStageCols = kTileCols + 2;   // staged pixels per row (halo)
 
+// Offset (BF16 elements) of 16-byte chunk c (channels 8c .. 8c + 7) of pixel
+// p in an LDS area of 32-channel pixels.  The chunk index is XORed with bits
+// 1-2 of the pixel index.  A ds_read_b128 is served 8 lanes (128 bytes, 32
+// banks) at a time, and 8 lanes of an MFMA operand read the same chunk of 8
+// consecutive pixels: at a plain 64-byte pixel stride those fall on 2 of the
+// 8 bank quads, a 4-way conflict (measured: about 70 % of the convolutions'
+// LDS cycles were bank-conflict cycles); swizzled they cover all 8.
+__device__ __forceinline__ int chunk_off(int p, int c) { return p * 32 + ((c ^ ((p >> 1) & 3)) << 3); }
+
 // Persistent, LDS-staged 3x3 convolution.  Each block owns a contiguous run
 // of ROWS-row x 64-pixel output tiles (ROWS = waves per block) (contiguous, so neighbouring tiles share
 // halo rows in the same XCD's L2) and keeps the layer's weights (the MFMA A
@@ -101,11 +110,12 @@ __global__ __launch_bounds__(64 * ROWS) void k_conv3x3(SwConvArgs a, int tiles_y
             }
         }
     };
-    auto store_tile = [&](int buf) {
+    auto store_tile = [&](int buf) {   // chunk c: pixel c / 4, chunk c % 4 (CIN = 32, swizzled) or pixel c (CIN = 8)
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int c = threadIdx.x + k * NT;
-            if (c < CHUNKS) *reinterpret_cast<bf16x8 *>(&tile[buf][c * 8]) = stg[k];
+            if (c < CHUNKS)
+                *reinterpret_cast<bf16x8 *>(&tile[buf][CIN == 32 ? chunk_off(c >> 2, c & 3) : c * 8]) = stg[k];
         }
     };
 
@@ -144,7 +154,8 @@ __global__ __launch_bounds__(64 * ROWS) void k_conv3x3(SwConvArgs a, int tiles_y
             const int dy = live ? tap / 3 : 1, dx = live ? tap % 3 : 1;
 #pragma unroll
             for (int pb = 0; pb < NPB; ++pb) {
-                bf16x8 xb = *reinterpret_cast<const bf16x8 *>(T + ((w + dy) * kStageCols + pb * 16 + n + dx) * CIN + ci0);
+                const int px = (w + dy) * kStageCols + pb * 16 + n + dx;
+                bf16x8 xb = *reinterpret_cast<const bf16x8 *>(T + (CIN == 32 ? chunk_off(px, g) : px * CIN + ci0));
                 if (!live) xb = bf16x8{};
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb)
@@ -176,8 +187,9 @@ __global__ __launch_bounds__(64 * ROWS) void k_conv3x3(SwConvArgs a, int tiles_y
                 // NHWC row: values go to the wave's LDS area, then out as 16 contiguous bytes
                 // per lane.  Two outputs (RESID's ReLU part, DGRAD's dZ) reuse the area in turn.
                 const int64_t row0 = (((int64_t)b * (a.H + 2) + y + 1) * Wp + x0 + 1) * COUT;
+                // the area holds the wave's 64 pixels x 32 channels, chunks swizzled as the input tile's
                 auto slot = [&](int mb, int pb) -> bf16x4 & {
-                    return *reinterpret_cast<bf16x4 *>(&ostage[w][(pb * 16 + n) * COUT + mb * 16 + 4 * g]);
+                    return *reinterpret_cast<bf16x4 *>(&ostage[w][chunk_off(pb * 16 + n, 2 * mb + (g >> 1)) + 4 * (g & 1)]);
                 };
                 auto wave_sync = [] {
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -187,9 +199,12 @@ __global__ __launch_bounds__(64 * ROWS) void k_conv3x3(SwConvArgs a, int tiles_y
                 auto flush = [&](__bf16 *dst) {
                     wave_sync();
 #pragma unroll
-                    for (int k = 0; k < kTileCols * COUT / 512; ++k)   // non-temporal: GB-sized tensors
-                        __builtin_nontemporal_store(*reinterpret_cast<const bf16x8 *>(&ostage[w][k * 512 + lane * 8]),
-                                                    reinterpret_cast<bf16x8 *>(dst + row0 + k * 512 + lane * 8));
+                    for (int k = 0; k < kTileCols * COUT / 512; ++k) {   // non-temporal: GB-sized tensors
+                        const int e = k * 512 + lane * 8;                 // chunk (e / 8) % 4 of pixel e / 32
+                        __builtin_nontemporal_store(
+                            *reinterpret_cast<const bf16x8 *>(&ostage[w][chunk_off(e >> 5, (e >> 3) & 3)]),
+                            reinterpret_cast<bf16x8 *>(dst + row0 + e));
+                    }
                     wave_sync();   // the copy's reads are done before the area is written again
                 };
                 auto relu_part = [&](int mb, int pb) {
@@ -206,7 +221,7 @@ __global__ __launch_bounds__(64 * ROWS) void k_conv3x3(SwConvArgs a, int tiles_y
                             f32x4 v = relu_part(mb, pb);
                             if (MODE == SW_CONV_RESID_BF16) {   // CIN == COUT: the block's input at this pixel, from LDS
                                 const bf16x4 xin = *reinterpret_cast<const bf16x4 *>(
-                                    T + ((w + 1) * kStageCols + pb * 16 + n + 1) * CIN + mb * 16 + 4 * g);
+                                    T + chunk_off((w + 1) * kStageCols + pb * 16 + n + 1, 2 * mb + (g >> 1)) + 4 * (g & 1));
 #pragma unroll
                                 for (int q = 0; q < 4; ++q) v[q] += (float)xin[q];
                             }

@@ -336,16 +336,15 @@ __global__ void k_relayout(const float *master, const SwLayerDesc *layers, int n
 // The mean dh comes from the output layer's per-row sums, added by every
 // block in the same fixed order (so every block, and every run, gets the
 // same value).
-__global__ __launch_bounds__(256) void k_apply(const float *delta, const double *dh_part, const SwBatchGrid *grids,
-                                               int cur, int H, int W, SwNorm nrm, int project, int bcx, int bcy,
-                                               SwGateStats *st) {
+__global__ __launch_bounds__(256) void k_apply(const float *delta, const double *dh_part, int nparts,
+                                               const SwBatchGrid *grids, int cur, int H, int W, SwNorm nrm, int project,
+                                               int bcx, int bcy, SwGateStats *st) {
     const int b = blockIdx.y;
     const SwBatchGrid &g = grids[b];
     const int64_t n = (int64_t)H * W;
     float dh_mean = 0.f;
     if (project) {
         __shared__ double s_part[4];
-        const int nparts = H * (W / 64);
         const double *part = dh_part + (int64_t)b * nparts;
         double acc = 0.0;
         for (int k = threadIdx.x; k < nparts; k += blockDim.x) acc += part[k];
@@ -579,11 +578,12 @@ unsigned per_grid_blocks(int64_t n, int B) {
 }
 
 
-hipError_t sw_sur_apply(const float *delta, const double *dh_part, const SwBatchGrid *grids, int cur, int B, int H,
-                        int W, SwNorm nrm, int project, int bcx, int bcy, SwGateStats *st, hipStream_t s) {
-    if (project && (!dh_part || W % 64 != 0)) return hipErrorInvalidValue;
+hipError_t sw_sur_apply(const float *delta, const double *dh_part, int nparts, const SwBatchGrid *grids, int cur,
+                        int B, int H, int W, SwNorm nrm, int project, int bcx, int bcy, SwGateStats *st,
+                        hipStream_t s) {
+    if (project && (!dh_part || nparts < 1)) return hipErrorInvalidValue;
     dim3 grid(per_grid_blocks((int64_t)H * W, B), B);
-    k_apply<<<grid, 256, 0, s>>>(delta, dh_part, grids, cur, H, W, nrm, project, bcx, bcy, st);
+    k_apply<<<grid, 256, 0, s>>>(delta, dh_part, nparts, grids, cur, H, W, nrm, project, bcx, bcy, st);
     return hipGetLastError();
 }
 

@@ -137,6 +137,7 @@ def solver_run(u0: torch.Tensor, nsteps: int, tune_cache: str | None = TUNE_CACH
     return b.export(), sec
 
 
+DEFAULT_FORM = 2   # sw_surrogate_set_fused: the library picks the rollout network's form per batch size
 WEIGHTS_256 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "surrogate_256x256_j8.npz")
 
 

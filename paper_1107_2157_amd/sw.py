@@ -138,6 +138,7 @@ SIGNATURES = {
                                                ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p]),
     "sw_surrogate_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "sw_surrogate_set_block_cap": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "sw_surrogate_set_fused": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "sw_surrogate_advance": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Gate),
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sw_step_noalloc": (ctypes.c_int, [Grid, Halo, ctypes.c_double, ctypes.c_double, ctypes.POINTER(Opts),
@@ -506,6 +507,11 @@ class Surrogate:
     def set_block_cap(self, max_blocks: int):
         """Cap the persistent convolution / weight-gradient grids (0: one block per resident slot)."""
         check(lib().sw_surrogate_set_block_cap(self.handle, max_blocks), "sw_surrogate_set_block_cap")
+
+    def set_fused(self, mode):
+        """Rollout network form: 1 / True one fused launch per jump, 0 / False one launch
+        per layer, 2 (the default) whichever the batch size favours."""
+        check(lib().sw_surrogate_set_fused(self.handle, int(mode)), "sw_surrogate_set_fused")
 
     def forward(self, u: torch.Tensor) -> torch.Tensor:
         """u: [B][3][H][W] FP32 on the GPU -> normalised delta [B][H][W][4]."""

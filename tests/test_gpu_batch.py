@@ -94,10 +94,12 @@ def test_graph_replays_equal_eager():
 
 
 TUNINGS = {sw.SCHEME_PAPER: (dict(rows=8, vec=1, order=0), dict(rows=16, vec=2, order=1, occupancy=4, prefetch=2),
-                             dict(rows=32, vec=4, order=0, prefetch=3), dict(rows=5, vec=2, order=1, prefetch=1)),
+                             dict(rows=32, vec=4, order=0, prefetch=3), dict(rows=5, vec=2, order=1, prefetch=1),
+                             dict(rows=8, vec=2, order=2, prefetch=2), dict(rows=3, vec=1, order=2, occupancy=4,
+                                                                            prefetch=2)),
            sw.SCHEME_TRANSVERSE: (dict(rows=8, vec=1, order=0, prefetch=1), dict(rows=16, vec=2, order=1, prefetch=2),
                                   dict(rows=32, vec=4, order=0, prefetch=2), dict(rows=5, vec=2, order=1, prefetch=1),
-                                  dict(rows=2, vec=1, order=0, prefetch=2))}
+                                  dict(rows=2, vec=1, order=0, prefetch=2), dict(rows=4, vec=1, order=2, prefetch=1))}
 
 
 @pytest.mark.parametrize("scheme", [sw.SCHEME_PAPER, sw.SCHEME_TRANSVERSE])
@@ -144,3 +146,28 @@ def test_per_grid_sticky_flag_and_dt():
     with pytest.raises(sw.Unstable):
         b.sync_status()
     assert t[0] != t[2]            # independent CFL dt per grid
+
+
+@pytest.mark.parametrize("scheme", [sw.SCHEME_PAPER, sw.SCHEME_TRANSVERSE])
+def test_persistent_walk_equals_wave_per_tile(scheme):
+    """The persistent schedule (order 2: resident waves, each walking a
+    contiguous run of the LPT table, the next entry loaded ahead, dt kept and
+    the signal-speed max flushed per grid) against one wave per tile, on a
+    batch with enough tiles (about 17 000 at 2-row, 64-column tiles) that
+    every wave walks several tiles and many runs cross from one grid into the
+    next: bitwise equal states with halos, times and step counts, CFL dt."""
+    rng = np.random.default_rng(11)
+    shapes = [(int(64 * rng.integers(1, 7)), int(32 * rng.integers(1, 13))) for _ in range(40)]
+    sts = states(shapes, 900, False)
+    announce(f"persistent batch walk, scheme {scheme}, {len(shapes)} grids")
+    outs = []
+    for order in (0, 2):
+        b = make_batch(shapes, sts, "f32", sw.REFLECT, dict(variant=2, rows=2, vec=1, order=order, prefetch=1),
+                       scheme=scheme)
+        b.step(9)
+        outs.append(([[a.numpy() for a in b.get_state(i, halo=True)] for i in range(len(shapes))], b.sync_status()))
+    (ra, sa), (rb, sb) = outs
+    for gi in range(len(shapes)):
+        for x, y in zip(ra[gi], rb[gi]):
+            assert np.array_equal(x, y), gi
+    assert sa == sb

@@ -520,3 +520,64 @@ def test_set_norm_drops_captured_rollouts():
     (b_eager, *_), = _rollout_runs(net, b, u0, nsteps, gate, graph=False, reps=1)
     assert torch.equal(b_graph, b_eager)
     assert not torch.equal(a_graph, b_graph)
+
+
+def _advance_both(net, u0, nsteps, gate):
+    """The same rollout with the fused network launch and with the per-layer
+    kernels: (state, fallbacks, last delta) of each."""
+    out = []
+    for fused in (True, False):
+        net.set_fused(fused)
+        state, fb, _ = surrogate.rollout(net, u0, nsteps, gate)
+        out.append((state, fb, net.activation(6, u0.shape[0]).clone()))
+    net.set_fused(surrogate.DEFAULT_FORM)
+    return out
+
+
+@pytest.mark.parametrize("n,H,W,cap", [(3, 40, 64, 0), (2, 37, 128, 0), (4, 256, 256, 0), (3, 40, 64, 2)])
+def test_fused_rollout_equals_per_layer(n, H, W, cap):
+    """The rollout's fused network launch (all six layers per tile in LDS,
+    the border recomputed) against the per-layer kernels: the prediction of
+    the last jump and, with the mass projection off, every grid's state
+    after two jumps are bitwise equal; with the projection on, the mean dh is
+    summed per tile instead of per row segment, so hu and hv stay bitwise
+    and h agrees to float rounding.  Shapes cover ragged bottom tiles (37 and
+    40 rows), both tile widths (16 x 32 where a batch has two such tiles per
+    CU: 4 grids of 256^2) and a capped persistent grid (each workgroup walks
+    several tiles)."""
+    announce(f"fused rollout n={n} {H}x{W} cap={cap}")
+    u0 = states(n, H, W, 61)
+    net = sw.Surrogate(H, W, n, jump=8, seed=4)
+    net.set_norm(OFF, SCALE, (0.02, 0.02, 0.02))
+    if cap:
+        net.set_block_cap(cap)
+    accept = dict(mass_rel_tol=10.0, hmin=-1.0e30)
+    (a, fa, da), (b, fb, db) = _advance_both(net, u0, 16, dict(accept, project_mass=False))
+    assert fa.tolist() == fb.tolist() == [0] * n
+    assert torch.equal(da, db)
+    assert torch.equal(a, b)
+    (a, fa, da), (b, fb, db) = _advance_both(net, u0, 16, dict(accept, project_mass=True))
+    assert torch.equal(da, db)
+    assert torch.equal(a[:, 1:], b[:, 1:])
+    assert torch.max(torch.abs(a[:, 0] - b[:, 0])).item() <= 4 * 2.0 ** -23 * torch.max(torch.abs(b[:, 0])).item()
+
+
+def test_fused_rollout_mixed_verdicts_equal_per_layer():
+    """A batch where the gate rejects some grids and accepts the others (a
+    depth threshold between the grids' depths): the fused path (gate verdict
+    and the rejected grids' solver steps in one launch) leaves bitwise the
+    per-layer path's states and fallback counts, and the rejected grids hold
+    the plain solver's result."""
+    n, H, W = 4, 48, 64
+    u0 = states(n, H, W, 67)
+    for k in (1, 3):                  # grids 1 and 3 sit below the threshold: depth at most 0.5
+        u0[k] *= 0.5 / u0[k, 0].max()
+    announce("fused rollout, mixed verdicts")
+    net = sw.Surrogate(H, W, n, jump=8, seed=5)
+    net.set_norm(OFF, SCALE, (0.02, 0.02, 0.02))
+    gate = dict(mass_rel_tol=10.0, hmin=0.75, project_mass=True)
+    (a, fa, _), (b, fb, _) = _advance_both(net, u0, 16, gate)
+    assert fa.tolist() == fb.tolist() == [0, 2, 0, 2]
+    assert torch.equal(a, b)
+    ref, _ = surrogate.solver_run(u0, 16, tune_cache=None)
+    assert torch.equal(a[1], ref[1]) and torch.equal(a[3], ref[3])
