@@ -47,6 +47,10 @@ WORKLOADS = {
                                        "transverse scheme"),
 }
 GOLDEN_4096 = os.path.join(ROOT, "tests", "golden", "swe4096_1000steps.json")
+# where the synthetic initial states are generated ("cpu" with --host-inputs:
+# they are then copied in, and the GPU runs only the library's kernels and
+# copies, which is how the committed profiles are taken)
+INPUT_DEVICE = "cuda"
 
 
 def scheme_of(name):
@@ -67,9 +71,9 @@ def make_solver(name, sw, ics, torch):
     scheme = sw.SCHEME_TRANSVERSE if scheme_of(name) == "transverse" else sw.SCHEME_PAPER
     s = sw.Solver(n, n, dtype=dtype, bc_x=bcv, bc_y=bcv, scheme=scheme)
     if seed is None:
-        st = ics.dam_break_state(n, device="cuda")
+        st = ics.dam_break_state(n, device=INPUT_DEVICE)
     else:
-        st = ics.bumps_state(n, n, seed=seed, periodic=bc == "periodic", count=8, device="cuda")
+        st = ics.bumps_state(n, n, seed=seed, periodic=bc == "periodic", count=8, device=INPUT_DEVICE)
     s.set_state(*st)
     del st
     torch.cuda.synchronize()
@@ -182,7 +186,7 @@ def run_fixed_dt(steps, fused_tuning, sw, ics, torch, tune_cache):
     multiple of every K, so no single-step remainder runs.  Both runs start
     from the same state; their final states must be bitwise equal."""
     n, dtype, _, seed, _, _ = WORKLOADS["swe16384-f32-periodic"]
-    st = ics.bumps_state(n, n, seed=seed, periodic=True, count=8, device="cuda")
+    st = ics.bumps_state(n, n, seed=seed, periodic=True, count=8, device=INPUT_DEVICE)
     h, hu, hv = st
     dt = 0.5 / float((torch.maximum(hu.abs(), hv.abs()) / h + torch.sqrt(9.8 * h)).max())
     s = sw.Solver(n, n, dtype=dtype, bc_x=sw.PERIODIC, bc_y=sw.PERIODIC, cfl=0.0, dt_fixed=dt)
@@ -298,7 +302,7 @@ def run_table1(sw, ics, torch, steps=100):
     rows = []
     for n, paper_ms in paper_table1_gpu_ms().items():
         s = sw.Solver(n, n, dtype="f32")
-        st = ics.bumps_state(n, n, seed=ics.SEED_BUMPS_4096, periodic=False, count=8, device="cuda")
+        st = ics.bumps_state(n, n, seed=ics.SEED_BUMPS_4096, periodic=False, count=8, device=INPUT_DEVICE)
         for _ in range(2):                         # graph capture for both buffers, warm
             s.state.cur = 0
             s.set_state(*st)
@@ -325,7 +329,7 @@ def run_batch(steps, sw, ics, torch, tune_cache, per_grid_steps):
     cells = sum(s * s for s in sides)
     b = sw.Batch(sides, dtype="f32")
     for k, n in enumerate(sides):
-        b.set_state(k, *ics.bumps_state(n, n, seed=ics.SEED_BATCH_GRID0 + k, periodic=False, device="cuda"))
+        b.set_state(k, *ics.bumps_state(n, n, seed=ics.SEED_BATCH_GRID0 + k, periodic=False, device=INPUT_DEVICE))
     torch.cuda.synchronize()
     tuning = b.autotune(steps_per_trial=3, cache_path=tune_cache)
     b.step(2)                                          # warm: captures the graph for this call shape
@@ -347,7 +351,7 @@ def run_batch(steps, sw, ics, torch, tune_cache, per_grid_steps):
     solvers = []
     for k, n in enumerate(sides):
         s = sw.Solver(n, n, dtype="f32")
-        s.set_state(*ics.bumps_state(n, n, seed=ics.SEED_BATCH_GRID0 + k, periodic=False, device="cuda"))
+        s.set_state(*ics.bumps_state(n, n, seed=ics.SEED_BATCH_GRID0 + k, periodic=False, device=INPUT_DEVICE))
         solvers.append(s)
     for s in solvers:
         s.step(1)
@@ -387,7 +391,7 @@ def run_surrogate(sw, ics, torch, n=256, size=256, nsteps=64, kernels=True):
         net, meta = surrogate.load_weights(surrogate.WEIGHTS_256, n)
     else:   # timings only: accuracy figures of an untrained network mean nothing
         net, meta = sw.Surrogate(size, size, n, jump=8, seed=1), {"untrained": True}
-    u0 = surrogate.initial_states(n, size, size, ics.SEED_SURR_EVAL0)
+    u0 = surrogate.initial_states(n, size, size, ics.SEED_SURR_EVAL0, device=INPUT_DEVICE).cuda()
     ref, t_solver = surrogate.solver_run(u0, nsteps)
     gate = dict(mass_rel_tol=1e-4, project_mass=True)
     b = sw.Batch([(size, size)] * n, dtype="f32")
@@ -451,9 +455,7 @@ def surrogate_kernels(sw, ics, torch, n=256, size=256, reps=3):
     the per-layer kernels (eager launches, gate wide open, so that every
     jump is the network's)."""
     from paper_1107_2157_amd import surrogate
-    # inputs built on the host and copied in: the process launches only the
-    # library's kernels (and the runtime's copies), which keeps it profilable
-    u0 = surrogate.initial_states(n, size, size, ics.SEED_SURR_EVAL0, device="cpu").cuda()
+    u0 = surrogate.initial_states(n, size, size, ics.SEED_SURR_EVAL0, device=INPUT_DEVICE).cuda()
     b = sw.Batch([(size, size)] * n, dtype="f32")
     b.load(u0)
     b.step(8)
@@ -564,11 +566,16 @@ def main():
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1107_2157_amd", "tune_cache_gfx950.txt"),
                     help="autotuner cache (launch shapes found by sw_autotune on MI355X; missing keys are tuned "
                          "and appended)")
+    ap.add_argument("--host-inputs", action="store_true",
+                    help="generate the initial states on the host and copy them in (for profiled runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 3 GiB device-to-device copy (counter calibration) and exit")
     ap.add_argument("--tuning", default=None,
                     help="fixed launch shape 'variant,rows,vec,occupancy' instead of the autotuner")
     args = ap.parse_args()
+    global INPUT_DEVICE
+    if args.host_inputs:
+        INPUT_DEVICE = "cpu"
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no "
               "domain-decomposed path", file=sys.stderr)

@@ -417,7 +417,7 @@ sw_status sw_surrogate_set_block_cap(sw_net *net, int32_t max_blocks);
  * grids' solver steps share one launch: three launches per jump.  0: one
  * launch per layer through activation tensors in device memory, then
  * separate gate and fallback launches.  2 (default): 1 while the batch has
- * at most 16 output tiles of 16 x 32 pixels per compute unit, else 0 (the
+ * at most 2 output tiles of 16 x 32 pixels per compute unit, else 0 (the
  * fused form recomputes each tile's border and wins where launches and HBM
  * traffic dominate, i.e. at small batches).  The predictions are bitwise
  * equal; with project_mass the mean of the predicted dh is summed in a

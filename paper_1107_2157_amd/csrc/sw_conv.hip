@@ -40,16 +40,20 @@ constexpr int kStageCols = kTileCols + 2;   // staged pixels per row (halo)
 __device__ __forceinline__ int chunk_off(int p, int c) { return p * 32 + ((c ^ ((p >> 1) & 3)) << 3); }
 
 // Persistent, LDS-staged 3x3 convolution.  Each block owns a contiguous run
-// of ROWS-row x 64-pixel output tiles (ROWS = waves per block) (contiguous, so neighbouring tiles share
-// halo rows in the same XCD's L2) and keeps the layer's weights (the MFMA A
-// operands of every K step) in registers for its whole life.  A tile's input
+// of ROWS-row x 64-pixel output tiles (ROWS = waves per block), numbered down
+// the columns of tiles, so the tile a block takes next is the one below the
+// last and re-reads two of its staged rows while they are still in L2 (with
+// the run along the rows, counters showed 1.5x the input bytes coming from
+// HBM), and keeps the layer's weights (the MFMA A operands of every K step)
+// in registers for its whole life.  A tile's input
 // rows ((ROWS + 2) x 66 pixels x CIN channels, halo included) are staged in LDS, double
 // buffered: the global loads of tile t + 1 are in flight while the MFMAs of
 // tile t read LDS.  Wave w computes output row w of the tile: per K step one
 // 16-byte LDS read per 16-pixel block gives the B operand (16 pixels x 64 B
-// contiguous per wave: conflict free).
+// per wave, chunks swizzled by chunk_off so that the reads are conflict
+// free).
 template <int CIN, int COUT, int MODE, int ROWS>
-__global__ __launch_bounds__(64 * ROWS) void k_conv3x3(SwConvArgs a, int tiles_y, int tiles_x, int ntiles) {
+__global__ __launch_bounds__(64 * ROWS, 2) void k_conv3x3(SwConvArgs a, int tiles_y, int tiles_x, int ntiles) {
     constexpr int NT = 64 * ROWS;
     constexpr int MB = (COUT + 15) / 16;
     constexpr int KS = ksteps<CIN>();
@@ -83,7 +87,7 @@ __global__ __launch_bounds__(64 * ROWS) void k_conv3x3(SwConvArgs a, int tiles_y
     auto load_tile = [&](int t) {
         const int b = t / (tiles_y * tiles_x);
         const int r = t - b * tiles_y * tiles_x;
-        const int ty = r / tiles_x, tx = r - ty * tiles_x;
+        const int tx = r / tiles_y, ty = r - tx * tiles_y;        // column-major: the next tile is the one below
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int c = threadIdx.x + k * NT;
@@ -127,7 +131,7 @@ __global__ __launch_bounds__(64 * ROWS) void k_conv3x3(SwConvArgs a, int tiles_y
         if (t + 1 < t1) load_tile(t + 1);                         // in flight during the MFMAs below
         const int b = t / (tiles_y * tiles_x);
         const int r = t - b * tiles_y * tiles_x;
-        const int ty = r / tiles_x, tx = r - ty * tiles_x;
+        const int tx = r / tiles_y, ty = r - tx * tiles_y;        // column-major: the next tile is the one below
         const int y = ty * ROWS + w;                               // output row of this wave
         const int x0 = tx * kTileCols;
         const __bf16 *T = tile[buf];

@@ -73,7 +73,7 @@ __device__ __forceinline__ bf16x8 load_wk(const __bf16 *Wk, int mb, int ks, int 
 // stored).  (gy0, gx0): grid coordinates of the region's first pixel; bias:
 // the layer's biases in LDS.  wcur holds the weights of K step 0 on entry
 // and, on return, those of the next layer (next_wk), loaded during this
-// layer's last K step, after which at_last() issues the caller's own loads
+// layer's last K steps, after which at_last() issues the caller's own loads
 // (the next tile's input), so that no wait for this layer's operands waits
 // for them.
 template <int CIN, int COUT, int MODE, int WOUT, int HOUT, int NW, int MBN, int KSN, typename AtLast>
@@ -120,25 +120,30 @@ __device__ __forceinline__ double run_layer(const __bf16 *src, __bf16 *dst, cons
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int k = 0; k < NB; ++k) acc[mb][k] = f32x4{0.f, 0.f, 0.f, 0.f};
-    bf16x8 wa[2][MB], xb[2][NB];
+    // weights run WD K steps ahead (a global load's latency is longer than one
+    // K step's MFMAs), B operands one step ahead
+    constexpr int WD = KS > 2 ? 2 : 1;
+    bf16x8 wa[WD + 1][MB], xb[2][NB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) wa[0][mb] = wcur[mb];
+#pragma unroll
+    for (int d = 1; d < WD; ++d) load_w(d, wa[d]);
     load_b(0, xb[0]);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-        if (ks + 1 < KS) {
-            load_w(ks + 1, wa[(ks + 1) & 1]);
-            load_b(ks + 1, xb[(ks + 1) & 1]);
-        } else {   // the next layer's first weights (MBN M blocks, KSN K steps), then what the caller issues last
+        if (ks + WD < KS) load_w(ks + WD, wa[(ks + WD) % (WD + 1)]);
+        if (ks + WD == KS) {   // the next layer's first weights (MBN M blocks, KSN K steps)
 #pragma unroll
             for (int mb = 0; mb < MBN; ++mb) wcur[mb] = load_wk<KSN>((const __bf16 *)next_wk, mb, 0, n, g);
-            at_last();
         }
+        if (ks + 1 < KS) load_b(ks + 1, xb[(ks + 1) & 1]);
+        else at_last();        // then what the caller issues last
 #pragma unroll
         for (int k = 0; k < NB; ++k)
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
-                acc[mb][k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[ks & 1][mb], xb[ks & 1][k], acc[mb][k], 0, 0, 0);
+                acc[mb][k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[ks % (WD + 1)][mb], xb[ks & 1][k], acc[mb][k],
+                                                                     0, 0, 0);
     }
     // epilogue: lane holds channels mb * 16 + 4 g .. + 3 of pixel pp[k]
     double dh = 0.0;

@@ -419,10 +419,11 @@ namespace {
 // automatic mode: while the batch has at most kFusedMaxTiles 16 x 32 output
 // tiles per CU.  The fused launch recomputes a 6-pixel border of every tile
 // (1.5-1.8x the flops) but moves only the state and the prediction through
-// HBM and takes one launch per jump instead of six; measured on MI355X at
-// 256^2 grids it is 1.4x faster than the per-layer launches at batch 1 and
-// even at batch 16 (8 tiles per CU), and slower from about 64 tiles per CU.
-constexpr int kFusedMaxTiles = 16;
+// HBM and takes one launch per jump instead of six; measured on MI355X with
+// 256^2 grids (128 such tiles each), the whole 64-step rollout is 1.37x
+// faster than with per-layer launches at batch 1, 1.05x at batch 4 (2 tiles
+// per CU), and 0.94x at batch 8.
+constexpr int kFusedMaxTiles = 2;
 bool rollout_fused(const sw_net *n, int B) {
     if (n->fused_mode != 2) return n->fused_mode == 1;
     const int64_t tiles = (int64_t)B * ((n->H + 15) / 16) * (n->W / 32);

@@ -110,7 +110,8 @@ __global__ void k_reduce_sum(const float *partial, int n, float *out) {
 // Weight gradient partials on MFMA (v_mfma_f32_16x16x32_bf16), K = pixels:
 //     dW[co][(tap, ci)] = sum_p dZ[p][co] A[p + off(tap)][ci]
 // read from the NHWC tensors.  Persistent blocks walk contiguous runs of
-// 4-row x 64-pixel tiles and keep dW in registers.  A tile's dZ (4 x 64
+// 4-row x 64-pixel tiles, numbered down the columns of tiles (the next tile's
+// halo rows are still in L2), and keep dW in registers.  A tile's dZ (4 x 64
 // pixels) and input rows (6 x 66 pixels, halo included) are staged in LDS
 // transposed, channel-major with the pixels contiguous, so 8 consecutive
 // pixels of one channel are one 16-byte LDS read (row strides padded so the
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(CINP == 32 ? 384 : 192) void k_wgrad(const __bf16 *
     auto load_tile = [&](int t) {
         const int b = t / (tiles_y * tiles_x);
         const int r = t - b * tiles_y * tiles_x;
-        const int ty = r / tiles_x, tx = r - ty * tiles_x;
+        const int tx = r / tiles_y, ty = r - tx * tiles_y;   // column-major: the next tile is the one below
 #pragma unroll
         for (int k = 0; k < DZ_PER; ++k) {   // chunk c = (row * NKO + part) * 64 + p
             const int c = threadIdx.x + k * NTH;
