@@ -15,6 +15,9 @@ using namespace sw::tile;
 
 namespace {
 
+// A slot is read by one wave (a stripe per lane) and indexed with a mask.
+static_assert(kBatchStripes <= 64 && (kBatchStripes & (kBatchStripes - 1)) == 0, "stripes: power of two, at most 64");
+
 // dt of grid `grid` for step `step` (wave-wide).
 // The grid's dt in two halves (its ring stripe, a load; then the wave max
 // and the division), so that the step kernel issues its first row loads in
@@ -318,8 +321,8 @@ __global__ __launch_bounds__(64 * kFbWaves) void k_batch_fallback(SwBatchLaunch 
 __global__ void k_batch_reset(SwBatchScalars *sc, int n, int clear_time) {
     const int gi = blockIdx.x;
     if (gi >= n) return;
-    if (threadIdx.x < 3 * kBatchStripes)
-        sc[gi].smax[threadIdx.x / kBatchStripes][threadIdx.x % kBatchStripes] = 0ull;
+    for (int k = threadIdx.x; k < 3 * kBatchStripes; k += blockDim.x)
+        sc[gi].smax[k / kBatchStripes][k % kBatchStripes] = 0ull;
     if (clear_time && threadIdx.x == 0) {
         sc[gi].t = 0.0;
         sc[gi].last_dt = 0.0;

@@ -5,9 +5,12 @@
 
 #include "sw_internal.h"
 
-constexpr int kBatchStripes = 16;
+// Words each CFL ring slot of a batched grid is striped over: one per lane of
+// a wave, so that the tiles of a large grid rarely meet on one atomic word.
+constexpr int kBatchStripes = 64;
 
-// Per-grid device scalars (CFL ring slots striped over 16 words, time, flag).
+// Per-grid device scalars (CFL ring slots striped over kBatchStripes words,
+// time, flag).
 struct SwBatchScalars {
     unsigned long long smax[3][kBatchStripes];
     double t;
