@@ -51,7 +51,9 @@ __device__ __forceinline__ int chunk_off(int p, int c) { return p * 32 + ((c ^ (
 // tile t read LDS.  Wave w computes output row w of the tile: per K step one
 // 16-byte LDS read per 16-pixel block gives the B operand (16 pixels x 64 B
 // per wave, chunks swizzled by chunk_off so that the reads are conflict
-// free).
+// free).  Runs the 8-channel input layer and the input-gradient mode; the
+// 32-channel forward modes run k_conv3x3_dma below, which keeps two tiles'
+// loads in flight.
 template <int CIN, int COUT, int MODE, int ROWS>
 __global__ __launch_bounds__(64 * ROWS, 2) void k_conv3x3(SwConvArgs a, int tiles_y, int tiles_x, int ntiles) {
     constexpr int NT = 64 * ROWS;
@@ -292,6 +294,271 @@ int sw_device_cus() {
 
 namespace {
 
+constexpr int kDmaRows = 8;   // tile height of the LDS DMA kernel
+
+// LDS byte address of a __shared__ object.
+__device__ __forceinline__ unsigned lds_addr(const void *p) {
+    return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+
+// One LDS DMA instruction (global_load_lds_dwordx4): lane l's 16 bytes at
+// base + off (off in bytes, per lane) go to LDS byte address lds + 16 l.
+// Asynchronous and counted in vmcnt like a load; written as asm so that the
+// compiler, which does not see the LDS write, does not wait for it before
+// every LDS read: the kernel waits for it itself.
+__device__ __forceinline__ void lds_dma16(const void *base, unsigned off, unsigned lds) {
+    // (one wait state between the M0 write and its use by the DMA)
+    asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1" ::"v"(off), "s"(base), "s"(lds)
+                 : "memory", "m0");
+}
+
+// Wait until at most n vector memory operations of this wave are
+// outstanding (n wave-uniform; values above K wait for K).  Vector memory
+// operations complete in issue order, so this leaves exactly the n newest
+// in flight.
+template <int K> __device__ __forceinline__ void wait_vm_upto(int n) {
+    if constexpr (K > 0) {
+        if (n >= K) {
+            asm volatile("s_waitcnt vmcnt(%0)" ::"n"(K) : "memory");
+            return;
+        }
+        wait_vm_upto<K - 1>(n);
+    } else {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+}
+
+// The forward 32-channel modes (residual block, output layer) with the
+// input tiles brought in by LDS DMA, three buffers deep: while tile t is
+// computed, the loads of tiles t + 1 and t + 2 are in flight and hold no
+// registers.  With 8-row tiles (one workgroup of 8 waves per CU: three
+// 43 KB input buffers and the waves' 4 KB output staging areas fill the
+// 160 KB of LDS) two tiles' loads, 86 KB, are in flight per CU.  Same
+// operands, MFMA order and output staging as k_conv3x3, hence the same
+// results.
+//
+// A tile's (ROWS + 2) x 66 staged pixels are 16-byte slots; slot s holds
+// chunk (s & 3) ^ ((p >> 1) & 3) of pixel p = s >> 2 (the chunk_off
+// layout), so one DMA instruction fills 64 consecutive slots.  The slots
+// are padded to whole instructions; the padding lanes load a slot of the
+// window again and land past its end.  Rows past the image's bottom halo
+// row (below the last tile of an image whose height is not a multiple of
+// ROWS) are loaded from that halo row: they feed only outputs that are
+// never stored.
+template <int COUT, int MODE, int ROWS>
+__global__ __launch_bounds__(64 * ROWS, 1) void k_conv3x3_dma(SwConvArgs a, int tiles_y, int tiles_x, int ntiles) {
+    constexpr int CIN = 32;
+    constexpr int OST = MODE == SW_CONV_RESID_BF16 ? kTileCols * COUT : 8;   // output staging per wave (bf16)
+    constexpr int MB = (COUT + 15) / 16;
+    constexpr int KS = ksteps<CIN>();
+    constexpr int KP = KS * 32;
+    constexpr int NPB = kTileCols / 16;
+    constexpr int SLOTS = (ROWS + 2) * kStageCols * 4;
+    constexpr int NI = (SLOTS + 63) / 64;          // DMA instructions per tile
+    constexpr int BUF = NI * 64 * 8;               // bf16 per buffer
+    constexpr int PERW = (NI + ROWS - 1) / ROWS;   // most instructions of one wave
+    constexpr int NBUF = 3;
+    static_assert(MODE == SW_CONV_RESID_BF16 || MODE == SW_CONV_F32, "forward 32-channel modes only");
+    __shared__ __attribute__((aligned(16))) __bf16 tile[NBUF][BUF];
+    __shared__ __attribute__((aligned(16))) __bf16 ostage[ROWS][OST];
+
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = lane >> 4, n = lane & 15;
+    const int Wp = a.W + 2;
+    const int per_block = (ntiles + gridDim.x - 1) / gridDim.x;
+    const int t0 = blockIdx.x * per_block;
+    const int t1 = min(ntiles, t0 + per_block);
+    if (t0 >= t1) return;                          // uniform per block: no barrier is skipped by part of it
+
+    bf16x8 wa[KS][MB];
+    const __bf16 *Wk = (const __bf16 *)a.w;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+            wa[ks][mb] = *reinterpret_cast<const bf16x8 *>(Wk + (int64_t)(mb * 16 + n) * KP + ks * 32 + 8 * g);
+    float bias[MB][4];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            bias[mb][q] = MODE == SW_CONV_F32 ? (q < COUT ? a.bias[q] : 0.f) : a.bias[mb * 16 + 4 * g + q];
+
+    // this wave's DMA instructions i = w + ROWS k (k < nw): per lane the
+    // slot's byte offset from the window's first pixel, and its window row
+    const int nw = (NI - w + ROWS - 1) / ROWS;
+    unsigned soff[PERW];
+    int srow[PERW];
+#pragma unroll
+    for (int k = 0; k < PERW; ++k) {
+        int sl = (w + ROWS * k) * 64 + lane;
+        if (sl >= SLOTS) sl = lane;                // padding: reload a slot of the window
+        const int p = sl >> 2, c = (sl & 3) ^ ((p >> 1) & 3);
+        const int row = p / kStageCols, col = p - row * kStageCols;
+        soff[k] = (unsigned)(((row * Wp + col) * CIN + c * 8) * 2);
+        srow[k] = row;
+    }
+    const char *X = (const char *)a.x;
+    auto issue = [&](int t, int buf) {
+        const int b = t / (tiles_y * tiles_x);
+        const int r = t - b * tiles_y * tiles_x;
+        const int tx = r / tiles_y, ty = r - tx * tiles_y;
+        const char *base = X + ((((int64_t)b * (a.H + 2) + ty * ROWS) * Wp + tx * kTileCols) * CIN) * 2;
+        const int rmax = a.H + 1 - ty * ROWS;      // last window row inside the image's halo
+        const unsigned l0 = lds_addr(&tile[0][0]) + (unsigned)(buf * BUF * 2);
+#pragma unroll
+        for (int k = 0; k < PERW; ++k) {
+            if (k < nw) {
+                const unsigned off =
+                    srow[k] > rmax ? soff[k] - (unsigned)((srow[k] - rmax) * Wp * CIN * 2) : soff[k];
+                lds_dma16(base, off, l0 + (unsigned)((w + ROWS * k) * 1024));
+            }
+        }
+    };
+
+    issue(t0, 0);
+    if (t0 + 1 < t1) issue(t0 + 1, 1);
+    wait_vm_upto<PERW>(t0 + 1 < t1 ? nw : 0);      // tile t0 has landed (t0 + 1 may be in flight)
+    __syncthreads();
+    for (int t = t0; t < t1; ++t) {
+        const int buf = (t - t0) % NBUF;
+        if (t + 2 < t1) issue(t + 2, (t - t0 + 2) % NBUF);   // its buffer was last read before the barrier
+        const int b = t / (tiles_y * tiles_x);
+        const int r = t - b * tiles_y * tiles_x;
+        const int tx = r / tiles_y, ty = r - tx * tiles_y;
+        const int y = ty * ROWS + w;
+        const int x0 = tx * kTileCols;
+        const __bf16 *T = tile[buf];
+
+        f32x4 acc[MB][NPB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int pb = 0; pb < NPB; ++pb) acc[mb][pb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int dy = ks / 3, dx = ks % 3;
+#pragma unroll
+            for (int pb = 0; pb < NPB; ++pb) {
+                const int px = (w + dy) * kStageCols + pb * 16 + n + dx;
+                const bf16x8 xb = *reinterpret_cast<const bf16x8 *>(T + chunk_off(px, g));
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+                    acc[mb][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[ks][mb], xb, acc[mb][pb], 0, 0, 0);
+            }
+        }
+
+        int stores = 0;                            // vector memory operations issued below
+        if (y < a.H) {
+            if constexpr (MODE == SW_CONV_F32) {
+                double dh = 0.0;
+                if (g == 0) {
+#pragma unroll
+                    for (int pb = 0; pb < NPB; ++pb) {
+                        f32x4 v = acc[0][pb];
+                        float *Y = a.yf + (((int64_t)b * a.H + y) * a.W + x0 + pb * 16 + n) * 4;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) v[q] = q < COUT ? v[q] + bias[0][q] : 0.f;
+                        *reinterpret_cast<f32x4 *>(Y) = v;
+                        dh += (double)v[0];
+                    }
+                }
+                stores = NPB;
+                if (a.dh_part) {
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) dh += __shfl_xor(dh, o);
+                    if (lane == 0) a.dh_part[((int64_t)b * a.H + y) * tiles_x + tx] = dh;
+                    stores += 1;
+                }
+            } else {
+                // the wave's 64 pixels x 32 channels are one contiguous run of the
+                // NHWC row: staged in the wave's LDS area (chunks swizzled as the
+                // input tile's), then stored as 16 contiguous bytes per lane
+                const int64_t row0 = (((int64_t)b * (a.H + 2) + y + 1) * Wp + x0 + 1) * COUT;
+                auto slot = [&](int mb, int pb) -> bf16x4 & {
+                    return *reinterpret_cast<bf16x4 *>(&ostage[w][chunk_off(pb * 16 + n, 2 * mb + (g >> 1)) + 4 * (g & 1)]);
+                };
+                auto wave_sync = [] {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                };
+                constexpr int FL = kTileCols * COUT / 512;    // 16-byte stores per lane per output
+                auto flush = [&](__bf16 *dst) {
+                    wave_sync();
+#pragma unroll
+                    for (int k = 0; k < FL; ++k) {
+                        const int e = k * 512 + lane * 8;
+                        __builtin_nontemporal_store(
+                            *reinterpret_cast<const bf16x8 *>(&ostage[w][chunk_off(e >> 5, (e >> 3) & 3)]),
+                            reinterpret_cast<bf16x8 *>(dst + row0 + e));
+                    }
+                    wave_sync();
+                };
+                auto relu_part = [&](int mb, int pb) {
+                    f32x4 v = acc[mb][pb];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) v[q] = fmaxf(v[q] + bias[mb][q], 0.f);
+                    return v;
+                };
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int pb = 0; pb < NPB; ++pb) {
+                        f32x4 v = relu_part(mb, pb);
+                        const bf16x4 xin = *reinterpret_cast<const bf16x4 *>(
+                            T + chunk_off((w + 1) * kStageCols + pb * 16 + n + 1, 2 * mb + (g >> 1)) + 4 * (g & 1));
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) v[q] += (float)xin[q];
+                        slot(mb, pb) = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+                    }
+                flush((__bf16 *)a.y);
+                stores = FL;
+                if (a.y2) {
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                        for (int pb = 0; pb < NPB; ++pb) {
+                            const f32x4 v = relu_part(mb, pb);
+                            slot(mb, pb) = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+                        }
+                    flush((__bf16 *)a.y2);
+                    stores += FL;
+                }
+            }
+        }
+        // tile t + 1 has landed: newer than its loads are tile t + 2's loads
+        // and this tile's stores (the previous tile's stores are older still).
+        // `stores` counts the store instructions issued above (one per
+        // 16-byte lane store of a flush, one per f32x4 store, the row sum);
+        // the loop issues no other vector memory operation.  A count below
+        // the true one only waits longer.
+        if (t + 1 < t1) wait_vm_upto<PERW + (MODE == SW_CONV_F32 ? NPB + 1 : 2 * kTileCols * COUT / 512)>(
+            (t + 2 < t1 ? nw : 0) + stores);
+        __syncthreads();
+    }
+}
+
+template <int COUT, int MODE>
+hipError_t launch_dma(const SwConvArgs &a, hipStream_t s) {
+    constexpr int ROWS = kDmaRows;
+    if (a.W % kTileCols != 0) return hipErrorInvalidValue;
+    const int tiles_y = (a.H + ROWS - 1) / ROWS, tiles_x = a.W / kTileCols;
+    const int64_t ntiles = (int64_t)a.B * tiles_y * tiles_x;
+    if (ntiles > (int64_t)1 << 30) return hipErrorInvalidValue;
+    static const int resident = [] {
+        int r = 0;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, k_conv3x3_dma<COUT, MODE, ROWS>, 64 * ROWS, 0) == hipSuccess &&
+                       r > 0
+                   ? r
+                   : 1;
+    }();
+    int64_t blocks = std::min<int64_t>(ntiles, (int64_t)sw_device_cus() * resident);
+    if (a.max_blocks > 0) blocks = std::min<int64_t>(blocks, a.max_blocks);
+    k_conv3x3_dma<COUT, MODE, ROWS><<<(unsigned)blocks, 64 * ROWS, 0, s>>>(a, tiles_y, tiles_x, (int)ntiles);
+    return hipGetLastError();
+}
+
 template <int CIN, int COUT, int MODE, int ROWS>
 hipError_t launch(const SwConvArgs &a, hipStream_t s) {
     if (a.W % kTileCols != 0) return hipErrorInvalidValue;
@@ -312,10 +579,10 @@ hipError_t launch(const SwConvArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Tile height of the forward modes.  8-row tiles (staged input rows 1.25x
-// the rows written instead of 1.5x, one block of 8 waves per CU instead of
-// two of 4) measured the same forward time at 256 x 256 x 256: the halo rows
-// are served by L2, not HBM.
+// Tile height of the 8-channel forward modes (register-staged kernel).
+// 8-row tiles (staged input rows 1.25x the rows written instead of 1.5x, one
+// block of 8 waves per CU instead of two of 4) measured the same forward
+// time at 256 x 256 x 256: the halo rows are served by L2, not HBM.
 constexpr int kFwdRows = 4;
 
 }  // namespace
@@ -330,8 +597,8 @@ hipError_t sw_conv3x3(const SwConvArgs &a, int cin, int cout, int mode, hipStrea
         return launch<8, 32, SW_CONV_RELU_PLANES, kFwdRows>(a, s);
     }
     if (cin == 32 && cout == 32 && mode == SW_CONV_RESID_BF16)
-        return launch<32, 32, SW_CONV_RESID_BF16, kFwdRows>(a, s);
-    if (cin == 32 && cout == 3 && mode == SW_CONV_F32) return launch<32, 3, SW_CONV_F32, kFwdRows>(a, s);
+        return launch_dma<32, SW_CONV_RESID_BF16>(a, s);
+    if (cin == 32 && cout == 3 && mode == SW_CONV_F32) return launch_dma<3, SW_CONV_F32>(a, s);
     if (cin == 32 && cout == 32 && mode == SW_CONV_DGRAD) return launch<32, 32, SW_CONV_DGRAD, 4>(a, s);
     if (cin == 8 && cout == 32 && mode == SW_CONV_DGRAD) return launch<8, 32, SW_CONV_DGRAD, 4>(a, s);
     return hipErrorInvalidValue;
