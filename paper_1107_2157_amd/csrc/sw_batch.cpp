@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <cstdarg>
 #include <cstdio>
@@ -605,17 +606,44 @@ sw_status sw_batch_autotune(sw_batch *b, int32_t steps_per_trial, const char *ca
         if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
         return hipEventElapsedTime(ms, e0, e1);
     };
-    b->use_graph = false;
+    // Trials replay graphs, as sw_batch_step runs (eager launches would time
+    // the host's launch rate on small batches); each shape's graphs are
+    // captured in an untimed warm-up first, and every run starts from the
+    // saved state (so from the same buffer, whose graphs were captured).
+    b->use_graph = true;
+    auto warm = [&](int k1, int k2) -> hipError_t {
+        drop_graphs(b);
+        hipError_t e = restore();
+        if (e != hipSuccess) return e;
+        if (sw_batch_step(b, k1, stream) != SW_OK) return hipErrorUnknown;
+        if (k2 > 0 && sw_batch_step(b, k2, stream) != SW_OK) return hipErrorUnknown;
+        return restore();
+    };
+    // Steps per trial: enough for the timed difference to span about 2 ms
+    // (small batches take a few microseconds per step), measured with the
+    // tuning in place; each trial takes the best of two runs of each length.
+    int steps = steps_per_trial;
+    if (he == hipSuccess && (he = warm(steps, 0)) == hipSuccess) {
+        float m = 0.f;
+        if ((he = timed(steps, &m)) == hipSuccess && m > 0.f && m < 2.f)
+            steps = (int)std::min<double>(2000.0, std::ceil(steps * 2.0 / m));
+    }
     sw_tuning best{};
     double best_us = 1e300;
     for (size_t i = 0; i < cands.size() && he == hipSuccess; ++i) {
         if (sw_batch_set_tuning(b, &cands[i]) != SW_OK) continue;
-        if ((he = restore()) != hipSuccess) break;
-        float m1 = 0.f, mk = 0.f;
-        if (sw_batch_step(b, 1, stream) != SW_OK) continue;
-        if ((he = timed(1, &m1)) != hipSuccess) break;
-        if ((he = timed(1 + steps_per_trial, &mk)) != hipSuccess) break;
-        const double us = 1000.0 * (mk - m1) / steps_per_trial;
+        if ((he = warm(1, 1 + steps)) != hipSuccess) break;
+        float m1 = 1e30f, mk = 1e30f;
+        for (int rep = 0; rep < 2 && he == hipSuccess; ++rep) {
+            float a = 0.f, c = 0.f;
+            if (rep > 0 && (he = restore()) != hipSuccess) break;
+            if ((he = timed(1, &a)) != hipSuccess) break;
+            if ((he = timed(1 + steps, &c)) != hipSuccess) break;
+            m1 = std::min(m1, a);
+            mk = std::min(mk, c);
+        }
+        if (he != hipSuccess) break;
+        const double us = 1000.0 * (mk - m1) / steps;
         if (us < best_us) {
             best_us = us;
             best = cands[i];
@@ -625,6 +653,8 @@ sw_status sw_batch_autotune(sw_batch *b, int32_t steps_per_trial, const char *ca
     if (he == hipSuccess) he = hipStreamSynchronize(s);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);           // no trial graph is still running
+    drop_graphs(b);                          // the trial shapes' graphs
     (void)hipFree(backup);
     (void)hipFree(sbackup);
     b->use_graph = graph0;

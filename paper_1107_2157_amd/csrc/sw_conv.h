@@ -107,9 +107,18 @@ hipError_t sw_sur_relayout(const float *master, const SwLayerDesc *layers, int n
 // dh_part: partial sums of the normalised dh, nparts per grid ([B][nparts]:
 // the per-layer output layer's per-row-segment sums, or the fused network's
 // per-tile sums), summed per grid in a fixed order for the mass projection.
+// part / ticket: scratch of the statistics' reduction, sw_sur_apply_slots
+// entries and one ticket per grid (zero before the first call; every call
+// leaves the tickets at zero).
+struct SwApplyPart {
+    unsigned long long mo, mn;       // FP64 bits: the block's sums of h before and after
+    unsigned long long hmin_bad;     // FP32 bits of the block's least h (high word), non-finite flag (low)
+    unsigned long long pad;
+};
+unsigned sw_sur_apply_slots(int64_t pixels, int B);
 hipError_t sw_sur_apply(const float *delta, const double *dh_part, int nparts, const SwBatchGrid *grids, int cur,
                         int B, int H, int W, SwNorm nrm, int project, int bcx, int bcy, SwGateStats *st,
-                        hipStream_t s);
+                        SwApplyPart *part, unsigned *ticket, hipStream_t s);
 // The gate's verdict per grid (active[b] = 1 and fallbacks[b] += 1 for a
 // rejected jump); rejected grids get U^n (buffer cur, halos included) copied
 // over the prediction in buffer cur ^ 1, where the solver then takes the jump.

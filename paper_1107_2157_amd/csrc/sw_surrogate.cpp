@@ -48,6 +48,8 @@ struct sw_net {
     // form the batch size favours (rollout_fused)
     int fused_mode = 2;
     SwGateStats *stats = nullptr;
+    SwApplyPart *apply_part = nullptr;   // the update's per-block statistics ([B][blocks per grid])
+    unsigned *apply_ticket = nullptr;    // per grid, blocks of the update done (zero between launches)
     int32_t *active = nullptr;
     // judge mode: a clone of the advanced batch that runs the plain solver
     sw_batch *shadow = nullptr;
@@ -261,6 +263,9 @@ sw_status sw_surrogate_create(const sw_net_cfg *cfg, int32_t H, int32_t W, int32
     if (st == SW_OK) st = dalloc(n, (void **)&n->target, (size_t)max_batch * H * W * 16);
     if (st == SW_OK) st = dalloc(n, (void **)&n->stats, (size_t)max_batch * sizeof(SwGateStats));
     if (st == SW_OK) st = dalloc(n, (void **)&n->dh_part, (size_t)max_batch * H * (W / 64) * sizeof(double));
+    if (st == SW_OK)
+        st = dalloc(n, (void **)&n->apply_part, (size_t)sw_sur_apply_slots((int64_t)H * W, max_batch) * sizeof(SwApplyPart));
+    if (st == SW_OK) st = dalloc(n, (void **)&n->apply_ticket, (size_t)max_batch * sizeof(unsigned));
     if (st == SW_OK)   // the smallest fused tile is 16 x 16
         st = dalloc(n, (void **)&n->dh_tile, (size_t)max_batch * ((H + 15) / 16) * (W / 16) * sizeof(double));
     if (st == SW_OK) st = dalloc(n, (void **)&n->active, (size_t)max_batch * 4);
@@ -460,7 +465,8 @@ sw_status enqueue_rollout(sw_net *n, sw_batch *solver, const SwBatchInfo &bi, in
             int th = 0, tw = 0;
             sw_net_fused_tile(B, n->H, n->W, &th, &tw);
             SHIP(sw_sur_apply(n->delta, n->dh_tile, ((n->H + th - 1) / th) * (n->W / tw), bi.d_grids, cur, B, n->H,
-                              n->W, n->nrm, gate->project_mass, bi.bc_x, bi.bc_y, n->stats, s));
+                              n->W, n->nrm, gate->project_mass, bi.bc_x, bi.bc_y, n->stats, n->apply_part,
+                              n->apply_ticket, s));
             cur ^= 1;
             if ((st = (sw_status)sw_batch_internal_set_cur(solver, cur)) != SW_OK) return st;
             const SwFallbackGate fg{n->stats, gate->mass_rel_tol, gate->hmin, fallbacks};
@@ -471,7 +477,7 @@ sw_status enqueue_rollout(sw_net *n, sw_batch *solver, const SwBatchInfo &bi, in
         const RolloutInput in{bi.d_grids, cur, gate->project_mass != 0};
         if ((st = forward(n, B, false, s, &in)) != SW_OK) return st;
         SHIP(sw_sur_apply(n->delta, n->dh_part, n->H * (n->W / 64), bi.d_grids, cur, B, n->H, n->W, n->nrm,
-                          gate->project_mass, bi.bc_x, bi.bc_y, n->stats, s));
+                          gate->project_mass, bi.bc_x, bi.bc_y, n->stats, n->apply_part, n->apply_ticket, s));
         // the gate; rejected grids: U^n over the prediction, then the plain solver takes the jump (an
         // even number of steps, so it ends where it started); accepted grids keep the prediction
         SHIP(sw_sur_gate_restore(bi.d_grids, cur, B, n->H, n->W, n->stats, gate->mass_rel_tol, gate->hmin, n->active,

@@ -339,10 +339,43 @@ __global__ void k_relayout(const float *master, const SwLayerDesc *layers, int n
 // same value).
 __global__ __launch_bounds__(256) void k_apply(const float *delta, const double *dh_part, int nparts,
                                                const SwBatchGrid *grids, int cur, int H, int W, SwNorm nrm, int project,
-                                               int bcx, int bcy, SwGateStats *st) {
+                                               int bcx, int bcy, SwGateStats *st, SwApplyPart *part,
+                                               unsigned *ticket) {
     const int b = blockIdx.y;
     const SwBatchGrid &g = grids[b];
     const int64_t n = (int64_t)H * W;
+    const float *U[3] = {(const float *)g.plane[cur][0], (const float *)g.plane[cur][1], (const float *)g.plane[cur][2]};
+    float *O[3] = {(float *)g.plane[cur ^ 1][0], (float *)g.plane[cur ^ 1][1], (float *)g.plane[cur ^ 1][2]};
+    // a thread's pixels in pairs, a pair's loads issued together (the first
+    // pair's before the projection's sum, which they do not need)
+    struct Px {
+        float4 d;
+        float h, hu, hv;
+        int x, y;
+        int64_t off;
+        bool live;
+    };
+    auto fetch = [&](int64_t q, Px &v) {
+        v.live = q < n;
+        if (!v.live) return;
+        if (n <= 0x7fffffff) {
+            v.y = (int)q / W;
+            v.x = (int)q - v.y * W;
+        } else {
+            v.y = (int)(q / W);
+            v.x = (int)(q - (int64_t)v.y * W);
+        }
+        v.off = (int64_t)v.y * g.pitch + v.x;
+        v.d = *reinterpret_cast<const float4 *>(delta + ((int64_t)b * n + q) * 4);
+        v.h = U[0][v.off];
+        v.hu = U[1][v.off];
+        v.hv = U[2][v.off];
+    };
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    Px pa, pb;
+    fetch(p, pa);
+    fetch(p + stride, pb);
     float dh_mean = 0.f;
     if (project) {
         __shared__ double s_part[4];
@@ -354,35 +387,46 @@ __global__ __launch_bounds__(256) void k_apply(const float *delta, const double 
         __syncthreads();
         dh_mean = (float)(((s_part[0] + s_part[1]) + (s_part[2] + s_part[3])) / (double)n);
     }
-    const float *U[3] = {(const float *)g.plane[cur][0], (const float *)g.plane[cur][1], (const float *)g.plane[cur][2]};
-    float *O[3] = {(float *)g.plane[cur ^ 1][0], (float *)g.plane[cur ^ 1][1], (float *)g.plane[cur ^ 1][2]};
     double mo = 0.0, mn = 0.0;
     float hmin = 3.0e38f;
     bool bad = false;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
-        const int64_t off = (int64_t)y * g.pitch + x;
-        const float4 d = *reinterpret_cast<const float4 *>(delta + ((int64_t)b * n + p) * 4);
-        const float h = U[0][off], hu = U[1][off], hv = U[2][off];
-        U3<float> c = {h + (d.x - dh_mean) * nrm.out_scale[0], hu + d.y * nrm.out_scale[1], hv + d.z * nrm.out_scale[2]};
-        O[0][off] = c.h;
-        O[1][off] = c.p;
-        O[2][off] = c.q;
-        if (x == 0 || x == W - 1 || y == 0 || y == H - 1) write_ghosts(O, g.pitch, W, H, bcx, bcy, x, y, c);
-        mo += h;
+    auto emit = [&](const Px &v) {
+        U3<float> c = {v.h + (v.d.x - dh_mean) * nrm.out_scale[0], v.hu + v.d.y * nrm.out_scale[1],
+                       v.hv + v.d.z * nrm.out_scale[2]};
+        O[0][v.off] = c.h;
+        O[1][v.off] = c.p;
+        O[2][v.off] = c.q;
+        if (v.x == 0 || v.x == W - 1 || v.y == 0 || v.y == H - 1) write_ghosts(O, g.pitch, W, H, bcx, bcy, v.x, v.y, c);
+        mo += v.h;
         mn += c.h;
         hmin = fminf(hmin, c.h);
         bad |= !(fabsf(c.h) <= 3.0e38f) || !(fabsf(c.p) <= 3.0e38f) || !(fabsf(c.q) <= 3.0e38f);
+    };
+    while (pa.live) {
+        emit(pa);
+        if (!pb.live) break;
+        emit(pb);
+        p += 2 * stride;
+        fetch(p, pa);
+        fetch(p + stride, pb);
     }
     mo = wave_sum_d(mo);
     mn = wave_sum_d(mn);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) hmin = fminf(hmin, __shfl_xor(hmin, o));
     const unsigned long long anybad = __ballot(bad);
-    // the four waves' partial results meet in LDS: one set of atomics per block
+    // The four waves' partial results meet in LDS; each block then publishes
+    // its partials in its own slot with device-scope atomic exchanges
+    // (performed where every XCD sees them) and takes a ticket; the block
+    // with the last ticket sums the slots in block order and writes the
+    // grid's statistics, then clears the ticket.  Per grid that is one
+    // contended atomic per block, where atomics on the statistics themselves
+    // (four per block, one cache line) serialised into microseconds for the
+    // few grids of a small batch.
     __shared__ double s_mo[4], s_mn[4];
     __shared__ float s_hmin[4];
     __shared__ int s_bad[4];
+    __shared__ int s_last;
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         s_mo[w] = mo;
@@ -391,13 +435,55 @@ __global__ __launch_bounds__(256) void k_apply(const float *delta, const double 
         s_bad[w] = anybad != 0;
     }
     __syncthreads();
+    const unsigned nb = gridDim.x;
+    SwApplyPart *P = part + (int64_t)b * nb;
     if (threadIdx.x == 0) {
-        atomicAdd(&st[b].mass_old, (s_mo[0] + s_mo[1]) + (s_mo[2] + s_mo[3]));
-        atomicAdd(&st[b].mass_new, (s_mn[0] + s_mn[1]) + (s_mn[2] + s_mn[3]));
+        const double bmo = (s_mo[0] + s_mo[1]) + (s_mo[2] + s_mo[3]);
+        const double bmn = (s_mn[0] + s_mn[1]) + (s_mn[2] + s_mn[3]);
         const float hm = fminf(fminf(s_hmin[0], s_hmin[1]), fminf(s_hmin[2], s_hmin[3]));
-        // min over non-negative values by integer order; a non-positive depth is recorded as 0
-        atomicMin(reinterpret_cast<int *>(&st[b].hmin), __float_as_int(hm > 0.f ? hm : 0.f));
-        if (s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3]) atomicOr(&st[b].nonfinite, 1u);
+        const unsigned bd = (unsigned)(s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3]);
+        unsigned long long r = atomicExch(&P[blockIdx.x].mo, (unsigned long long)__double_as_longlong(bmo));
+        r ^= atomicExch(&P[blockIdx.x].mn, (unsigned long long)__double_as_longlong(bmn));
+        r ^= atomicExch(&P[blockIdx.x].hmin_bad, ((unsigned long long)__float_as_uint(hm) << 32) | bd);
+        // the exchanges have returned (so are performed) before the ticket is taken
+        asm volatile("" : "+v"(r)::"memory");
+        const unsigned t = atomicAdd(&ticket[b], 1u);
+        s_last = t == nb - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;                              // uniform per block
+    // every block's slot is published: per thread a strided run of slots in
+    // block order, then the waves and the block in a fixed order
+    double tmo = 0.0, tmn = 0.0;
+    float thm = 3.0e38f;
+    unsigned tbad = 0u;
+    for (unsigned k = threadIdx.x; k < nb; k += blockDim.x) {
+        tmo += __longlong_as_double((long long)atomicAdd(&P[k].mo, 0ull));
+        tmn += __longlong_as_double((long long)atomicAdd(&P[k].mn, 0ull));
+        const unsigned long long hb = atomicAdd(&P[k].hmin_bad, 0ull);
+        thm = fminf(thm, __uint_as_float((unsigned)(hb >> 32)));
+        tbad |= (unsigned)hb;
+    }
+    tmo = wave_sum_d(tmo);
+    tmn = wave_sum_d(tmn);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) thm = fminf(thm, __shfl_xor(thm, o));
+    const unsigned long long wbad = __ballot(tbad != 0u);
+    __syncthreads();                                  // the LDS slots are reused
+    if ((threadIdx.x & 63) == 0) {
+        s_mo[w] = tmo;
+        s_mn[w] = tmn;
+        s_hmin[w] = thm;
+        s_bad[w] = wbad != 0ull;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st[b].mass_old = (s_mo[0] + s_mo[1]) + (s_mo[2] + s_mo[3]);
+        st[b].mass_new = (s_mn[0] + s_mn[1]) + (s_mn[2] + s_mn[3]);
+        const float hm = fminf(fminf(s_hmin[0], s_hmin[1]), fminf(s_hmin[2], s_hmin[3]));
+        st[b].hmin = hm > 0.f ? hm : 0.f;             // a non-positive depth is recorded as 0
+        st[b].nonfinite = (unsigned)(s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3]);
+        atomicExch(&ticket[b], 0u);                   // ready for the next launch
     }
 }
 
@@ -579,12 +665,17 @@ unsigned per_grid_blocks(int64_t n, int B) {
 }
 
 
+unsigned sw_sur_apply_slots(int64_t pixels, int B) { return per_grid_blocks(pixels, 1) * (unsigned)B; }
+
 hipError_t sw_sur_apply(const float *delta, const double *dh_part, int nparts, const SwBatchGrid *grids, int cur,
                         int B, int H, int W, SwNorm nrm, int project, int bcx, int bcy, SwGateStats *st,
-                        hipStream_t s) {
+                        SwApplyPart *part, unsigned *ticket, hipStream_t s) {
     if (project && (!dh_part || nparts < 1)) return hipErrorInvalidValue;
-    dim3 grid(per_grid_blocks((int64_t)H * W, B), B);
-    k_apply<<<grid, 256, 0, s>>>(delta, dh_part, nparts, grids, cur, H, W, nrm, project, bcx, bcy, st);
+    if (!part || !ticket) return hipErrorInvalidValue;
+    // at most 128 blocks per grid (two pixels per thread on a 256^2 grid):
+    // the blocks of one grid meet on its ticket
+    dim3 grid(std::min(per_grid_blocks((int64_t)H * W, B), 128u), B);
+    k_apply<<<grid, 256, 0, s>>>(delta, dh_part, nparts, grids, cur, H, W, nrm, project, bcx, bcy, st, part, ticket);
     return hipGetLastError();
 }
 
