@@ -16,6 +16,7 @@
 // n + 16 * (k / 8), element k % 8; D[m][n] in lane n + 16 * (m / 4), element
 // m % 4.
 #include "sw_conv.h"
+#include "sw_dma.h"
 
 #include <algorithm>
 
@@ -295,38 +296,6 @@ int sw_device_cus() {
 namespace {
 
 constexpr int kDmaRows = 8;   // tile height of the LDS DMA kernel
-
-// LDS byte address of a __shared__ object.
-__device__ __forceinline__ unsigned lds_addr(const void *p) {
-    return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
-}
-
-// One LDS DMA instruction (global_load_lds_dwordx4): lane l's 16 bytes at
-// base + off (off in bytes, per lane) go to LDS byte address lds + 16 l.
-// Asynchronous and counted in vmcnt like a load; written as asm so that the
-// compiler, which does not see the LDS write, does not wait for it before
-// every LDS read: the kernel waits for it itself.
-__device__ __forceinline__ void lds_dma16(const void *base, unsigned off, unsigned lds) {
-    // (one wait state between the M0 write and its use by the DMA)
-    asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1" ::"v"(off), "s"(base), "s"(lds)
-                 : "memory", "m0");
-}
-
-// Wait until at most n vector memory operations of this wave are
-// outstanding (n wave-uniform; values above K wait for K).  Vector memory
-// operations complete in issue order, so this leaves exactly the n newest
-// in flight.
-template <int K> __device__ __forceinline__ void wait_vm_upto(int n) {
-    if constexpr (K > 0) {
-        if (n >= K) {
-            asm volatile("s_waitcnt vmcnt(%0)" ::"n"(K) : "memory");
-            return;
-        }
-        wait_vm_upto<K - 1>(n);
-    } else {
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    }
-}
 
 // The forward 32-channel modes (residual block, output layer) with the
 // input tiles brought in by LDS DMA, three buffers deep: while tile t is

@@ -3,6 +3,8 @@
 // re-layout, and the gated rollout (apply, gate statistics, accept).
 #include <algorithm>
 
+#include "sw_dma.h"
+
 #include "sw_common.h"
 #include "sw_conv.h"
 
@@ -274,6 +276,200 @@ __global__ __launch_bounds__(CINP == 32 ? 384 : 192) void k_wgrad(const __bf16 *
                 if (cc < cin) P[(co * 9 + tap) * cin + cc] = acc[mb][tt][q];
             }
             if (w == 0 && n == 0) P[cout * 9 * cin + co] = accb[mb][q];
+        }
+}
+
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+
+// Offset (BF16 elements) of 16-byte chunk c (channels 8c .. 8c + 7) of pixel
+// p in a pixel-major 32-channel LDS tile.  The chunk index is XORed with
+// pixel bits 1-2 (the same chunk of 8 consecutive pixels covers all bank
+// quads) and with pixel bit 3 into chunk bit 1 (a transposing read takes two
+// chunks of pixels p .. p + 3 and p + 8 .. p + 11 in one pass; they then fall
+// on disjoint banks).
+__device__ __forceinline__ int wg_chunk(int p, int c) {
+    return p * 32 + ((c ^ ((p >> 1) & 3) ^ ((p >> 2) & 2)) << 3);
+}
+
+// Channel-major read of a pixel-major tile with ds_read_b64_tr_b16 (gfx950):
+// within each group of 16 lanes, lane i reads 4 16-bit elements and lane j
+// receives element (j & 3) of the reads of lanes 4 e + (j >> 2), e = 0..3
+// (probed on MI355X).  With lane i reading channels c0 + 4 (i & 3) .. + 3 of
+// pixel p0 + (i >> 2), lane j of the group receives channel c0 + j of pixels
+// p0 .. p0 + 3.  Two reads give the 8 consecutive pixels of one channel that
+// an MFMA operand lane holds (i: the lane's index in its group).
+__device__ __forceinline__ bf16x8 wg_pixels8(const __bf16 *tile, int p0, int c0, int i) {
+    const int ch = c0 + 4 * (i & 3);
+    const __bf16 *lo = tile + wg_chunk(p0 + (i >> 2), ch >> 3) + (ch & 7);
+    const __bf16 *hi = tile + wg_chunk(p0 + 4 + (i >> 2), ch >> 3) + (ch & 7);
+    const i16x4 x = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) i16x4 *)lo);
+    const i16x4 y = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) i16x4 *)hi);
+    const i16x4 v[2] = {x, y};
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+// Weight gradient of a 32 -> 32 layer: k_wgrad's tile walk and MFMA
+// operands for 32 channels, with the tiles brought in by LDS DMA,
+// pixel-major as they lie in HBM, three buffers deep (two tiles' loads in
+// flight while one is computed; one workgroup per CU, the buffers fill 123 KB
+// of LDS), and the operands read channel-major with transposing LDS reads
+// instead of staged transposed.  12 waves: wave w takes input row dy = u / 2
+// and channel half u % 2 (u = w % 6) of the K steps over pixel half w / 6 of
+// each tile row (three waves per SIMD hide each other's LDS latency); the
+// two halves' sums meet in LDS at the end.  A tile's 16-byte slots: dZ (4 x
+// 64 pixels) then the input (6 x 66 pixels, padded to whole DMA
+// instructions; padding lanes reload a slot of the window and land past its
+// end); slot s holds chunk (s & 3) ^ swizzle of pixel s >> 2 (wg_chunk).  dZ
+// rows below the image (the last tile row of an image whose height is not a
+// multiple of 4) are loaded from its last row and their K steps skipped;
+// input rows below the bottom halo row feed only those steps.  The loop
+// issues no vector memory operation other than the DMA, so waiting for all
+// but the newest tile's DMA instructions leaves exactly that tile in flight.
+__global__ __launch_bounds__(768) void k_wgrad_dma(const __bf16 *dz, const __bf16 *a, int cout, int cin, int H, int W,
+                                                    int tiles_y, int tiles_x, int ntiles, float *partial, int nent) {
+    constexpr int NWV = 12, MB = 2, NT = 3;
+    constexpr int DZ_SLOTS = kWgRows * kWgCols * 4;
+    constexpr int A_SLOTS = (kWgRows + 2) * (kWgCols + 2) * 4;
+    constexpr int DZ_NI = DZ_SLOTS / 64;
+    constexpr int A_NI = (A_SLOTS + 63) / 64;
+    constexpr int NI = DZ_NI + A_NI;                 // DMA instructions per tile
+    constexpr int BUF = NI * 64 * 8;                 // bf16 per buffer
+    constexpr int PERW = (NI + NWV - 1) / NWV;       // most instructions of one wave
+    constexpr int NBUF = 3;
+    constexpr int NACC = MB * NT * 4 + MB * 4;       // a lane's sums (with the bias's)
+    static_assert(6 * 64 * NACC * 4 <= NBUF * BUF * 2, "the halves' sums fit the tile buffers");
+    __shared__ __attribute__((aligned(16))) __bf16 tiles[NBUF][BUF];
+
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int n = lane & 15, kg = lane >> 4;
+    const int u = w % 6, half = w / 6;
+    const int dy = u >> 1, chalf = u & 1;
+    const bool bias_wave = u == 0;
+    const int Wp = W + 2;
+    const int per_block = (ntiles + gridDim.x - 1) / gridDim.x;
+    const int t0 = blockIdx.x * per_block, t1 = min(ntiles, t0 + per_block);
+    const u32x4 ones = {0x3F803F80u, 0x3F803F80u, 0x3F803F80u, 0x3F803F80u};   // bf16 1.0 pairs
+
+    f32x4 acc[MB][NT], accb[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+        accb[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[mb][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+
+    // this wave's DMA instructions i = w + 12 k (k < nw): per lane the slot's
+    // byte offset from its window's first pixel, and its window row
+    const int nw = (NI - w + NWV - 1) / NWV;
+    unsigned soff[PERW];
+    int srow[PERW];
+#pragma unroll
+    for (int k = 0; k < PERW; ++k) {
+        const int i = w + NWV * k;
+        const bool isdz = i < DZ_NI;
+        const int cols = isdz ? kWgCols : kWgCols + 2;
+        int sl = (isdz ? i : i - DZ_NI) * 64 + lane;
+        if (!isdz && sl >= A_SLOTS) sl = lane;
+        const int p = sl >> 2, c = (sl & 3) ^ ((p >> 1) & 3) ^ ((p >> 2) & 2);
+        const int row = p / cols, col = p - row * cols;
+        soff[k] = (unsigned)(((row * Wp + col) * 32 + c * 8) * 2);
+        srow[k] = row;
+    }
+    const unsigned lds0 = lds_addr(&tiles[0][0]);
+    auto issue = [&](int t, int buf) {
+        const int b = t / (tiles_y * tiles_x);
+        const int r = t - b * tiles_y * tiles_x;
+        const int tx = r / tiles_y, ty = r - tx * tiles_y;   // column-major: the next tile is the one below
+        const char *zb = (const char *)(dz + ((((int64_t)b * (H + 2) + ty * kWgRows + 1) * Wp + tx * kWgCols + 1) * 32));
+        const char *ab = (const char *)(a + ((((int64_t)b * (H + 2) + ty * kWgRows) * Wp + tx * kWgCols) * 32));
+        const int rz = H - 1 - ty * kWgRows, ra = H + 1 - ty * kWgRows;   // last window rows inside the image
+        const unsigned l0 = lds0 + (unsigned)(buf * BUF * 2);
+#pragma unroll
+        for (int k = 0; k < PERW; ++k) {
+            if (k < nw) {
+                const int i = w + NWV * k;
+                const bool isdz = i < DZ_NI;
+                const int rm = isdz ? rz : ra;
+                const unsigned off = srow[k] > rm ? soff[k] - (unsigned)((srow[k] - rm) * Wp * 64) : soff[k];
+                lds_dma16(isdz ? zb : ab, off, l0 + (unsigned)(i * 1024));
+            }
+        }
+    };
+
+    if (t0 < t1) {
+        issue(t0, 0);
+        if (t0 + 1 < t1) issue(t0 + 1, 1);
+        wait_vm_upto<PERW>(t0 + 1 < t1 ? nw : 0);      // tile t0 has landed
+    }
+    __syncthreads();
+    for (int t = t0; t < t1; ++t) {
+        const int buf = (t - t0) % NBUF;
+        if (t + 2 < t1) issue(t + 2, (t - t0 + 2) % NBUF);   // its buffer was last read before the barrier
+        const int r0 = t - (t / (tiles_y * tiles_x)) * tiles_y * tiles_x;
+        const int ty = r0 - (r0 / tiles_y) * tiles_y;
+        const int rows = min(kWgRows, H - ty * kWgRows);
+        const __bf16 *DZ = tiles[buf];
+        const __bf16 *AT = tiles[buf] + DZ_SLOTS * 8;
+#pragma unroll
+        for (int r = 0; r < kWgRows; ++r) {
+            if (r >= rows) break;
+            const int j0 = half * 32 + 8 * kg;
+            bf16x8 aop[MB], bop[NT];
+            // dZ: channel mb * 16 + n of pixels j0 .. j0 + 7 of row r; the
+            // input: channel 16 chalf + n of staged pixels j0 + dx .. + 7 of row r + dy
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) aop[mb] = wg_pixels8(DZ, r * kWgCols + j0, mb * 16, n);
+#pragma unroll
+            for (int dx = 0; dx < NT; ++dx) bop[dx] = wg_pixels8(AT, (r + dy) * (kWgCols + 2) + j0 + dx, chalf * 16, n);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+                for (int tt = 0; tt < NT; ++tt)
+                    acc[mb][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop[mb], bop[tt], acc[mb][tt], 0, 0, 0);
+                if (bias_wave)
+                    accb[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop[mb], as_bf16x8(ones), accb[mb], 0, 0, 0);
+            }
+        }
+        if (t + 1 < t1) wait_vm_upto<PERW>(t + 2 < t1 ? nw : 0);   // tile t + 1 has landed
+        __syncthreads();
+    }
+    // the second pixel half's sums join the first's (the tile buffers are free)
+    float *X = reinterpret_cast<float *>(&tiles[0][0]) + (u * 64 + lane) * NACC;
+    if (half == 1) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+            for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) X[(mb * NT + tt) * 4 + q] = acc[mb][tt][q];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) X[MB * NT * 4 + mb * 4 + q] = accb[mb][q];
+        }
+    }
+    __syncthreads();
+    if (half == 1) return;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[mb][tt][q] += X[(mb * NT + tt) * 4 + q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) accb[mb][q] += X[MB * NT * 4 + mb * 4 + q];
+    }
+    // D[m][n] in lane n + 16 (m / 4), element m % 4
+    float *P = partial + (int64_t)blockIdx.x * nent;
+    const int ci = chalf * 16 + n;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int co = mb * 16 + 4 * kg + q;
+            if (co >= cout) continue;
+#pragma unroll
+            for (int tt = 0; tt < NT; ++tt)
+                if (ci < cin) P[(co * 9 + 3 * dy + tt) * cin + ci] = acc[mb][tt][q];
+            if (bias_wave && n == 0) P[cout * 9 * cin + co] = accb[mb][q];
         }
 }
 
@@ -625,6 +821,17 @@ hipError_t launch_wgrad(const __bf16 *dz, const __bf16 *a, int cout, int cin, in
     return hipGetLastError();
 }
 
+hipError_t launch_wgrad_dma(const __bf16 *dz, const __bf16 *a, int cout, int cin, int B, int H, int W, float *partial,
+                            int maxblocks, int nent, int *used, hipStream_t s) {
+    const int tiles_y = (H + kWgRows - 1) / kWgRows, tiles_x = W / kWgCols;
+    const int64_t ntiles = (int64_t)B * tiles_y * tiles_x;
+    if (ntiles > (int64_t)1 << 30) return hipErrorInvalidValue;
+    const int nb = (int)std::min<int64_t>({ntiles, (int64_t)sw_device_cus(), (int64_t)maxblocks});   // one per CU (LDS)
+    k_wgrad_dma<<<nb, 768, 0, s>>>(dz, a, cout, cin, H, W, tiles_y, tiles_x, (int)ntiles, partial, nent);
+    *used = nb;
+    return hipGetLastError();
+}
+
 hipError_t sw_sur_wgrad(const void *dzv, int coutp, int cout, const void *av, int cinp, int cin, int B, int H, int W,
                         float *partial, int nblocks, float *grad_w, float *grad_b, hipStream_t s) {
     if (W % kWgCols != 0 || nblocks < 1 || cout > coutp || cin > cinp) return hipErrorInvalidValue;
@@ -633,7 +840,7 @@ hipError_t sw_sur_wgrad(const void *dzv, int coutp, int cout, const void *av, in
     int used = 0;
     hipError_t e;
     if (cinp == 32 && coutp == 32)
-        e = launch_wgrad<32, 32>(dz, a, cout, cin, B, H, W, partial, nblocks, nent, &used, s);
+        e = launch_wgrad_dma(dz, a, cout, cin, B, H, W, partial, nblocks, nent, &used, s);
     else if (cinp == 8 && coutp == 32)
         e = launch_wgrad<8, 32>(dz, a, cout, cin, B, H, W, partial, nblocks, nent, &used, s);
     else if (cinp == 32 && coutp == 8)
