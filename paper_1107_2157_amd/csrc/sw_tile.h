@@ -181,9 +181,18 @@ __device__ __forceinline__ void fused_tile_dir(const TileArgs &t, DtFn &&dt_of, 
         // Edge loads: lanes 0..31 read the column left of the strip, lanes
         // 32..63 the column right of it (two addresses per instruction);
         // lane 0 and lane 63 use them.  Past the right end of the grid the
-        // right edge is never needed and reads the left one instead.
+        // right edge is never needed and reads the left one instead.  At a
+        // wall the ghost column holds the image of an interior column (the
+        // boundary rule, refreshed before every step): the load reads that
+        // column instead, whose line the interior loads share (the ghost's
+        // line holds nothing else a tile reads), and a reflective wall's hu is
+        // negated where the value is used (esign).  Same values, fewer lines.
         const bool right_ok = c0 + W <= nx;
-        const unsigned ec = (lane < 32 || !right_ok) ? (unsigned)c0 : (unsigned)(c0 + W + 1);   // column + 1
+        const bool left_lane = lane < 32 || !right_ok;
+        const bool wall = left_lane ? s == 0 : c0 + W == nx;
+        unsigned ec = left_lane ? (unsigned)c0 : (unsigned)(c0 + W + 1);   // column + 1
+        if (wall) ec = (left_lane == (t.bc_x == 0)) ? 1u : (unsigned)nx;   // column 0 or nx - 1
+        const T esign = wall && t.bc_x == 0 ? T(-1) : T(1);
         // Lanes past the end of the row read the strip's first vector; their
         // cells are never stored and never enter the CFL max.  All loads are
         // unconditional (rows past the tile are clamped to its last row) so
@@ -306,12 +315,13 @@ __device__ __forceinline__ void fused_tile_dir(const TileArgs &t, DtFn &&dt_of, 
             // just outside the strip
             T E[3];
             {
+                const T e1 = e[1] * esign;
                 T r = fast_rcp(e[0]);
-                T u = e[1] * r;
-                T fp = fma(k * e[0], e[0], e[1] * u);
+                T u = e1 * r;
+                T fp = fma(k * e[0], e[0], e1 * u);
                 T fq = e[2] * u;
-                E[0] = fma(elx, e[1], T(0.5) * e[0]);
-                E[1] = fma(elx, fp, T(0.5) * e[1]);
+                E[0] = fma(elx, e1, T(0.5) * e[0]);
+                E[1] = fma(elx, fp, T(0.5) * e1);
                 E[2] = fma(elx, fq, T(0.5) * e[2]);
             }
             T fl[3], fr[3];
