@@ -176,7 +176,15 @@ __device__ __forceinline__ void fused_tile_dir(const TileArgs &t, DtFn &&dt_of, 
     {
         const int c0 = s * W, j0 = rb * rows, j1 = min(j0 + rows, ny);
         const unsigned c = (unsigned)(c0 + VEC * lane);
-        const bool in_row = (int)c <= nx;                    // the vector stays inside the row's allocation
+        // At a reflective right wall whose ghost column starts a lane's vector
+        // (nx a multiple of VEC, the strip ragged) that vector holds only the
+        // ghost and row padding: the lane loads the strip's first vector
+        // instead, and the wall cell's right neighbour is formed from the
+        // cell itself (its mirror image: L with the hu part negated, exactly
+        // what the ghost gives).
+        const bool ghost_lane = t.bc_x == 0 && (int)c == nx;
+        const bool rwall = t.bc_x == 0 && (int)c + VEC == nx;   // the lane's last cell is nx - 1
+        const bool in_row = (int)c <= nx && !ghost_lane;     // the vector stays inside the row's allocation
         const bool full = (int)c + VEC <= nx;                // all VEC cells are interior
         // Edge loads: lanes 0..31 read the column left of the strip, lanes
         // 32..63 the column right of it (two addresses per instruction);
@@ -340,6 +348,11 @@ __device__ __forceinline__ void fused_tile_dir(const TileArgs &t, DtFn &&dt_of, 
                     T Rp[3];
 #pragma unroll
                     for (int kk = 0; kk < 3; ++kk) Rp[kk] = from_next_lane(R[kk][0], E[kk]);
+                    if (rwall) {
+                        Rp[0] = L[0][m];
+                        Rp[1] = -L[1][m];
+                        Rp[2] = L[2][m];
+                    }
                     xface_flux<T>(L[0][m] + Rp[0], L[1][m] + Rp[1], L[2][m] + Rp[2], k, fr);
                 }
 #pragma unroll
