@@ -138,6 +138,7 @@ SwLaunch launch_of(const sw_ctx *ctx, const sw_state *st, int from) {
     a.dtype = (int32_t)ctx->opts.dtype;
     a.sc = ctx->sc;
     a.step = 0;
+    a.ghosts = 1;
     return a;
 }
 
@@ -231,9 +232,17 @@ sw_status enqueue_steps(sw_ctx *ctx, const sw_state *state, int nsteps, const Sw
         single.pd = 2;
         single.order = 0;
     }
+    // With reflective walls on both axes and the width a multiple of the
+    // cells per lane, the paper's scheme reads no ghost cell (the walls'
+    // images are formed from the edge cells; a width that is not a multiple
+    // puts the right ghost inside a lane's vector, which is read), so only
+    // the call's last step writes them.
+    const bool ghost_free = ctx->opts.scheme == SW_SCHEME_PAPER && ctx->opts.bc_x == SW_BC_REFLECT &&
+                            ctx->opts.bc_y == SW_BC_REFLECT && single.vec > 0 && ctx->grid.nx % single.vec == 0;
     for (; n < nsteps; ++n) {
         SwLaunch b = launch_of(ctx, state, cur);
         b.step = n;
+        b.ghosts = ghost_free && n + 1 < nsteps ? 0 : 1;
         SW_HIP(sw_launch_step(b, single, s));
         cur ^= 1;
     }

@@ -165,6 +165,7 @@ SwBatchLaunch launch_of(const sw_batch *b, const Resolved &r, int cur, int step)
     a.bc_y = (int)b->opts.bc_y;
     a.dtype = (int)b->opts.dtype;
     a.scheme = (int)b->opts.scheme;
+    a.ghosts = 1;
     return a;
 }
 
@@ -176,9 +177,17 @@ sw_status enqueue(const sw_batch *b, const Resolved &r, int nsteps, int cur, hip
     SwBatchLaunch p = launch_of(b, r, cur, 0);
     p.active = active;
     BHIP(sw_batch_launch_prologue(p, r.vec, s));
+    // With reflective walls on both axes and every grid's width a multiple
+    // of the cells per lane, the paper's scheme reads no ghost cell (the
+    // walls' images are formed from the edge cells; a width that is not a
+    // multiple puts the right ghost inside a lane's vector, which is read),
+    // so only the call's last step writes them.
+    bool ghost_free = b->opts.scheme == SW_SCHEME_PAPER && b->opts.bc_x == SW_BC_REFLECT && b->opts.bc_y == SW_BC_REFLECT;
+    for (int i = 0; i < b->n && ghost_free; ++i) ghost_free = b->grids[i].nx % r.vec == 0;
     for (int k = 0; k < nsteps; ++k) {
         SwBatchLaunch a = launch_of(b, r, cur, k);
         a.active = active;
+        a.ghosts = ghost_free && k + 1 < nsteps ? 0 : 1;
         BHIP(sw_batch_launch_step(a, r.vec, r.minw, r.pd, r.order == 2, s));
         cur ^= 1;
     }

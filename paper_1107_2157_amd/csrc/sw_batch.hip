@@ -72,6 +72,7 @@ __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_batch_step(SwBat
     t.s = tt.s;
     t.rb = tt.rb;
     t.rows = a.rows;
+    t.ghosts = a.ghosts;
     T smax = T(0);
     bool bad = false;
     double dt = 0.0;
@@ -136,6 +137,7 @@ __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_batch_step_pers(
         ta.s = tt.s;
         ta.rb = tt.rb;
         ta.rows = a.rows;
+        ta.ghosts = a.ghosts;
         double dt = 0.0;
         const double dtg = dt_grid;
         if constexpr (TR)

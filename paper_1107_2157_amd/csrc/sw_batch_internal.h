@@ -46,6 +46,7 @@ struct SwBatchLaunch {
     double g, dx, dy, cfl, dt_fixed;
     int32_t bc_x, bc_y, dtype, scheme;   // scheme: 0 paper, 1 transverse
     const int32_t *active;   // optional per-grid mask: grids with 0 are skipped entirely
+    int32_t ghosts;          // 0: the step leaves the ghost cells unwritten (TileArgs::ghosts)
 };
 
 // Gate statistics of a surrogate jump, per grid: mass before and after, the

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256, (MINW > 0 ? MINW : 1)) void k_step_fused(SwLau
         for (int kk = 0; kk < 3; ++kk) { t.in[kk] = a.in[kk]; t.out[kk] = a.out[kk]; }
         t.pitch = a.pitch;
         t.nx = a.nx; t.ny = a.ny; t.bc_x = a.bc_x; t.bc_y = a.bc_y;
-        t.s = s; t.rb = rb; t.rows = rows;
+        t.s = s; t.rb = rb; t.rows = rows; t.ghosts = a.ghosts;
         if constexpr (TR)
             fused_tile_tr<T, VEC, PD>(t, [&] { return step_dt_finish(a, stripe); }, a.g, a.dx, a.dy, smax, bad, dt);
         else

@@ -34,6 +34,7 @@ struct SwLaunch {
     int32_t dtype;            // 0 f32, 1 f64
     SwScalars *sc;
     int32_t step;             // index of this step inside the call (ring position)
+    int32_t ghosts;           // 0: the fused step leaves the ghost cells unwritten (TileArgs::ghosts)
 };
 
 hipError_t sw_launch_reset(SwScalars *sc, int clear_time, hipStream_t s);

@@ -115,6 +115,7 @@ extern "C" sw_status sw_step_noalloc(sw_grid grid, sw_halo halo, double g, doubl
         a.dtype = (int32_t)o.dtype;
         a.sc = sc;
         a.step = step;
+        a.ghosts = 1;
         return a;
     };
 #define NA_HIP(call)                                                                              \

@@ -160,6 +160,10 @@ struct TileArgs {
     int64_t pitch;
     int nx, ny, bc_x, bc_y;
     int s, rb, rows;
+    // 0: leave the ghost cells of t.out unwritten (a step whose successor in
+    // the same launch sequence reads no ghost: reflective walls on both axes
+    // and the paper's scheme); the last step of a call writes them
+    int ghosts = 1;
 };
 
 template <typename T, int VEC, int PD, bool DOWN, typename DtFn>
@@ -207,7 +211,7 @@ __device__ __forceinline__ void fused_tile_dir(const TileArgs &t, DtFn &&dt_of, 
         // that the compiler can count the loads in flight exactly and keep
         // the prefetched rows outstanding while it computes.
         const unsigned cl = in_row ? c : (unsigned)c0;
-        const bool tile_at_wall = s == 0 || c0 + W >= nx || j0 == 0 || j1 >= ny;
+        const bool tile_at_wall = t.ghosts && (s == 0 || c0 + W >= nx || j0 == 0 || j1 >= ny);
         T *O[3] = {(T *)t.out[0], (T *)t.out[1], (T *)t.out[2]};
         // Descriptors of this tile: they start at cell (-1, j0 - 1) and span
         // rows j0 - 1 .. j1; a row's byte offset is (j - j0 + 1) * pitch * size.
@@ -224,7 +228,13 @@ __device__ __forceinline__ void fused_tile_dir(const TileArgs &t, DtFn &&dt_of, 
         const unsigned eb = ec * (unsigned)sizeof(T);         // lane's edge cell (ec is column + 1)
         const unsigned sb = (c + 1) * (unsigned)sizeof(T);    // lane's store vector
 
+        // A reflective wall's ghost row (row -1 or ny) is the mirror of the
+        // edge row with hv negated: the row is loaded instead and its hv
+        // negated where the march takes it in (ymirror), so the step reads no
+        // ghost row either.
+        const bool ymirror = t.bc_y == 0;
         auto load_row = [&](int j, T h[VEC], T p[VEC], T q[VEC], T e[3]) {
+            if (ymirror) j = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
             const unsigned so = (unsigned)(j - j0 + 1) * row_bytes;
             bload<T, VEC>(rin0, lb, so, h);
             bload<T, VEC>(rin1, lb, so, p);
@@ -387,9 +397,15 @@ __device__ __forceinline__ void fused_tile_dir(const TileArgs &t, DtFn &&dt_of, 
             my = (T)(dt / dy);
             elx = lane == 0 ? lx : -lx;                      // lane 0 needs L of its edge, lane 63 needs R
         }
+        const int jfirst = rowat(0), jlast = rowat(nr + 1);   // the march's halo rows
+        if (ymirror && (jfirst < 0 || jfirst >= ny)) {
+#pragma unroll
+            for (int m = 0; m < VEC; ++m) rq[0][m] = -rq[0][m];
+        }
         row_pass(bconst<false>{}, bconst<false>{}, rh[0], rp[0], rq[0], re[0], false, 0);
         row_pass(bconst<true>{}, bconst<false>{}, rh[1 % (PD + 1)], rp[1 % (PD + 1)], rq[1 % (PD + 1)],
                  re[1 % (PD + 1)], true, 0);
+        const bool mirror_last = ymirror && (jlast < 0 || jlast >= ny);
 #pragma unroll
         for (int u = 0; u < PD; ++u) load_row(rowat(min(2 + u, nr + 1)), rh[u], rp[u], rq[u], re[u]);
         for (int ib = 0; ib < nr; ib += PD + 1) {
@@ -399,6 +415,10 @@ __device__ __forceinline__ void fused_tile_dir(const TileArgs &t, DtFn &&dt_of, 
                 if (i >= nr) break;
                 const int slot = (u + PD) % (PD + 1);
                 load_row(rowat(min(i + 2 + PD, nr + 1)), rh[slot], rp[slot], rq[slot], re[slot]);
+                if (mirror_last && i + 1 == nr) {     // the arriving row is the last halo row
+#pragma unroll
+                    for (int m = 0; m < VEC; ++m) rq[u][m] = -rq[u][m];
+                }
                 row_pass(bconst<true>{}, bconst<true>{}, rh[u], rp[u], rq[u], re[u], i + 1 < nr, rowat(i + 1));
             }
         }
