@@ -45,14 +45,16 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *base, unsigned bytes) {
 // Cache policy bits of the step's row loads and stores (buffer instruction
 // aux field: 1 = sc0, 2 = nt, 16 = sc1).  Stores are non-temporal: the new
 // state is not read again before the whole grid has been written, and
-// streaming it past the caches was measured 5-16 % faster on every workload.
-// Loads keep the default policy, so the halo rows that neighbouring tiles
-// share stay in L2 (non-temporal loads were measured 15-20 % slower).
+// streaming it past the caches was measured 5-16 % faster on every workload
+// (with sc1 as well, 0.4-1 % faster again at 4096^2 and 16384^2; sc0 alone
+// or sc1 alone was slower).  Loads keep the default policy, so the halo rows
+// that neighbouring tiles share stay in L2 (non-temporal loads were measured
+// 15-20 % slower).
 #ifndef SW_LOAD_POLICY
 #define SW_LOAD_POLICY 0
 #endif
 #ifndef SW_STORE_POLICY
-#define SW_STORE_POLICY 2
+#define SW_STORE_POLICY 18
 #endif
 
 template <typename T, int VEC> __device__ __forceinline__ void bload(rsrc_t r, unsigned vo, unsigned so, T o[VEC]);
