@@ -293,28 +293,36 @@ def paper_table1_gpu_ms():
     return out
 
 
-def run_table1(sw, ics, torch, steps=100):
+def run_table1(sw, ics, torch, tune_cache, steps=100):
     """The widths of the paper's Table 1, FP32, reflective walls, CFL 0.5,
     8 Gaussian bumps (the paper does not state its initial state): one
     sw_step(100) call (one graph launch) per width, timed whole, as the
-    paper averaged 100 iterations of its time loop; the fused kernel in its
-    default launch shape."""
+    paper averaged 100 iterations of its time loop; the fused kernel in the
+    autotuner's launch shape for the width (`ms_per_step`) and in its default
+    shape (`default_ms_per_step`)."""
     rows = []
     for n, paper_ms in paper_table1_gpu_ms().items():
         s = sw.Solver(n, n, dtype="f32")
         st = ics.bumps_state(n, n, seed=ics.SEED_BUMPS_4096, periodic=False, count=8, device=INPUT_DEVICE)
-        for _ in range(2):                         # graph capture for both buffers, warm
+
+        def call_ms():
+            for _ in range(2):                     # graph capture for both buffers, warm
+                s.state.cur = 0
+                s.set_state(*st)
+                s.step(steps)
             s.state.cur = 0
             s.set_state(*st)
-            s.step(steps)
-        s.state.cur = 0
-        s.set_state(*st)
-        s.reset_time()
-        t = timed(torch, lambda: s.step(steps))
-        s.sync_status()
-        ms = 1e3 * t / steps
+            s.reset_time()
+            t = timed(torch, lambda: s.step(steps))
+            s.sync_status()
+            return 1e3 * t / steps
+
+        default_ms = call_ms()
+        tuning = s.autotune(steps_per_trial=10, cache_path=tune_cache)
+        ms = call_ms()
         rows.append({"width": n, "ms_per_step": ms, "gcells_per_s": n * n / (ms * 1e-3) / 1e9,
-                     "paper_c2050_ms": paper_ms, "ratio_to_paper": paper_ms / ms})
+                     "paper_c2050_ms": paper_ms, "ratio_to_paper": paper_ms / ms, "tuning": tuning,
+                     "default_ms_per_step": default_ms})
         del s, st
     torch.cuda.empty_cache()
     return {"workload": "table1-widths-f32-reflect", "steps_per_call": steps, "rows": rows}
@@ -653,7 +661,7 @@ def main():
         also.append(run_batch(500, sw, ics, torch, args.tune_cache, per_grid_steps=50))
 
     if not args.no_also and args.workload == "swe16384-f32-periodic":
-        also.append(run_table1(sw, ics, torch))
+        also.append(run_table1(sw, ics, torch, args.tune_cache))
 
     if not args.no_also and not args.no_surrogate and args.workload == "swe16384-f32-periodic":
         also.append(run_surrogate(sw, ics, torch))
