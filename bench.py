@@ -293,6 +293,34 @@ def paper_table1_gpu_ms():
     return out
 
 
+def run_batch_uniform(n_grids, side, steps, sw, ics, torch, tune_cache):
+    """A batch of equal grids: n_grids of side^2 cells (the surrogate's
+    solver workload at 256 grids of 256^2), each with its own 1-8 Gaussian
+    bumps (seed 4000 + k), FP32, reflective walls, one graph launch per
+    call in the autotuner's launch shape."""
+    b = sw.Batch([side] * n_grids, dtype="f32")
+    for k in range(n_grids):
+        b.set_state(k, *ics.bumps_state(side, side, seed=ics.SEED_BATCH_GRID0 + k, periodic=False,
+                                        device=INPUT_DEVICE))
+    torch.cuda.synchronize()
+    tuning = b.autotune(steps_per_trial=3, cache_path=tune_cache)
+    b.step(2)
+    b.step(steps)
+    t = timed(torch, lambda: b.step(steps))
+    finite = True
+    try:
+        b.sync_status()
+    except sw.Unstable:
+        finite = False
+    del b
+    torch.cuda.empty_cache()
+    cells = n_grids * side * side
+    rate = cells * steps / t / 1e9
+    return {"workload": f"batch{n_grids}x{side}-f32-reflect", "grids": n_grids, "cells_per_step": cells,
+            "steps": steps, "seconds": t, "gcells_per_s": rate, "ms_per_step": 1e3 * t / steps, "tuning": tuning,
+            "finite": finite, "hbm_frac": rate * 24 / HBM_PEAK_GBS}
+
+
 def run_table1(sw, ics, torch, tune_cache, steps=100):
     """The widths of the paper's Table 1, FP32, reflective walls, CFL 0.5,
     8 Gaussian bumps (the paper does not state its initial state): one
@@ -659,6 +687,7 @@ def main():
 
     if not args.no_also and not args.no_batch and args.workload == "swe16384-f32-periodic":
         also.append(run_batch(500, sw, ics, torch, args.tune_cache, per_grid_steps=50))
+        also.append(run_batch_uniform(256, 256, 200, sw, ics, torch, args.tune_cache))
 
     if not args.no_also and args.workload == "swe16384-f32-periodic":
         also.append(run_table1(sw, ics, torch, args.tune_cache))
