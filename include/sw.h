@@ -260,10 +260,12 @@ sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per_trial, con
  * keeps its own CFL dt, simulated time and sticky flag; a grid advanced in a
  * batch is bitwise identical to the same grid advanced alone with the same
  * launch shape.  One kernel launch per time step covers every grid (a tile
- * table over all grids); sw_batch_step replays the whole call as one
- * hipGraph launch (captured on first use per (nsteps, buffer, tuning)).
+ * table over all grids; two launches per step, one per chain of grids, for
+ * batches of 8 M cells or more); sw_batch_step replays the whole call as
+ * hipGraph launches (captured on first use per (nsteps, buffer, tuning)).
  * The caller owns the arena (device memory); the library owns the tile
- * table, per-grid scalars, graphs and a capture stream. */
+ * table, per-grid scalars, graphs, a capture stream and the second chain's
+ * stream and events. */
 typedef struct sw_batch sw_batch;
 
 /* Validates every grid like sw_create (no HIP call until then), then
@@ -284,7 +286,11 @@ sw_status sw_batch_view(const sw_batch *batch, int32_t i, sw_state *view, sw_lay
 /* Async: materialise every grid's halo of the current buffer. */
 sw_status sw_batch_fill_halo(sw_batch *batch, void *stream);
 /* Async: advance every grid by nsteps (>= 0); the current buffer flips
- * when nsteps is odd.  Errors (synchronous): SW_EINVAL, SW_EHIP. */
+ * when nsteps is odd.  A batch of 8 M cells or more per step advances as
+ * two chains of grids, the second on a stream the batch owns (default
+ * priority), forked from `stream` after the call's first launches and joined
+ * back into it at the end: work enqueued on `stream` afterwards sees the
+ * whole call, as with one chain.  Errors (synchronous): SW_EINVAL, SW_EHIP. */
 sw_status sw_batch_step(sw_batch *batch, int32_t nsteps, void *stream);
 /* Synchronise, then per grid (arrays of n entries, each may be NULL): time,
  * steps and the sticky flag.  Returns SW_EUNSTABLE if any grid is flagged. */
