@@ -58,6 +58,39 @@ def test_batch_equals_each_grid_alone(dtype, bc, graph, scheme):
         assert n_b[i] == n_s == 11 and t_b[i] == t_s
 
 
+# Batches of 8 M cells or more per step advance as two chains of grids on
+# two streams; every grid must still equal the same grid advanced alone.
+SPLIT_SHAPES = {
+    "widths_multiple_of_4": [(2048, 2048), (1024, 2048), (2048, 1024), (1500, 1300), (64, 64), (256, 8)],
+    "ragged": [(2048, 2048), (1023, 2049), (2049, 1024), (1500, 1300), (1, 1), (300, 17), (17, 300)],
+}
+
+
+@pytest.mark.parametrize("shapes", sorted(SPLIT_SHAPES))
+@pytest.mark.parametrize("bc", [sw.REFLECT, sw.PERIODIC])
+@pytest.mark.parametrize("graph", [True, False])
+def test_split_batch_equals_each_grid_alone(shapes, bc, graph):
+    shp = SPLIT_SHAPES[shapes]
+    assert sum(nx * ny for nx, ny in shp) >= 1 << 23
+    tun = dict(variant=2, rows=8, vec=4, occupancy=0, prefetch=1, order=0)
+    sts = states(shp, 700, bc == sw.PERIODIC)
+    announce(f"split batch {shapes} bc{bc} graph{graph}")
+    b = make_batch(shp, sts, "f32", bc, tun, graph)
+    b.step(7)
+    b.step(4)
+    t_b, n_b, _ = b.sync_status()
+    for i, (nx, ny) in enumerate(shp):
+        s = sw.Solver(nx, ny, dtype="f32", bc_x=bc, bc_y=bc)
+        s.set_tuning(**tun)
+        s.set_state(*sts[i])
+        s.step(7)
+        s.step(4)
+        t_s, _, n_s = s.sync_status()
+        for x, y in zip(b.get_state(i, halo=True), s.get_state(halo=True)):
+            assert np.array_equal(x.numpy(), y.numpy()), (i, nx, ny)
+        assert n_b[i] == n_s == 11 and t_b[i] == t_s
+
+
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
 @pytest.mark.parametrize("scheme", [sw.SCHEME_PAPER, sw.SCHEME_TRANSVERSE])
 def test_batch_matches_oracle(dtype, tol, scheme):
