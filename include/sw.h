@@ -261,7 +261,7 @@ sw_status sw_autotune(sw_ctx *ctx, sw_state *state, int32_t steps_per_trial, con
  * batch is bitwise identical to the same grid advanced alone with the same
  * launch shape.  One kernel launch per time step covers every grid (a tile
  * table over all grids; two launches per step, one per chain of grids, for
- * batches of 8 M cells or more); sw_batch_step replays the whole call as
+ * batches of 4 M cells or more); sw_batch_step replays the whole call as
  * hipGraph launches (captured on first use per (nsteps, buffer, tuning)).
  * The caller owns the arena (device memory); the library owns the tile
  * table, per-grid scalars, graphs, a capture stream and the second chain's
@@ -286,7 +286,7 @@ sw_status sw_batch_view(const sw_batch *batch, int32_t i, sw_state *view, sw_lay
 /* Async: materialise every grid's halo of the current buffer. */
 sw_status sw_batch_fill_halo(sw_batch *batch, void *stream);
 /* Async: advance every grid by nsteps (>= 0); the current buffer flips
- * when nsteps is odd.  A batch of 8 M cells or more per step advances as
+ * when nsteps is odd.  A batch of 4 M cells or more per step advances as
  * two chains of grids, the second on a stream the batch owns (default
  * priority), forked from `stream` after the call's first launches and joined
  * back into it at the end: work enqueued on `stream` afterwards sees the
